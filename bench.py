@@ -1,0 +1,158 @@
+"""Benchmark: dense affinity propagation at N=20000 on one MI355X.
+
+A step is one pass of the dense-AP hot path over the resident 64-D Gaussian
+mixture (N=20000, 50 components): similarity build on FP32 matrix cores,
+median preference with tie-break noise, AP (damping 0.9, stop after 15
+unchanged exemplar sets, at most 2000 iterations) and the final labels and
+net similarity.  Inputs are generated once and are resident in HBM before
+the timed region starts.
+
+Prints one JSON line (see the fields below).  `value` is the algorithmic
+message traffic of the AP iterations (20 bytes per matrix element and
+iteration: read S, R, A and write A, R) divided by the whole step time, so
+similarity, preference and finalize time count against it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N, D, K_MIX, SEED = 20000, 64, 50, 2001
+LAMBDA, MAX_ITER, CONV_ITER = 0.9, 2000, 15
+BYTES_PER_ELEM_ITER = 20          # read S, R, A; write A, R (FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    return ap.parse_args()
+
+
+def cpu_baseline(pts, n_iter: int) -> dict:
+    """The FP64 oracle on the host: n_iter AP iterations on the same matrix."""
+    import oracle
+    S = oracle.prepare(oracle.similarity(pts.X), "median", seed=SEED).S
+    oracle.ap(S, LAMBDA, 1, 0)                      # touch pages once
+    t0 = time.perf_counter()
+    oracle.ap(S, LAMBDA, n_iter, 0, finalize_labels=False)
+    dt = time.perf_counter() - t0
+    n = S.shape[0]
+    it_s = n_iter / dt
+    return {"value": round(it_s * BYTES_PER_ELEM_ITER * n * n / 1e9, 3), "unit": "GB/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "iter_per_s": round(it_s, 4),
+            "sample": f"{n_iter} FP64 oracle iterations of dense AP on the same N={n} matrix "
+                      f"(similarity/preference setup untimed); GB/s counts the same "
+                      f"{BYTES_PER_ELEM_ITER} B per element and iteration as the GPU figure"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_0910_1650_amd as apx
+    import synth
+
+    n = args.n
+    torch.cuda.set_device(0)
+    pts = synth.gaussian_mixture(n=n, d=D, k=K_MIX, seed=SEED)
+    X = torch.from_numpy(pts.X).cuda()
+    S = apx.empty_matrix(n)
+    R = apx.empty_matrix(n)
+    A = apx.empty_matrix(n)
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def step():
+        apx.ap_similarity(X, S, pref="median", noise_seed=SEED, noise_rel=1e-12)
+        return apx.ap_solve(S, R, A, LAMBDA, MAX_ITER, CONV_ITER, idx=idx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    apx.apx_profile(True)
+    apx.apx_profile_read()
+    iters = 0
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        _, res = step()
+        iters += res.iterations
+        results.append(res)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, pass_ms = apx.apx_profile_read()
+    apx.apx_profile(False)
+    print(f"timed {args.steps} steps in {dt:.3f}s", file=sys.stderr, flush=True)
+
+    # similarity build on its own (events on the current stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    apx.ap_similarity(X, S, pref="median", noise_seed=SEED, noise_rel=1e-12)
+    e1.record()
+    torch.cuda.synchronize()
+    sim_ms = e0.elapsed_time(e1)
+
+    elems = n * n
+    ms_step = dt * 1e3 / args.steps
+    gbs = iters * BYTES_PER_ELEM_ITER * elems / dt / 1e9
+    avg_pass_ms = pass_ms / max(launches, 1)
+    achieved = BYTES_PER_ELEM_ITER * elems / (avg_pass_ms * 1e-3) / 1e9
+    r0 = results[-1]
+    out = {
+        "metric": "dense AP GB/s & iter/s at N=20k; time to oracle exemplars, plain vs warm-start",
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dense AP, {n} points in {D}-D from a {K_MIX}-component Gaussian "
+                               f"mixture; MFMA similarity, median preference, damping {LAMBDA}, "
+                               f"stop after {CONV_ITER} unchanged exemplar sets",
+                   "n": n, "d": D, "damping": LAMBDA, "max_iter": MAX_ITER, "conv_iter": CONV_ITER},
+        "iter_per_s": round(iters / dt, 2),
+        "iterations_per_step": r0.iterations,
+        "converged": r0.converged,
+        "n_exemplars": r0.n_exemplars,
+        "netsim": r0.netsim,
+        "similarity_ms": round(sim_ms, 3),
+        "roofline": {"bound": "hbm", "kernel": "k_row_pass (full iteration pass)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": launches, "avg_launch_ms": round(avg_pass_ms, 4),
+                     "bytes_per_launch": BYTES_PER_ELEM_ITER * elems},
+    }
+    if not args.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(pts, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * apx.h -- C ABI of the MI355X (gfx950) dense affinity-propagation library.
+ *
+ * Method: Xia, Wu, Zhang, Zhuang, "Local and global approaches of affinity
+ * propagation clustering for large scale data".
+ *   Section 2, Algorithm 1  affinity propagation (Eqs. (1)-(4), damping,
+ *                           exemplar decision, stop rules)
+ *   Section 3, Algorithm 2  partition affinity propagation (PAP)
+ *   Section 4, Algorithm 3  landmark affinity propagation (LAP), Steps 1-2
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Matrices (S, R, A) are DEVICE pointers to FP32, row-major, n rows with
+ *   leading dimension ld (elements): ld >= n, ld % 4 == 0, base address
+ *   16-byte aligned.  Padding columns [n, ld) are never read as data and
+ *   never written.
+ * - Point sets X are DEVICE pointers to FP32, row-major n x d, leading
+ *   dimension ldx >= d.
+ * - Label / decision vectors are DEVICE int32 arrays of length n, 0-based.
+ *   A label of -1 means "no exemplar" (only when the exemplar set is empty).
+ * - Host-side arrays (partition permutations, offsets, results) are marked
+ *   "host".  The caller owns every buffer it passes; the library owns only
+ *   its internal workspace (allocated per context on first need, grown on
+ *   demand, released by apx_destroy).
+ * - Every call returns an apx_status and never aborts.  Arguments are
+ *   validated before any write, so APX_EINVAL leaves all outputs untouched.
+ *   apx_last_error() returns a text for the last failure on the context.
+ * - Work is enqueued on the context's HIP stream.  ap_similarity and
+ *   ap_iterate are asynchronous (stream-ordered); the *_solve calls
+ *   synchronise the stream before filling their host result structs.
+ * - One context per host thread; contexts share no mutable state.
+ */
+#ifndef APX_H
+#define APX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APX_OK = 0,
+    APX_EINVAL = 1,    /* invalid argument (shape, alignment, range, null) */
+    APX_ENOMEM = 2,    /* device workspace could not be allocated */
+    APX_EDEVICE = 3,   /* HIP runtime error; text via apx_last_error */
+    APX_ENOTIMPL = 4   /* size or mode outside what this build supports */
+} apx_status;
+
+/* Preference modes for ap_similarity (Section 2: the diagonal s(k,k)). */
+enum {
+    APX_PREF_MEDIAN = 0, /* median of the n(n-1) off-diagonal similarities */
+    APX_PREF_SCALAR = 1, /* one value for every point */
+    APX_PREF_VECTOR = 2  /* per-point device vector of n floats */
+};
+
+/* Warm-start modes for ap_solve. */
+enum {
+    APX_COLD = 0,     /* A_0 = 0 (Eq. (1)) and R_0 = 0; A, R are outputs only */
+    APX_WARM_A = 1,   /* A holds A_0 on entry (e.g. PAP's A'); R_0 = 0 */
+    APX_WARM_AR = 2   /* A and R hold A_0 and R_0 on entry */
+};
+
+typedef struct apx_ctx apx_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+apx_status apx_create(apx_ctx **out, int device, void *hip_stream);
+void apx_destroy(apx_ctx *ctx);
+apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream);
+const char *apx_last_error(const apx_ctx *ctx);
+/* Bytes of device workspace currently held by the context. */
+size_t apx_workspace_bytes(const apx_ctx *ctx);
+
+/* Kernel timing for benchmarks: while enabled, ap_solve brackets every full
+ * row pass (the dominant kernel) with HIP events on the context stream and
+ * accumulates the launch count and total duration of the passes that did
+ * work.  apx_profile_read returns and clears the totals.  Timing never
+ * changes results. */
+apx_status apx_profile(apx_ctx *ctx, int enable);
+apx_status apx_profile_read(apx_ctx *ctx, int64_t *launches, double *total_ms);
+
+typedef struct {
+    float damping;       /* lambda in [0,1): new = lambda*old + (1-lambda)*update (Section 2) */
+    int32_t max_iter;    /* >= 1: iteration cap (Section 2, Step 4) */
+    int32_t conv_iter;   /* >= 0: stop once the exemplar set has been the same, and
+                            non-empty, for conv_iter consecutive iterations;
+                            0 = run exactly max_iter iterations */
+    int32_t check_every; /* iterations between host polls of the stop flag
+                            (0 = library default); never changes results */
+} apx_params;
+
+typedef struct {
+    int32_t iterations;  /* iterations run (the stop iteration) */
+    int32_t converged;   /* 1 if the exemplar-set rule stopped the run */
+    int32_t n_exemplars; /* |E| */
+    int32_t status;      /* apx_status of this instance */
+    double dpsim;        /* sum of s(i, idx(i)) over non-exemplars (Algorithm 1 output) */
+    double expref;       /* sum of s(k,k) over exemplars */
+    double netsim;       /* dpsim + expref (= -E(c), Section 2) */
+} apx_result;
+
+/*
+ * ap_similarity -- S from points (Section 2): s(i,k) = -||x_i - x_k||^2,
+ * computed as 2<x_i,x_k> - (||x_i||^2 + ||x_k||^2) with FP32 matrix cores and
+ * mirrored so that S is exactly symmetric before noise.  Then the diagonal
+ * is set to the preferences (pref_mode; pref_vec is a device vector used by
+ * APX_PREF_VECTOR, pref_scalar by APX_PREF_SCALAR), and, if noise_rel > 0,
+ * every entry gets noise_rel * (max S - min S) * u(noise_seed, i, k), where
+ * u is the SplitMix64 output function of the counter i*n+k+1 (top 53 bits
+ * scaled to [0,1)) and the range is taken over S with the preferences set.
+ * pref_out (host, nullable) receives the preference used (median or scalar).
+ * Requires n >= 2, 1 <= d.
+ */
+apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
+                         float *S, int64_t ld, int32_t pref_mode, const float *pref_vec,
+                         float pref_scalar, uint64_t noise_seed, double noise_rel,
+                         double *pref_out);
+
+/*
+ * ap_iterate -- n_iter damped iterations of Algorithm 1 (Eqs. (2), (3), (4)).
+ * On entry R, A hold the messages after some iteration t (zeros for a cold
+ * start); on exit they hold those after iteration t + n_iter.  Each
+ * iteration first updates and damps R from (S, A), then A from the new R.
+ * decision (device, nullable) receives argmax_k a(i,k)+r(i,k) after the last
+ * iteration (lowest k on ties).  Calls compose: n1 then n2 iterations give
+ * bit-identical messages to n1 + n2 in one call.  Requires n >= 2,
+ * n_iter >= 1.  Asynchronous.
+ */
+apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                      float damping, int32_t n_iter, int32_t *decision);
+
+/*
+ * ap_solve -- Algorithm 1 to its stop rule.  S holds the similarities with
+ * the preferences on the diagonal.  warm selects the start (APX_COLD,
+ * APX_WARM_A, APX_WARM_AR).  On exit R and A hold the messages of the stop
+ * iteration, idx (device, n) the labels: exemplars E = {k : argmax_j
+ * a(k,j)+r(k,j) = k} label themselves and every other point takes the
+ * exemplar of largest s(i,k) (lowest k on ties).  res (host) gets the
+ * iteration count, convergence flag, |E| and dpsim/expref/netsim in FP64.
+ * n = 1 returns idx = [0] and netsim = s(0,0) without iterating.
+ * Non-convergence is not an error (converged = 0).  Synchronises the stream.
+ */
+apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                    int32_t warm, const apx_params *params, int32_t *idx, apx_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APX_H */

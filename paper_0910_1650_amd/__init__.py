@@ -1,0 +1,228 @@
+"""Python binding of libapx (MI355X dense affinity propagation).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libapx.so``; PyTorch supplies device memory and the stream.
+The function names match the C ABI in ``include/apx.h``.
+
+Matrices are 2-D float32 CUDA tensors of shape (n, n) with unit column
+stride; their row stride is the leading dimension ``ld`` (a multiple of 4).
+``empty_matrix`` allocates such a view with rows padded to 64 elements.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapx.so")
+
+APX_OK, APX_EINVAL, APX_ENOMEM, APX_EDEVICE, APX_ENOTIMPL = range(5)
+APX_PREF_MEDIAN, APX_PREF_SCALAR, APX_PREF_VECTOR = range(3)
+APX_COLD, APX_WARM_A, APX_WARM_AR = range(3)
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTIMPL"}
+
+
+class ApxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"apx {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class apx_params(ctypes.Structure):
+    _fields_ = [("damping", ctypes.c_float), ("max_iter", ctypes.c_int32),
+                ("conv_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class apx_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_exemplars", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("dpsim", ctypes.c_double), ("expref", ctypes.c_double),
+                ("netsim", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+# name -> (restype, argtypes); every symbol include/apx.h declares
+SIGNATURES = {
+    "apx_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "apx_destroy": (None, [_P]),
+    "apx_set_stream": (ctypes.c_int, [_P, _P]),
+    "apx_last_error": (ctypes.c_char_p, [_P]),
+    "apx_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
+    "ap_similarity": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _I32, _P, ctypes.c_float,
+                                     ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "ap_iterate": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, ctypes.c_float, _I32, _P]),
+    "ap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, ctypes.POINTER(apx_params), _P,
+                                ctypes.POINTER(apx_result)]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libapx.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0910_1650_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+_ctxs: dict[int, ctypes.c_void_p] = {}
+
+
+def context(device: torch.device | int | None = None) -> ctypes.c_void_p:
+    """The library context of a device, bound to torch's current stream."""
+    if device is None:
+        device = torch.cuda.current_device()
+    dev = torch.device("cuda", device) if isinstance(device, int) else device
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    L = lib()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    if idx not in _ctxs:
+        h = _P()
+        st = L.apx_create(ctypes.byref(h), idx, _P(stream))
+        if st != APX_OK:
+            raise ApxError(st, f"apx_create on device {idx}")
+        _ctxs[idx] = h
+    else:
+        L.apx_set_stream(_ctxs[idx], _P(stream))
+    return _ctxs[idx]
+
+
+def _check(ctx, st: int, what: str):
+    if st != APX_OK:
+        raise ApxError(st, f"{what}: {lib().apx_last_error(ctx).decode()}")
+
+
+def round_ld(n: int, align: int = 64) -> int:
+    return max(align, (n + align - 1) // align * align)
+
+
+def empty_matrix(n: int, device="cuda", fill: float | None = None) -> torch.Tensor:
+    """(n, n) float32 view whose rows are padded to a multiple of 64 elements."""
+    ld = round_ld(n)
+    base = torch.empty((max(n, 1), ld), dtype=torch.float32, device=device)
+    if fill is not None:
+        base.fill_(fill)
+    return base[:n, :n]
+
+
+def to_matrix(M: torch.Tensor) -> torch.Tensor:
+    """Copy a dense (n, n) tensor into a padded device matrix."""
+    n = M.shape[0]
+    out = empty_matrix(n, device="cuda")
+    out.copy_(M.to(device="cuda", dtype=torch.float32))
+    return out
+
+
+def _mat(M: torch.Tensor, name: str, n: int | None = None):
+    if not (M.is_cuda and M.dtype == torch.float32 and M.dim() == 2):
+        raise ValueError(f"{name} must be a 2-D float32 CUDA tensor")
+    if M.shape[0] != M.shape[1] or M.stride(1) != 1:
+        raise ValueError(f"{name} must be square with unit column stride")
+    if n is not None and M.shape[0] != n:
+        raise ValueError(f"{name} has {M.shape[0]} rows, expected {n}")
+    return _P(M.data_ptr()), M.shape[0], M.stride(0)
+
+
+@dataclass
+class Result:
+    iterations: int
+    converged: bool
+    n_exemplars: int
+    dpsim: float
+    expref: float
+    netsim: float
+
+
+def _res(r: apx_result) -> Result:
+    return Result(r.iterations, bool(r.converged), r.n_exemplars, r.dpsim, r.expref, r.netsim)
+
+
+def ap_similarity(X: torch.Tensor, S: torch.Tensor | None = None, pref: str | float | torch.Tensor = "median",
+                  noise_seed: int = 0, noise_rel: float = 1e-12):
+    """S (padded (n,n) view) from points X (n,d) float32; returns (S, preference)."""
+    if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
+        raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
+    n, d = X.shape
+    if S is None:
+        S = empty_matrix(n, device=X.device)
+    Sp, _, ld = _mat(S, "S", n)
+    ctx = context(X.device)
+    if isinstance(pref, str):
+        mode, vec, scal = APX_PREF_MEDIAN, None, 0.0
+    elif isinstance(pref, torch.Tensor):
+        mode, vec, scal = APX_PREF_VECTOR, pref.contiguous(), 0.0
+    else:
+        mode, vec, scal = APX_PREF_SCALAR, None, float(pref)
+    out = ctypes.c_double(float("nan"))
+    st = lib().ap_similarity(ctx, _P(X.data_ptr()), n, d, X.stride(0), Sp, ld, mode,
+                             _P(vec.data_ptr()) if vec is not None else None, scal,
+                             noise_seed, noise_rel, ctypes.byref(out))
+    _check(ctx, st, "ap_similarity")
+    return S, out.value
+
+
+def ap_iterate(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float, n_iter: int,
+               decision: torch.Tensor | None = None) -> None:
+    """n_iter damped AP iterations on (R, A) in place (asynchronous)."""
+    Sp, n, ld = _mat(S, "S")
+    Rp, _, ldr = _mat(R, "R", n)
+    Ap, _, lda = _mat(A, "A", n)
+    if not (ld == ldr == lda):
+        raise ValueError("S, R and A must share one leading dimension")
+    dp = None
+    if decision is not None:
+        if not (decision.is_cuda and decision.dtype == torch.int32 and decision.numel() == n):
+            raise ValueError("decision must be an int32 CUDA tensor of n entries")
+        dp = _P(decision.data_ptr())
+    ctx = context(S.device)
+    _check(ctx, lib().ap_iterate(ctx, Sp, n, ld, Rp, Ap, damping, n_iter, dp), "ap_iterate")
+
+
+def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float = 0.5,
+             max_iter: int = 200, conv_iter: int = 15, warm: int = APX_COLD,
+             idx: torch.Tensor | None = None, check_every: int = 0):
+    """Algorithm 1 to its stop rule; returns (idx int32 tensor, Result)."""
+    Sp, n, ld = _mat(S, "S")
+    Rp, _, ldr = _mat(R, "R", n)
+    Ap, _, lda = _mat(A, "A", n)
+    if not (ld == ldr == lda):
+        raise ValueError("S, R and A must share one leading dimension")
+    if idx is None:
+        idx = torch.empty(n, dtype=torch.int32, device=S.device)
+    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    res = apx_result()
+    ctx = context(S.device)
+    _check(ctx, lib().ap_solve(ctx, Sp, n, ld, Rp, Ap, warm, ctypes.byref(prm), _P(idx.data_ptr()),
+                               ctypes.byref(res)), "ap_solve")
+    return idx, _res(res)
+
+
+def apx_profile(enable: bool, device=None) -> None:
+    """Enable/disable event timing of the full row passes inside ap_solve."""
+    ctx = context(device)
+    _check(ctx, lib().apx_profile(ctx, int(bool(enable))), "apx_profile")
+
+
+def apx_profile_read(device=None) -> tuple[int, float]:
+    """(launches, total milliseconds) of timed row passes since the last read."""
+    ctx = context(device)
+    n, ms = _I64(0), ctypes.c_double(0.0)
+    _check(ctx, lib().apx_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms)), "apx_profile_read")
+    return int(n.value), float(ms.value)

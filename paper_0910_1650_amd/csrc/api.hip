@@ -1,0 +1,386 @@
+// api.hip -- C ABI entry points: context, validation, workspace, and the
+// host side of the AP iteration loop (Algorithm 1, Section 2).
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "apx_internal.h"
+
+using namespace apx;
+
+namespace apx {
+
+apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return APX_OK;
+    if (e == hipErrorOutOfMemory)
+        return set_err(ctx, APX_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return set_err(ctx, APX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+apx_status ws_reserve(apx_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return APX_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_err(ctx, e, "workspace sync");
+    if (ctx->ws) {
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t want = bytes + (bytes >> 3);   // grow with slack
+    e = hipMalloc(&ctx->ws, want);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        return set_err(ctx, APX_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+    }
+    ctx->ws_bytes = want;
+    return APX_OK;
+}
+
+}  // namespace apx
+
+#define APX_TRY(expr)                       \
+    do {                                    \
+        apx_status _st = (expr);            \
+        if (_st != APX_OK) return _st;      \
+    } while (0)
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_err(ctx, _e, what);  \
+    } while (0)
+
+namespace {
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+apx_status check_matrix(apx_ctx *ctx, const void *M, const char *name, int64_t n, int64_t ld) {
+    if (M == nullptr) return set_err(ctx, APX_EINVAL, "%s is null", name);
+    if (!aligned16(M)) return set_err(ctx, APX_EINVAL, "%s is not 16-byte aligned", name);
+    if (ld < n) return set_err(ctx, APX_EINVAL, "ld (%lld) < n (%lld)", (long long)ld, (long long)n);
+    if (ld % 4 != 0) return set_err(ctx, APX_EINVAL, "ld (%lld) is not a multiple of 4", (long long)ld);
+    return APX_OK;
+}
+
+int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
+
+// Workspace of one AP run on an n x n problem.
+struct IterWs {
+    float *tcol, *ccol, *rdiag, *partial;
+    int64_t ldp;
+    int nparts;
+    int32_t *dec;
+    uint8_t *eflag;
+    ApState *st;
+    float *R2;            // second responsibility buffer (ap_solve)
+    int32_t *ex, *nex;
+    double *contrib, *sums;
+};
+
+apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const PassPlan &pl, IterWs &w) {
+    WsLayout L;
+    const int64_t ldp = round4(n);
+    size_t o_t = L.take(sizeof(float) * ldp);
+    size_t o_c = L.take(sizeof(float) * ldp);
+    size_t o_d = L.take(sizeof(float) * ldp);
+    size_t o_p = L.take(sizeof(float) * ldp * (size_t)pl.grid);
+    size_t o_dec = L.take(sizeof(int32_t) * n);
+    size_t o_e = L.take((size_t)n);
+    size_t o_st = L.take(sizeof(ApState));
+    size_t o_ex = L.take(sizeof(int32_t) * n);
+    size_t o_nex = L.take(sizeof(int32_t));
+    size_t o_con = L.take(sizeof(double) * 2 * (size_t)n);
+    size_t o_sum = L.take(sizeof(double) * 2);
+    size_t o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
+    APX_TRY(ws_reserve(ctx, L.off));
+    char *b = static_cast<char *>(ctx->ws);
+    w.tcol = reinterpret_cast<float *>(b + o_t);
+    w.ccol = reinterpret_cast<float *>(b + o_c);
+    w.rdiag = reinterpret_cast<float *>(b + o_d);
+    w.partial = reinterpret_cast<float *>(b + o_p);
+    w.ldp = ldp;
+    w.nparts = pl.grid;
+    w.dec = reinterpret_cast<int32_t *>(b + o_dec);
+    w.eflag = reinterpret_cast<uint8_t *>(b + o_e);
+    w.st = reinterpret_cast<ApState *>(b + o_st);
+    w.ex = reinterpret_cast<int32_t *>(b + o_ex);
+    w.nex = reinterpret_cast<int32_t *>(b + o_nex);
+    w.contrib = reinterpret_cast<double *>(b + o_con);
+    w.sums = reinterpret_cast<double *>(b + o_sum);
+    w.R2 = second_r ? reinterpret_cast<float *>(b + o_r2) : nullptr;
+    return APX_OK;
+}
+
+PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int64_t n, int64_t ld,
+                   float lam, const IterWs &w, int load_r, int load_a, int32_t *dec, uint8_t *eflag,
+                   ApState *st) {
+    PassArgs a{};
+    a.S = S;
+    a.Rin = Rin;
+    a.Rout = Rout;
+    a.A = A;
+    a.ld = ld;
+    a.n = (int32_t)n;
+    a.load_r = load_r;
+    a.load_a = load_a;
+    a.lam = lam;
+    a.tcol = w.tcol;
+    a.ccol = w.ccol;
+    a.partial = w.partial;
+    a.ldp = w.ldp;
+    a.rdiag = w.rdiag;
+    a.dec = dec;
+    a.eflag = eflag;
+    a.st = st;
+    a.row_begin = 0;
+    a.row_end = n;
+    return a;
+}
+
+ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep) {
+    ColArgs c{};
+    c.partial = w.partial;
+    c.ldp = w.ldp;
+    c.nparts = w.nparts;
+    c.rdiag = w.rdiag;
+    c.tcol = w.tcol;
+    c.ccol = w.ccol;
+    c.n = (int32_t)n;
+    c.st = st;
+    c.bookkeep = bookkeep;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
+    if (out == nullptr) return APX_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return APX_EDEVICE;
+    apx_ctx *ctx = new (std::nothrow) apx_ctx();
+    if (!ctx) return APX_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    DevGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return APX_ENOMEM;
+    }
+    *out = ctx;
+    return APX_OK;
+}
+
+void apx_destroy(apx_ctx *ctx) {
+    if (!ctx) return;
+    DevGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream) {
+    if (!ctx) return APX_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return APX_OK;
+}
+
+const char *apx_last_error(const apx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t apx_workspace_bytes(const apx_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+apx_status apx_profile(apx_ctx *ctx, int enable) {
+    if (!ctx) return APX_EINVAL;
+    ctx->prof = enable != 0;
+    return APX_OK;
+}
+
+apx_status apx_profile_read(apx_ctx *ctx, int64_t *launches, double *total_ms) {
+    if (!ctx || !launches || !total_ms) return APX_EINVAL;
+    *launches = ctx->prof_launches;
+    *total_ms = ctx->prof_ms;
+    ctx->prof_launches = 0;
+    ctx->prof_ms = 0.0;
+    return APX_OK;
+}
+
+apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                      float damping, int32_t n_iter, int32_t *decision) {
+    if (!ctx) return APX_EINVAL;
+    if (n < 2) return set_err(ctx, APX_EINVAL, "ap_iterate needs n >= 2 (n = %lld)", (long long)n);
+    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
+    APX_TRY(check_matrix(ctx, S, "S", n, ld));
+    APX_TRY(check_matrix(ctx, R, "R", n, ld));
+    APX_TRY(check_matrix(ctx, A, "A", n, ld));
+    if (!(damping >= 0.0f && damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
+    if (n_iter < 1) return set_err(ctx, APX_EINVAL, "n_iter must be >= 1");
+    DevGuard g(ctx->device);
+    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    IterWs w{};
+    APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
+    hipStream_t s = ctx->stream;
+    // R_{t+1} from (R_t, S, A_t), in place, with its column vectors.
+    PassArgs pa = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, nullptr, nullptr, nullptr);
+    HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pa, s), "row pass (R)");
+    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
+    for (int32_t it = 1; it < n_iter; ++it) {
+        PassArgs pf = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, nullptr, nullptr, nullptr);
+        HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
+        HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
+    }
+    PassArgs pe = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, decision, nullptr, nullptr);
+    HIP_TRY(launch_row_pass(pl, PASS_A_ONLY, pe, s), "row pass (A)");
+    return APX_OK;
+}
+
+apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                    int32_t warm, const apx_params *params, int32_t *idx, apx_result *res) {
+    if (!ctx) return APX_EINVAL;
+    if (n < 1) return set_err(ctx, APX_EINVAL, "n must be >= 1");
+    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
+    APX_TRY(check_matrix(ctx, S, "S", n, ld));
+    APX_TRY(check_matrix(ctx, R, "R", n, ld));
+    APX_TRY(check_matrix(ctx, A, "A", n, ld));
+    if (!params || !res || !idx) return set_err(ctx, APX_EINVAL, "params, idx and res must be non-null");
+    if (warm < APX_COLD || warm > APX_WARM_AR) return set_err(ctx, APX_EINVAL, "bad warm mode %d", warm);
+    const float lam = params->damping;
+    if (!(lam >= 0.0f && lam < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
+    if (params->max_iter < 1 || params->conv_iter < 0)
+        return set_err(ctx, APX_EINVAL, "max_iter must be >= 1 and conv_iter >= 0");
+    DevGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    std::memset(res, 0, sizeof *res);
+
+    if (n == 1) {
+        // A single point is its own exemplar; Eq. (2) has no other candidate.
+        float s00 = 0.0f;
+        int32_t *h = static_cast<int32_t *>(ctx->pinned);
+        h[0] = 0;
+        HIP_TRY(hipMemcpyAsync(idx, h, sizeof(int32_t), hipMemcpyHostToDevice, s), "idx");
+        HIP_TRY(hipMemcpyAsync(&h[4], S, sizeof(float), hipMemcpyDeviceToHost, s), "s00");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        std::memcpy(&s00, &h[4], sizeof s00);
+        res->iterations = 0;
+        res->converged = 1;
+        res->n_exemplars = 1;
+        res->dpsim = 0.0;
+        res->expref = s00;
+        res->netsim = s00;
+        return APX_OK;
+    }
+
+    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    IterWs w{};
+    APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
+    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, s), "state init");
+    HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
+
+    // R_t lives in buf[t & 1]; buf[0] is the caller's R.
+    float *buf[2] = {R, w.R2};
+    const int load_r0 = (warm == APX_WARM_AR);
+    const int load_a0 = (warm != APX_COLD);
+    PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, load_r0, load_a0, nullptr, nullptr, nullptr);
+    HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
+    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
+
+    const int chunk = params->check_every > 0 ? params->check_every : 16;
+    if (ctx->prof && (int)ctx->prof_ev.size() < 2 * chunk) {
+        while ((int)ctx->prof_ev.size() < 2 * chunk) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e), "event");
+            ctx->prof_ev.push_back(e);
+        }
+    }
+    ApState *hst = static_cast<ApState *>(ctx->pinned);
+    int32_t t = 1;   // next pass computes A_t and R_{t+1}
+    for (;;) {
+        int32_t stop_at = t + chunk;
+        if (stop_at > params->max_iter + 1) stop_at = params->max_iter + 1;
+        const int32_t t_first = t;
+        for (; t < stop_at; ++t) {
+            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, 1,
+                                    (t > 1) || load_a0, w.dec, w.eflag, w.st);
+            const int slot = t - t_first;
+            if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
+            HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
+            if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
+            HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1), s), "column reduce");
+        }
+        HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, s), "state");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (ctx->prof) {
+            // only the passes that did work (iterations <= the stop iteration)
+            for (int32_t u = t_first; u < t && u <= hst->iter; ++u) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_ev[2 * (u - t_first)],
+                                            ctx->prof_ev[2 * (u - t_first) + 1]), "elapsed");
+                ctx->prof_ms += ms;
+                ctx->prof_launches += 1;
+            }
+        }
+        if (hst->frozen || t > params->max_iter) break;
+    }
+    const int32_t T = hst->iter;
+    res->iterations = T;
+    res->converged = hst->converged;
+    if (T & 1) HIP_TRY(launch_copy_rows(R, w.R2, n, n, ld, s), "copy R");
+
+    FinalArgs fa{};
+    fa.S = S;
+    fa.ld = ld;
+    fa.n = (int32_t)n;
+    fa.eflag = w.eflag;
+    fa.ex = w.ex;
+    fa.nex = w.nex;
+    fa.idx = idx;
+    fa.contrib = w.contrib;
+    fa.sums = w.sums;
+    HIP_TRY(launch_finalize(fa, s), "finalize");
+    double *hd = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 256);
+    int32_t *hn = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 512);
+    HIP_TRY(hipMemcpyAsync(hd, w.sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "sums");
+    HIP_TRY(hipMemcpyAsync(hn, w.nex, sizeof(int32_t), hipMemcpyDeviceToHost, s), "nex");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    res->n_exemplars = *hn;
+    if (*hn == 0) {
+        res->dpsim = res->expref = res->netsim = NAN;
+    } else {
+        res->dpsim = hd[0];
+        res->expref = hd[1];
+        res->netsim = hd[0] + hd[1];
+    }
+    res->status = APX_OK;
+    return APX_OK;
+}
+
+}  // extern "C"

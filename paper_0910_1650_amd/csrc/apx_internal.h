@@ -1,0 +1,134 @@
+// apx_internal.h -- shared declarations of the HIP library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/apx.h"
+
+namespace apx {
+
+// Device-side run state of one AP instance (one solve).  Updated by the
+// column-reduce kernel after every full row pass; read by the host every few
+// iterations.  All counters are integers, so their atomics are deterministic.
+struct ApState {
+    int32_t iter;       // completed iterations t (A_t computed)
+    int32_t run;        // consecutive iterations with an unchanged exemplar set
+    int32_t frozen;     // 1 once the stop rule fired: later passes are no-ops
+    int32_t converged;  // 1 if the exemplar-set rule fired
+    int32_t nex;        // |E_t| accumulated by the running pass
+    int32_t changed;    // E_t != E_{t-1}, accumulated by the running pass
+    int32_t max_iter;
+    int32_t conv_iter;
+    int32_t last_nex;   // |E| of the last completed iteration
+    int32_t pad[7];
+};
+
+// Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
+// column vectors of R_t; it writes A_t, the decisions d_t and R_{t+1} with
+// the column partials of max(0, R_{t+1}).
+enum PassMode : int { PASS_FULL = 0, PASS_R_ONLY = 1, PASS_A_ONLY = 2 };
+
+struct PassArgs {
+    const float *S;
+    const float *Rin;   // R_t (may alias Rout: each element is read before it is written)
+    float *Rout;        // R_{t+1}
+    float *A;           // A_{t-1} in, A_t out (in place)
+    int64_t ld;
+    int32_t n;
+    int32_t load_r;     // 0: R_t is taken as zero (cold prologue)
+    int32_t load_a;     // 0: the incoming A is taken as zero
+    float lam;
+    const float *tcol;  // t_k = r(k,k) + c_k of R_t
+    const float *ccol;  // c_k = sum_{i != k} max(0, r(i,k)) of R_t
+    float *partial;     // [gridDim.x][ldp] column partials of max(0, R_{t+1})
+    int64_t ldp;
+    float *rdiag;       // r_{t+1}(k,k)
+    int32_t *dec;       // decisions d_t (nullable)
+    uint8_t *eflag;     // exemplar flags of the previous iteration (nullable)
+    ApState *st;        // nullable: no stop-rule bookkeeping
+    int64_t row_begin;  // rows handled by this launch: [row_begin, row_end)
+    int64_t row_end;
+};
+
+struct ColArgs {
+    const float *partial;
+    int64_t ldp;
+    int32_t nparts;
+    const float *rdiag;
+    float *tcol;
+    float *ccol;
+    int32_t n;
+    ApState *st;        // nullable
+    int32_t bookkeep;   // 1: apply the stop rule for the pass just finished
+};
+
+// Launch helpers (ap_iter.hip).
+struct PassPlan {
+    int threads;   // workgroup size
+    int chunks;    // float4 chunks per thread per row
+    int grid;      // workgroups
+};
+PassPlan plan_pass(int64_t n, int num_cus);
+hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);
+hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s);
+hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_fill_f32_rows(float *p, int64_t rows, int64_t cols, int64_t ld, float v,
+                                hipStream_t s);
+hipError_t launch_copy_rows(float *dst, const float *src, int64_t rows, int64_t cols, int64_t ld,
+                            hipStream_t s);
+
+// Finalize: labels and FP64 dpsim / expref.
+struct FinalArgs {
+    const float *S;
+    int64_t ld;
+    int32_t n;
+    const uint8_t *eflag;
+    int32_t *ex;        // exemplar list scratch (n)
+    int32_t *nex;       // device count
+    int32_t *idx;       // labels out
+    double *contrib;    // 2n scratch
+    double *sums;       // [dpsim, expref]
+};
+hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+
+}  // namespace apx
+
+// Context ------------------------------------------------------------------
+struct apx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 256;
+    std::string err;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *pinned = nullptr;   // small pinned host buffer for state read-back
+    // benchmark timing of full row passes (apx_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+};
+
+namespace apx {
+
+// Bump allocator over the context workspace (256-byte aligned slices).
+struct WsLayout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+apx_status ws_reserve(apx_ctx *ctx, size_t bytes);
+apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
+apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what);
+
+}  // namespace apx

@@ -1,0 +1,387 @@
+// similarity.hip -- S from points, preferences and tie-break noise.
+//
+//   s(i,k) = -||x_i - x_k||^2 = 2<x_i,x_k> - (||x_i||^2 + ||x_k||^2)   (Section 2)
+//
+// The Gram part runs on FP32 matrix cores (v_mfma_f32_32x32x2f32, FP32
+// accumulate).  Only tiles on or above the block diagonal are computed; each
+// result is written at (i,k) and mirrored to (k,i), so S is exactly
+// symmetric.  The preference is the median of the n(n-1) off-diagonal
+// entries, found exactly by a three-pass radix select over the upper
+// triangle (which holds every off-diagonal value twice by symmetry).
+#include <cmath>
+
+#include "apx_internal.h"
+
+namespace apx {
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128;      // tile edge
+constexpr int KB = 32;       // K chunk staged in LDS
+constexpr int NT = 256;      // threads per tile (4 wavefronts)
+
+// Ordered 32-bit key of a float: unsigned order equals float order.
+__device__ __forceinline__ uint32_t fkey(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float keyf(uint32_t k) {
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(b);
+}
+
+__global__ void k_sqnorm(const float *X, int64_t n, int64_t d, int64_t ldx, float *nrm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *x = X + i * ldx;
+    float acc = 0.0f;
+    for (int64_t j = 0; j < d; ++j) acc = fmaf(x[j], x[j], acc);
+    nrm[i] = acc;
+}
+
+struct SimArgs {
+    const float *X;
+    int64_t n, d, ldx;
+    const float *nrm;
+    float *S;
+    int64_t ld;
+    int64_t tiles_per_side;
+    uint32_t *minmax;     // [0] = min key, [1] = max key of off-diagonal entries
+};
+
+__global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
+    // Decode the upper-triangle tile (bi <= bj) from the linear block index.
+    const int64_t T = a.tiles_per_side;
+    int64_t t = blockIdx.x, bi = 0;
+    while (t >= T - bi) {
+        t -= T - bi;
+        ++bi;
+    }
+    const int64_t bj = bi + t;
+    const int64_t row0 = bi * BM, col0 = bj * BM;
+
+    __shared__ float smem[BM * (BM + 1)];          // 66 KB: staging, then the C tile
+    constexpr int LDA = BM + 1;                     // padded: conflict-free transposed stores
+    float *As = smem;                               // [KB][LDA]
+    float *Bs = smem + KB * LDA;                    // [KB][LDA]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    v16f acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.0f;
+
+    for (int64_t k0 = 0; k0 < a.d; k0 += KB) {
+        // Stage X[row0 .. +BM, k0 .. +KB] and X[col0 .. +BM, k0 .. +KB], k-major.
+        for (int e = tid; e < BM * KB; e += NT) {
+            const int m = e / KB, kk = e % KB;
+            const int64_t kg = k0 + kk;
+            const int64_t ra = row0 + m, rb = col0 + m;
+            As[kk * LDA + m] = (ra < a.n && kg < a.d) ? a.X[ra * a.ldx + kg] : 0.0f;
+            Bs[kk * LDA + m] = (rb < a.n && kg < a.d) ? a.X[rb * a.ldx + kg] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KB; kk += 2) {
+            const int kr = kk + (lane >> 5);
+            float av[2], bv[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) av[x] = As[kr * LDA + wm * 64 + x * 32 + (lane & 31)];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) bv[y] = Bs[kr * LDA + wn * 64 + y * 32 + (lane & 31)];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // Gram tile to LDS: C[m][c] with a padded stride.
+    constexpr int LDC = BM + 1;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int m = wm * 64 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int c = wn * 64 + y * 32 + (lane & 31);
+                smem[m * LDC + c] = acc[x][y][v];
+            }
+    __syncthreads();
+
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    const bool diag_tile = (bi == bj);
+    // Direct tile: rows row0+m, columns col0+c.  On a diagonal tile the value
+    // at (m,c) is taken from the upper entry min/max(m,c) so it is symmetric.
+    for (int e = tid; e < BM * BM; e += NT) {
+        const int m = e / BM, c = e % BM;
+        const int64_t i = row0 + m, k = col0 + c;
+        if (i >= a.n || k >= a.n || i == k) continue;
+        float g = smem[m * LDC + c];
+        if (diag_tile && m > c) g = smem[c * LDC + m];
+        const float s = 2.0f * g - (a.nrm[i] + a.nrm[k]);
+        a.S[i * a.ld + k] = s;
+        if (!diag_tile || m < c) {
+            const uint32_t key = fkey(s);
+            kmin = min(kmin, key);
+            kmax = max(kmax, key);
+        }
+    }
+    if (!diag_tile) {
+        // Mirror: S[col0+c][row0+m] = s(row0+m, col0+c).
+        for (int e = tid; e < BM * BM; e += NT) {
+            const int c = e / BM, m = e % BM;
+            const int64_t i = row0 + m, k = col0 + c;
+            if (i >= a.n || k >= a.n) continue;
+            const float s = 2.0f * smem[m * LDC + c] - (a.nrm[i] + a.nrm[k]);
+            a.S[k * a.ld + i] = s;
+        }
+    }
+    // Block min/max of the upper off-diagonal entries.
+    for (int off = 32; off >= 1; off >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+    }
+    if (lane == 0) {
+        atomicMin(&a.minmax[0], kmin);
+        atomicMax(&a.minmax[1], kmax);
+    }
+}
+
+// ---- exact order statistics of the upper triangle -------------------------
+// sel[0..1]: state of the two ranks (lo, hi): prefix key bits so far.
+struct SelState {
+    uint32_t prefix[2];
+    uint32_t pad0[2];
+    unsigned long long rank[2];   // remaining rank inside the current prefix
+};
+
+__global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo,
+                           unsigned long long hi, unsigned long long *hist) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->prefix[0] = st->prefix[1] = 0u;
+        st->rank[0] = lo;
+        st->rank[1] = hi;
+        minmax[0] = 0xffffffffu;
+        minmax[1] = 0u;
+    }
+    for (int b = threadIdx.x; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
+}
+
+// Histogram of the keys of upper-triangle entries whose high bits match the
+// current prefix of each rank.  shift/bits select the digit of this pass.
+__global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int64_t ld,
+                                                  const SelState *st, int pass,
+                                                  unsigned long long *hist) {
+    __shared__ uint32_t h[2][2048];
+    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const int bits = pass == 2 ? 10 : 11;
+    const uint32_t nb = 1u << bits;
+    const uint32_t hmask = pass == 0 ? 0u : (pass == 1 ? 0xffe00000u : 0xfffffc00u);
+    for (uint32_t b = threadIdx.x; b < 2 * 2048; b += blockDim.x) (&h[0][0])[b] = 0u;
+    __syncthreads();
+    const uint32_t p0 = st->prefix[0], p1 = st->prefix[1];
+    for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
+        const float *row = S + i * ld;
+        for (int64_t k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
+            const uint32_t key = fkey(row[k]);
+            const uint32_t dig = (key >> shift) & (nb - 1u);
+            if ((key & hmask) == p0) atomicAdd(&h[0][dig], 1u);
+            if ((key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        if (h[0][b]) atomicAdd(&hist[b], (unsigned long long)h[0][b]);
+        if (h[1][b]) atomicAdd(&hist[2048 + b], (unsigned long long)h[1][b]);
+    }
+}
+
+// Pick the digit holding each rank; extend the prefixes; clear the histogram.
+__global__ void k_sel_pick(SelState *st, int pass, unsigned long long *hist) {
+    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const int bits = pass == 2 ? 10 : 11;
+    const uint32_t nb = 1u << bits;
+    if (threadIdx.x < 2) {
+        const int r = threadIdx.x;
+        unsigned long long rank = st->rank[r], cum = 0ull;
+        uint32_t b = 0;
+        for (; b < nb; ++b) {
+            const unsigned long long c = hist[r * 2048 + b];
+            if (rank < cum + c) break;
+            cum += c;
+        }
+        st->rank[r] = rank - cum;
+        st->prefix[r] |= (b << shift);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
+}
+
+struct PrefArgs {
+    float *S;
+    int64_t n, ld;
+    int mode;                 // APX_PREF_*
+    const float *pref_vec;
+    float pref_scalar;
+    const SelState *sel;      // median mode
+    const uint32_t *minmax;
+    uint64_t seed;
+    double noise_rel;
+    double *pref_dev;         // out: the scalar preference (median/scalar)
+};
+
+__device__ __forceinline__ double pref_of(const PrefArgs &a, int64_t i, double pm) {
+    if (a.mode == APX_PREF_VECTOR) return (double)a.pref_vec[i];
+    return pm;
+}
+
+__device__ __forceinline__ double median_of(const PrefArgs &a) {
+    if (a.mode == APX_PREF_MEDIAN)
+        return 0.5 * ((double)keyf(a.sel->prefix[0]) + (double)keyf(a.sel->prefix[1]));
+    return (double)a.pref_scalar;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood 2014) on the counter
+// seed + (i*n+k+1) * golden gamma; top 53 bits as a double in [0,1).
+__device__ __forceinline__ double noise_u(uint64_t seed, int64_t n, int64_t i, int64_t k) {
+    uint64_t z = seed + (uint64_t)(i * n + k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Range of S with the preferences on the diagonal (FP64).
+__global__ void k_pref_range(PrefArgs a, double *range_out) {
+    __shared__ float lo[256], hi[256];
+    const double pm = median_of(a);
+    float mn = keyf(a.minmax[0]), mx = keyf(a.minmax[1]);
+    for (int64_t i = threadIdx.x; i < a.n; i += blockDim.x) {
+        const float p = (float)pref_of(a, i, pm);
+        mn = fminf(mn, p);
+        mx = fmaxf(mx, p);
+    }
+    lo[threadIdx.x] = mn;
+    hi[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + w]);
+            hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *range_out = (double)hi[0] - (double)lo[0];
+        *a.pref_dev = pm;
+    }
+}
+
+// Diagonal := preference; then, if enabled, every entry += scale * u(i,k).
+__global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *range) {
+    const double pm = median_of(a);
+    const double scale = a.noise_rel * (*range);
+    for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+        float *row = a.S + i * a.ld;
+        if (a.noise_rel > 0.0) {
+            for (int64_t k = threadIdx.x; k < a.n; k += blockDim.x) {
+                const double base = (k == i) ? pref_of(a, i, pm) : (double)row[k];
+                row[k] = (float)(base + scale * noise_u(a.seed, a.n, i, k));
+            }
+        } else if (threadIdx.x == 0) {
+            row[i] = (float)pref_of(a, i, pm);
+        }
+    }
+}
+
+}  // namespace
+}  // namespace apx
+
+using namespace apx;
+
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_err(ctx, _e, what);  \
+    } while (0)
+
+extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
+                                    float *S, int64_t ld, int32_t pref_mode, const float *pref_vec,
+                                    float pref_scalar, uint64_t noise_seed, double noise_rel,
+                                    double *pref_out) {
+    if (!ctx) return APX_EINVAL;
+    if (!X || !S) return set_err(ctx, APX_EINVAL, "X and S must be non-null");
+    if (n < 2 || d < 1) return set_err(ctx, APX_EINVAL, "need n >= 2 and d >= 1");
+    if (n > (int64_t)1 << 31) return set_err(ctx, APX_ENOTIMPL, "n too large");
+    if (ldx < d) return set_err(ctx, APX_EINVAL, "ldx < d");
+    if (ld < n || ld % 4) return set_err(ctx, APX_EINVAL, "ld must be >= n and a multiple of 4");
+    if ((reinterpret_cast<uintptr_t>(S) & 15u) != 0) return set_err(ctx, APX_EINVAL, "S not 16-byte aligned");
+    if (pref_mode < APX_PREF_MEDIAN || pref_mode > APX_PREF_VECTOR)
+        return set_err(ctx, APX_EINVAL, "bad pref_mode");
+    if (pref_mode == APX_PREF_VECTOR && !pref_vec) return set_err(ctx, APX_EINVAL, "pref_vec is null");
+    if (pref_mode == APX_PREF_SCALAR && !std::isfinite(pref_scalar))
+        return set_err(ctx, APX_EINVAL, "pref_scalar is not finite");
+    if (!(noise_rel >= 0.0) || !std::isfinite(noise_rel)) return set_err(ctx, APX_EINVAL, "bad noise_rel");
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != ctx->device) (void)hipSetDevice(ctx->device);
+    hipStream_t s = ctx->stream;
+
+    WsLayout L;
+    size_t o_n = L.take(sizeof(float) * (size_t)n);
+    size_t o_mm = L.take(sizeof(uint32_t) * 2);
+    size_t o_sel = L.take(sizeof(SelState));
+    size_t o_h = L.take(sizeof(unsigned long long) * 2 * 2048);
+    size_t o_r = L.take(sizeof(double) * 2);
+    apx_status st = ws_reserve(ctx, L.off);
+    if (st != APX_OK) return st;
+    char *b = static_cast<char *>(ctx->ws);
+    float *nrm = reinterpret_cast<float *>(b + o_n);
+    uint32_t *mm = reinterpret_cast<uint32_t *>(b + o_mm);
+    SelState *sel = reinterpret_cast<SelState *>(b + o_sel);
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(b + o_h);
+    double *dvals = reinterpret_cast<double *>(b + o_r);   // [0] range, [1] preference
+
+    const unsigned long long M = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+    const unsigned long long lo = (M % 2) ? (M - 1) / 2 : M / 2 - 1;
+    const unsigned long long hi = (M % 2) ? (M - 1) / 2 : M / 2;
+    k_sel_init<<<1, 256, 0, s>>>(sel, mm, lo, hi, hist);
+    HIP_TRY(hipGetLastError(), "select init");
+    k_sqnorm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(X, n, d, ldx, nrm);
+    HIP_TRY(hipGetLastError(), "sqnorm");
+    SimArgs sa{X, n, d, ldx, nrm, S, ld, (n + BM - 1) / BM, mm};
+    const int64_t ntiles = sa.tiles_per_side * (sa.tiles_per_side + 1) / 2;
+    k_sim_gemm<<<(unsigned)ntiles, NT, 0, s>>>(sa);
+    HIP_TRY(hipGetLastError(), "similarity gemm");
+    if (pref_mode == APX_PREF_MEDIAN) {
+        const int g = (int)(n - 1 < 2048 ? n - 1 : 2048);
+        for (int pass = 0; pass < 3; ++pass) {
+            k_sel_hist<<<g, 256, 0, s>>>(S, n, ld, sel, pass, hist);
+            HIP_TRY(hipGetLastError(), "select histogram");
+            k_sel_pick<<<1, 256, 0, s>>>(sel, pass, hist);
+            HIP_TRY(hipGetLastError(), "select pick");
+        }
+    }
+    PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1]};
+    k_pref_range<<<1, 256, 0, s>>>(pa, &dvals[0]);
+    HIP_TRY(hipGetLastError(), "preference range");
+    const int g = (int)(n < 8192 ? n : 8192);
+    k_pref_noise<<<g, 256, 0, s>>>(pa, &dvals[0]);
+    HIP_TRY(hipGetLastError(), "preference/noise");
+    if (pref_out) {
+        double *h = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 1024);
+        HIP_TRY(hipMemcpyAsync(h, &dvals[1], sizeof(double), hipMemcpyDeviceToHost, s), "pref copy");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        *pref_out = pref_mode == APX_PREF_VECTOR ? NAN : *h;
+    }
+    return APX_OK;
+}
