@@ -75,12 +75,17 @@ __device__ __forceinline__ void f4set(float4 &v, int e, float x) {
 // Availability update of one element (Eqs. (3), (4), damping).
 __device__ __forceinline__ float avail(float a, float r, float t, float ci, bool diag, float lam,
                                        float oml) {
+#pragma clang fp contract(off)
     float upd = diag ? ci : fminf(0.0f, t - fmaxf(0.0f, r));
     return lam * a + oml * upd;
 }
 
 template <int T, int J, int MODE>
 __global__ __launch_bounds__(T) void k_row_pass(PassArgs p) {
+    // Every product is rounded before it is added: with u = lambda*r +
+    // (1-lambda)*s and the subtraction of (1-lambda)*max below, an exact tie
+    // s(i,k) = max then cancels to exactly zero, as in Eq. (2).
+#pragma clang fp contract(off)
     if (p.st != nullptr && p.st->frozen) return;
     constexpr int NW = T / 64;
     __shared__ float sh_f[2][NW][3];
