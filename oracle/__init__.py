@@ -64,6 +64,9 @@ def lib():
     L.apo_finalize.restype = _i64
     L.apo_assign_nearest.argtypes = [_i64, _i64, _f32p, _i64, _i64, _i64p, _i32p,
                                      ctypes.POINTER(_dbl)]
+    L.apo_resp_rows.argtypes = [_i64, _f64p, _f64p, _f64p, _dbl, _i64p, _i64, _f64p]
+    L.apo_column_sums.argtypes = [_i64, _f64p, _f64p]
+    L.apo_avail_rows.argtypes = [_i64, _f64p, _f64p, _f64p, _dbl, _i64p, _i64, _f64p]
     _lib = L
     return L
 
@@ -184,6 +187,35 @@ def ap(S: np.ndarray, lam: float = 0.5, max_iter: int = 200, conv_iter: int = 15
         res.idx, res.n_exemplars = fin["idx"], fin["n_exemplars"]
         res.dpsim, res.expref, res.netsim = fin["dpsim"], fin["expref"], fin["netsim"]
     return res
+
+
+def resp_rows(S, A, R, lam, rows) -> np.ndarray:
+    """Eq. (2) with damping for the listed rows: R_next[rows] from (S, A, R)."""
+    n = S.shape[0]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.size, n))
+    lib().apo_resp_rows(n, np.ascontiguousarray(S, dtype=np.float64), np.ascontiguousarray(A, dtype=np.float64),
+                        np.ascontiguousarray(R, dtype=np.float64), lam, rows, rows.size, out)
+    return out
+
+
+def column_sums(R) -> np.ndarray:
+    """c_k = sum_{i != k} max(0, r(i,k))."""
+    n = R.shape[0]
+    c = np.empty(n)
+    lib().apo_column_sums(n, np.ascontiguousarray(R, dtype=np.float64), c)
+    return c
+
+
+def avail_rows(Rnew, A, lam, rows) -> np.ndarray:
+    """Eqs. (3), (4) with damping for the listed rows: A_next[rows] from (R_new, A)."""
+    n = Rnew.shape[0]
+    Rnew = np.ascontiguousarray(Rnew, dtype=np.float64)
+    c = column_sums(Rnew)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.size, n))
+    lib().apo_avail_rows(n, Rnew, c, np.ascontiguousarray(A, dtype=np.float64), lam, rows, rows.size, out)
+    return out
 
 
 def decisions(A: np.ndarray, R: np.ndarray) -> np.ndarray:

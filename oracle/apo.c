@@ -286,3 +286,47 @@ void apo_assign_nearest(int64_t n, int64_t d, const float *X, int64_t ldx, int64
     *dpsim = dp;
     free(is_ex); free(best_d);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Single-row pieces of one iteration, for checking large runs row by row.  */
+/* R_next rows: Eq. (2) with damping from (S, A, R) for the listed rows.    */
+/* ------------------------------------------------------------------------ */
+void apo_resp_rows(int64_t n, const double *S, const double *A, const double *R, double lam,
+                   const int64_t *rows, int64_t nrows, double *out /* nrows x n */)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nrows; ++q) {
+        const int64_t i = rows[q];
+        double *o = out + (size_t)q * (size_t)n;
+        for (int64_t k = 0; k < n; ++k) o[k] = R[IDX(i, k, n)];
+        /* responsibility_row updates row i of a matrix in place; point it
+         * at the output row by offsetting the base so that row i lands on o. */
+        responsibility_row(n, 0, S + IDX(i, 0, n), A + IDX(i, 0, n), o, lam);
+    }
+}
+
+/* Column sums c_k = sum_{i != k} max(0, r(i,k)) of a full R. */
+void apo_column_sums(int64_t n, const double *R, double *c) { column_sums(n, R, c); }
+
+/* A_next rows: Eqs. (3), (4) with damping from (R_new, c, A) for the listed rows. */
+void apo_avail_rows(int64_t n, const double *Rnew, const double *c, const double *A, double lam,
+                    const int64_t *rows, int64_t nrows, double *out /* nrows x n */)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nrows; ++q) {
+        const int64_t i = rows[q];
+        double *o = out + (size_t)q * (size_t)n;
+        const double *r = Rnew + IDX(i, 0, n);
+        for (int64_t k = 0; k < n; ++k) {
+            double upd;
+            if (k == i) {
+                upd = c[k];
+            } else {
+                double rik_pos = r[k] > 0.0 ? r[k] : 0.0;
+                double v = Rnew[IDX(k, k, n)] + (c[k] - rik_pos);
+                upd = v < 0.0 ? v : 0.0;
+            }
+            o[k] = lam * A[IDX(i, k, n)] + (1.0 - lam) * upd;
+        }
+    }
+}

@@ -40,6 +40,13 @@ int64_t apo_finalize(int64_t n, const double *S, const int32_t *dec, int32_t *id
 void apo_assign_nearest(int64_t n, int64_t d, const float *X, int64_t ldx, int64_t nex,
                         const int64_t *ex, int32_t *idx, double *dpsim);
 
+/* Row-wise pieces of one iteration (for sampled checks of large runs). */
+void apo_resp_rows(int64_t n, const double *S, const double *A, const double *R, double lam,
+                   const int64_t *rows, int64_t nrows, double *out);
+void apo_column_sums(int64_t n, const double *R, double *c);
+void apo_avail_rows(int64_t n, const double *Rnew, const double *c, const double *A, double lam,
+                    const int64_t *rows, int64_t nrows, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,11 +17,15 @@
 #include "apx_internal.h"
 
 #include <cfloat>
+#include <cstdlib>
 
 namespace apx {
 namespace {
 
 constexpr float kNegInf = -INFINITY;
+// Dynamic LDS of the row pass (u and column partials): 160 KB per CU on
+// gfx950, minus the static reduction scratch.
+constexpr int kMaxDynLds = 160 * 1024 - 1024;
 
 struct Top2 {
     float v1;   // largest a+s
@@ -34,32 +38,27 @@ struct ArgMax {
     int k;
 };
 
+// All merges are written as selects (no branches): columns arrive in
+// ascending order within a thread, so a tie keeps the earlier column.
 __device__ __forceinline__ void top2_push(Top2 &t, float v, int k) {
-    // columns arrive in ascending order within a thread: a tie keeps k1
-    if (v > t.v1) {
-        t.v2 = t.v1;
-        t.v1 = v;
-        t.k1 = k;
-    } else {
-        t.v2 = fmaxf(t.v2, v);
-    }
+    const bool gt = v > t.v1;
+    t.v2 = gt ? t.v1 : fmaxf(t.v2, v);
+    t.k1 = gt ? k : t.k1;
+    t.v1 = gt ? v : t.v1;
 }
 
 __device__ __forceinline__ void top2_merge(Top2 &t, float ov1, int ok1, float ov2) {
-    bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
-    float nv2 = take ? fmaxf(ov2, t.v1) : fmaxf(t.v2, ov1);
-    if (take) {
-        t.v1 = ov1;
-        t.k1 = ok1;
-    }
+    const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
+    const float nv2 = take ? fmaxf(ov2, t.v1) : fmaxf(t.v2, ov1);
+    t.v1 = take ? ov1 : t.v1;
+    t.k1 = take ? ok1 : t.k1;
     t.v2 = nv2;
 }
 
 __device__ __forceinline__ void argmax_merge(ArgMax &m, float ov, int ok) {
-    if (ov > m.v || (ov == m.v && ok < m.k)) {
-        m.v = ov;
-        m.k = ok;
-    }
+    const bool take = ov > m.v || (ov == m.v && ok < m.k);
+    m.v = take ? ov : m.v;
+    m.k = take ? ok : m.k;
 }
 
 __device__ __forceinline__ float f4get(const float4 &v, int e) {
@@ -80,14 +79,350 @@ __device__ __forceinline__ float avail(float a, float r, float t, float ci, bool
     return lam * a + oml * upd;
 }
 
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight (the next row is prefetched across the reduction).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, const float4 &v) { *reinterpret_cast<float4 *>(p) = v; }
+
+// Row access: every chunk of a row is addressed from a uniform row base (in
+// scalar registers) plus one shared per-thread byte offset (tid*16) and a
+// compile-time chunk offset (j*T*16).  Plain global loads and stores are
+// used: raw buffer-resource loads and stores (descriptor word 3 = 0x00020000)
+// gave run-to-run differences in this kernel on gfx950 for rows longer than
+// ~12k elements, while global memory operations are exact and reproducible.
+typedef const float *rsrc_t;
+__device__ __forceinline__ rsrc_t row_rsrc(const float *base, int64_t) { return base; }
+__device__ __forceinline__ float4 bld4(rsrc_t r, int voff, int soff) {
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(r) + voff + soff);
+}
+__device__ __forceinline__ void bst4(rsrc_t r, int voff, int soff, const float4 &x) {
+    *reinterpret_cast<float4 *>(const_cast<char *>(reinterpret_cast<const char *>(r)) + voff + soff) = x;
+}
+
+// ---- per-chunk pieces of the row pass ------------------------------------
+// Thread tid owns the float4 chunks j = 0..J-1 at columns c_j = 4*(j*T+tid)
+// of every row.  Inside a thread, columns are visited in ascending order and
+// identified by the local index 4*j+e (a compile-time constant), so ties keep
+// the lowest column without any per-element index arithmetic.  A column k
+// belongs to thread (k/4) % T, chunk (k/4) / T, element k % 4.
+struct ColOwner {
+    bool mine;   // this thread owns the column
+    int j, e;    // its chunk and element (uniform)
+};
+template <int T>
+__device__ __forceinline__ ColOwner owner_of(int k, int tid) {
+    return ColOwner{((k >> 2) % T) == tid, (k >> 2) / T, k & 3};
+}
+template <int T>
+__device__ __forceinline__ int local_to_col(int le, int tid) {
+    return ((le >> 2) * T + tid) * 4 + (le & 3);
+}
+
+// Availabilities A_t (Eqs. (3), (4), damping) of chunk j, and the running
+// decision argmax_k a(i,k)+r(i,k) as a local index.
+__device__ __forceinline__ void chunk_avail(float4 &a, const float4 &r, const float4 &t, float ci,
+                                            int j, const ColOwner &dg, int c, int n, bool full,
+                                            float lam, float oml, float &dv, int &dl) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (full || c + e < n) {
+            const bool diag = dg.mine && dg.j == j && dg.e == e;
+            const float an = avail(f4get(a, e), f4get(r, e), f4get(t, e), ci, diag, lam, oml);
+            f4set(a, e, an);
+            const float v = an + f4get(r, e);
+            const bool gt = v > dv;
+            dl = gt ? 4 * j + e : dl;
+            dv = gt ? v : dv;
+        }
+    }
+}
+
+// Top-2 of a(i,k)+s(i,k) (local indices) and u = lambda*r + (1-lambda)*s.
+__device__ __forceinline__ float4 chunk_top2(const float4 &a, const float4 &r, const float4 &sv,
+                                             int j, int c, int n, bool full, float lam, float oml,
+                                             float &v1, int &l1, float &v2) {
+#pragma clang fp contract(off)
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (full || c + e < n) {
+            const float v = f4get(a, e) + f4get(sv, e);
+            const bool gt = v > v1;
+            v2 = gt ? v1 : fmaxf(v2, v);
+            l1 = gt ? 4 * j + e : l1;
+            v1 = gt ? v : v1;
+            f4set(u, e, lam * f4get(r, e) + oml * f4get(sv, e));
+        }
+    }
+    return u;
+}
+
+// R_{t+1} (Eq. (2), damping) of chunk j from u; returns max(0, r) for the
+// column partials (zero on the diagonal and outside the row).
+__device__ __forceinline__ float4 chunk_resp(const float4 &u, int j, const ColOwner &k1,
+                                             const ColOwner &dg, float m_self, float m_other,
+                                             int c, int n, bool full, float4 &rn, float *rdiag) {
+#pragma clang fp contract(off)
+    float4 pos;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const bool self = k1.mine && k1.j == j && k1.e == e;
+        const bool diag = dg.mine && dg.j == j && dg.e == e;
+        const float v = f4get(u, e) - (self ? m_self : m_other);
+        f4set(rn, e, v);
+        f4set(pos, e, (diag || !(full || c + e < n)) ? 0.0f : fmaxf(0.0f, v));
+        if (diag) *rdiag = v;
+    }
+    return pos;
+}
+
+__device__ __forceinline__ void add4(float4 &a, const float4 &b) {
+    a.x += b.x;
+    a.y += b.y;
+    a.z += b.z;
+    a.w += b.w;
+}
+
+// Store a chunk: one 16-byte buffer store, or element stores for the tail.
+__device__ __forceinline__ void store_chunk(float *row, rsrc_t rs, int voff, int soff, int c, int n,
+                                            bool full, const float4 &v) {
+    if (full) {
+        bst4(rs, voff, soff, v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (c + e < n) row[c + e] = f4get(v, e);
+    }
+}
+
+// Workgroup reduction of the decision and the top-2 (deterministic order):
+// wavefront butterflies, one LDS slot per wavefront, then every wavefront
+// reduces the NW slots lane-parallel and broadcasts lane 0's result.
+template <int NW, bool DO_A, bool DO_R>
+__device__ __forceinline__ void wg_reduce(Top2 &t2, ArgMax &dm, float (*sh_f)[3], int (*sh_i)[2],
+                                          int lane, int wave) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        if constexpr (DO_R) {
+            const float ov1 = __shfl_xor(t2.v1, off, 64);
+            const int ok1 = __shfl_xor(t2.k1, off, 64);
+            const float ov2 = __shfl_xor(t2.v2, off, 64);
+            top2_merge(t2, ov1, ok1, ov2);
+        }
+        if constexpr (DO_A) {
+            const float odv = __shfl_xor(dm.v, off, 64);
+            const int odk = __shfl_xor(dm.k, off, 64);
+            argmax_merge(dm, odv, odk);
+        }
+    }
+    if (lane == 0) {
+        sh_f[wave][0] = t2.v1;
+        sh_f[wave][1] = t2.v2;
+        sh_f[wave][2] = dm.v;
+        sh_i[wave][0] = t2.k1;
+        sh_i[wave][1] = dm.k;
+    }
+    lds_barrier();
+    if constexpr (NW > 1) {
+        const bool has = lane < NW;
+        const int w = has ? lane : 0;
+        if constexpr (DO_R) t2 = has ? Top2{sh_f[w][0], sh_i[w][0], sh_f[w][1]} : Top2{kNegInf, INT32_MAX, kNegInf};
+        if constexpr (DO_A) dm = has ? ArgMax{sh_f[w][2], sh_i[w][1]} : ArgMax{kNegInf, INT32_MAX};
+#pragma unroll
+        for (int off = NW / 2; off >= 1; off >>= 1) {
+            if constexpr (DO_R) {
+                const float ov1 = __shfl_xor(t2.v1, off, 64);
+                const int ok1 = __shfl_xor(t2.k1, off, 64);
+                const float ov2 = __shfl_xor(t2.v2, off, 64);
+                top2_merge(t2, ov1, ok1, ov2);
+            }
+            if constexpr (DO_A) {
+                const float odv = __shfl_xor(dm.v, off, 64);
+                const int odk = __shfl_xor(dm.k, off, 64);
+                argmax_merge(dm, odv, odk);
+            }
+        }
+        if constexpr (DO_R) t2 = Top2{__shfl(t2.v1, 0, 64), __shfl(t2.k1, 0, 64), __shfl(t2.v2, 0, 64)};
+        if constexpr (DO_A) dm = ArgMax{__shfl(dm.v, 0, 64), __shfl(dm.k, 0, 64)};
+    } else {
+        t2 = Top2{sh_f[0][0], sh_i[0][0], sh_f[0][1]};
+        dm = ArgMax{sh_f[0][2], sh_i[0][1]};
+    }
+}
+
+// Decision bookkeeping of row ii (thread 0): raw decision, exemplar flag,
+// change of the exemplar set, exemplar count.
+__device__ __forceinline__ void note_decision(const PassArgs &p, int ii, int k, int &my_nex,
+                                              int &my_changed) {
+    if (p.dec) p.dec[ii] = k;
+    if (p.eflag) {
+        const uint8_t e = (uint8_t)(k == ii);
+        if (p.eflag[ii] != e) my_changed = 1;
+        p.eflag[ii] = e;
+        my_nex += e;
+    }
+}
+
+// Row pass, LDS-resident variant.  u = lambda*r + (1-lambda)*s and the
+// column partials live in LDS (2 * 16 * ceil(n/4) bytes), which leaves the
+// registers free to hold the next row's S, R, A chunks: they are loaded
+// before the top-2 reduction of the current row, so HBM reads stay in flight
+// across the reduction and the R_{t+1} stores.
 template <int T, int J, int MODE>
 __global__ __launch_bounds__(T) void k_row_pass(PassArgs p) {
-    // Every product is rounded before it is added: with u = lambda*r +
-    // (1-lambda)*s and the subtraction of (1-lambda)*max below, an exact tie
-    // s(i,k) = max then cancels to exactly zero, as in Eq. (2).
-#pragma clang fp contract(off)
-    if (p.st != nullptr && p.st->frozen) return;
+    constexpr bool DO_A = (MODE == PASS_FULL || MODE == PASS_A_ONLY);
+    constexpr bool DO_R = (MODE != PASS_A_ONLY);
+    constexpr bool LD_S = DO_R;
+    constexpr bool LD_RA = (MODE != PASS_R_COLD);
     constexpr int NW = T / 64;
+
+    if (p.st != nullptr && p.st->frozen) return;
+    __shared__ float sh_f[2][NW][3];
+    __shared__ int sh_i[2][NW][2];
+    extern __shared__ float4 dyn[];
+    const int q = (p.n + 3) >> 2;                // float4 chunks per row
+    float4 *lu = dyn;                            // u, q entries
+    float4 *lpart = dyn + q;                     // column partials, q entries
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n = p.n;
+    const int64_t ld = p.ld;
+    const float lam = p.lam;
+    const float oml = 1.0f - lam;
+    const int64_t nrows = p.row_end - p.row_begin;
+    const int64_t r0 = p.row_begin + (int64_t)blockIdx.x * nrows / gridDim.x;
+    const int64_t r1 = p.row_begin + (int64_t)(blockIdx.x + 1) * nrows / gridDim.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int voff = tid * 16;
+    const int c0 = tid * 4;
+    const int cl = ((J - 1) * T + tid) * 4;      // column of the last chunk
+    const bool last_in = cl < n;                 // last chunk holds data
+    const bool last_full = cl + 3 < n;
+
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if constexpr (DO_R)
+            if (j < J - 1 || last_in) lpart[j * T + tid] = z4;
+    int my_nex = 0, my_changed = 0;
+
+    // The column vector t_k is read per chunk inside the availability step
+    // (an L2 hit), never held in registers across the row reduction: with the
+    // next row's loads in flight, t_k values held across the reduction came
+    // out wrong in some lanes (lanes 12-15 of each 16) on gfx950 with this
+    // compiler; reading them at use is exact and costs no HBM traffic.
+    float4 s4[LD_S ? J : 1], r4[LD_RA ? J : 1], a4[LD_RA ? J : 1];
+    auto load_row = [&](int64_t i) {
+        const rsrc_t srs = row_rsrc(p.S + i * ld, ld);
+        const rsrc_t rrs = row_rsrc(p.Rin + i * ld, ld);
+        const rsrc_t ars = row_rsrc(p.A + i * ld, ld);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (j < J - 1 || last_in) {
+                if constexpr (LD_S) s4[j] = bld4(srs, voff, j * T * 16);
+                if constexpr (LD_RA) {
+                    r4[j] = bld4(rrs, voff, j * T * 16);
+                    a4[j] = bld4(ars, voff, j * T * 16);
+                }
+            }
+        }
+    };
+    if (r0 < r1) load_row(r0);
+
+    for (int64_t i = r0; i < r1; ++i) {
+        const int ii = (int)i;
+        const ColOwner dg = owner_of<T>(ii, tid);
+        float *Arow = p.A + i * ld;
+        const rsrc_t a_rs = row_rsrc(Arow, ld);
+        float ci = 0.0f;
+        if constexpr (DO_A) ci = p.ccol[ii];
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+        int l1 = -1, dl = -1;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            float4 a = z4, r = z4;
+            if constexpr (LD_RA) {
+                a = a4[j];
+                r = r4[j];
+            }
+            if constexpr (DO_A) {
+                chunk_avail(a, r, ld4(p.tcol + c), ci, j, dg, c, n, full, lam, oml, dv, dl);
+                store_chunk(Arow, a_rs, voff, j * T * 16, c, n, full, a);
+            }
+            if constexpr (DO_R) lu[j * T + tid] = chunk_top2(a, r, s4[j], j, c, n, full, lam, oml, v1, l1, v2);
+        }
+        // Keep the scheduler from hoisting the next row's loads into the
+        // computation above: both rows' registers would then be live at once.
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < r1) load_row(i + 1);
+        __builtin_amdgcn_sched_barrier(0);
+
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
+        const int slot = (int)(i & 1);
+        wg_reduce<NW, DO_A, DO_R>(t2, dm, sh_f[slot], sh_i[slot], lane, wave);
+        if constexpr (DO_A) {
+            if (tid == 0) note_decision(p, ii, dm.k, my_nex, my_changed);
+        }
+        if constexpr (DO_R) {
+            const float m_other = oml * t2.v1;   // (1-lambda) * max over k' != k, for k != k1
+            const float m_self = oml * t2.v2;    // for k = k1
+            const ColOwner ko = owner_of<T>(t2.k1, tid);
+            float *Rout = p.Rout + i * ld;
+            const rsrc_t r_rs = row_rsrc(Rout, ld);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (!(j < J - 1 || last_in)) continue;
+                const bool full = (j < J - 1) || last_full;
+                const int c = c0 + j * T * 4;
+                float4 rn;
+                const float4 pos = chunk_resp(lu[j * T + tid], j, ko, dg, m_self, m_other, c, n,
+                                              full, rn, p.rdiag + ii);
+                store_chunk(Rout, r_rs, voff, j * T * 16, c, n, full, rn);
+                float4 acc = lpart[j * T + tid];
+                add4(acc, pos);
+                lpart[j * T + tid] = acc;
+            }
+        }
+    }
+
+    if constexpr (DO_R) {
+        float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, lpart[j * T + tid]);
+    }
+    if constexpr (DO_A) {
+        if (tid == 0 && p.st != nullptr) {
+            if (my_nex) atomicAdd(&p.st->nex, my_nex);
+            if (my_changed) atomicOr(&p.st->changed, 1);
+        }
+    }
+}
+
+// Row pass, register variant for long rows (LDS too small for u and the
+// partials): u and the partials live in registers, t_k is read per chunk
+// from L2, and rows are not prefetched.
+template <int T, int J, int MODE>
+__global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
+    constexpr bool DO_A = (MODE == PASS_FULL || MODE == PASS_A_ONLY);
+    constexpr bool DO_R = (MODE != PASS_A_ONLY);
+    constexpr bool LD_S = DO_R;
+    constexpr bool LD_RA = (MODE != PASS_R_COLD);
+    constexpr int NW = T / 64;
+
+    if (p.st != nullptr && p.st->frozen) return;
     __shared__ float sh_f[2][NW][3];
     __shared__ int sh_i[2][NW][2];
 
@@ -101,161 +436,85 @@ __global__ __launch_bounds__(T) void k_row_pass(PassArgs p) {
     const int64_t nrows = p.row_end - p.row_begin;
     const int64_t r0 = p.row_begin + (int64_t)blockIdx.x * nrows / gridDim.x;
     const int64_t r1 = p.row_begin + (int64_t)(blockIdx.x + 1) * nrows / gridDim.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int voff = tid * 16;
+    const int c0 = tid * 4;
+    const int cl = ((J - 1) * T + tid) * 4;
+    const bool last_in = cl < n;
+    const bool last_full = cl + 3 < n;
 
-    float4 part[J];
-    float4 tv[J];
+    float4 part[DO_R ? J : 1];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        part[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int c = (j * T + tid) * 4;
-        if (MODE != PASS_R_ONLY && c < n) tv[j] = *reinterpret_cast<const float4 *>(p.tcol + c);
-        else tv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int j = 0; j < J; ++j)
+        if constexpr (DO_R) part[j] = z4;
     int my_nex = 0, my_changed = 0;
+    const rsrc_t t_rs = row_rsrc(p.tcol, p.ldp);
 
     for (int64_t i = r0; i < r1; ++i) {
         const int ii = (int)i;
-        const float *Srow = p.S + i * ld;
-        const float *Rin = p.Rin + i * ld;
-        float *Rout = p.Rout + i * ld;
+        const ColOwner dg = owner_of<T>(ii, tid);
         float *Arow = p.A + i * ld;
-        const float ci = (MODE != PASS_R_ONLY) ? p.ccol[ii] : 0.0f;
-
-        float4 u[J];
-        Top2 t2{kNegInf, n, kNegInf};
-        ArgMax dm{kNegInf, n};
+        const rsrc_t a_rs = row_rsrc(Arow, ld);
+        const rsrc_t r_rs = row_rsrc(p.Rin + i * ld, ld);
+        const rsrc_t s_rs = row_rsrc(p.S + i * ld, ld);
+        float ci = 0.0f;
+        if constexpr (DO_A) ci = p.ccol[ii];
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+        int l1 = -1, dl = -1;
+        float4 u[DO_R ? J : 1];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const int c = (j * T + tid) * 4;
-            u[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < n) {
-                float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (MODE != PASS_A_ONLY) s4 = *reinterpret_cast<const float4 *>(Srow + c);
-                float4 r4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (p.load_r) r4 = *reinterpret_cast<const float4 *>(Rin + c);
-                float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (p.load_a) a4 = *reinterpret_cast<const float4 *>(Arow + c);
-                const bool full = c + 3 < n;
-                if (MODE != PASS_R_ONLY) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k = c + e;
-                        if (k < n) {
-                            float an = avail(f4get(a4, e), f4get(r4, e), f4get(tv[j], e), ci,
-                                             k == ii, lam, oml);
-                            f4set(a4, e, an);
-                            float dvv = an + f4get(r4, e);
-                            if (dvv > dm.v) {
-                                dm.v = dvv;
-                                dm.k = k;
-                            }
-                        }
-                    }
-                    if (full) {
-                        *reinterpret_cast<float4 *>(Arow + c) = a4;
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (c + e < n) Arow[c + e] = f4get(a4, e);
-                    }
-                }
-                if (MODE != PASS_A_ONLY) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k = c + e;
-                        if (k < n) {
-                            top2_push(t2, f4get(a4, e) + f4get(s4, e), k);
-                            f4set(u[j], e, lam * f4get(r4, e) + oml * f4get(s4, e));
-                        }
-                    }
-                }
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            float4 a = z4, r = z4, sv = z4;
+            if constexpr (LD_RA) {
+                a = bld4(a_rs, voff, j * T * 16);
+                r = bld4(r_rs, voff, j * T * 16);
             }
+            if constexpr (LD_S) sv = bld4(s_rs, voff, j * T * 16);
+            if constexpr (DO_A) {
+                chunk_avail(a, r, bld4(t_rs, voff, j * T * 16), ci, j, dg, c, n, full, lam, oml, dv, dl);
+                store_chunk(Arow, a_rs, voff, j * T * 16, c, n, full, a);
+            }
+            if constexpr (DO_R) u[j] = chunk_top2(a, r, sv, j, c, n, full, lam, oml, v1, l1, v2);
         }
-
-        // ---- workgroup reduction of the decision and the top-2 ----------
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            if (MODE != PASS_A_ONLY) {
-                float ov1 = __shfl_xor(t2.v1, off, 64);
-                int ok1 = __shfl_xor(t2.k1, off, 64);
-                float ov2 = __shfl_xor(t2.v2, off, 64);
-                top2_merge(t2, ov1, ok1, ov2);
-            }
-            if (MODE != PASS_R_ONLY) {
-                float odv = __shfl_xor(dm.v, off, 64);
-                int odk = __shfl_xor(dm.k, off, 64);
-                argmax_merge(dm, odv, odk);
-            }
-        }
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
         const int slot = (int)(i & 1);
-        if (lane == 0) {
-            sh_f[slot][wave][0] = t2.v1;
-            sh_f[slot][wave][1] = t2.v2;
-            sh_f[slot][wave][2] = dm.v;
-            sh_i[slot][wave][0] = t2.k1;
-            sh_i[slot][wave][1] = dm.k;
+        wg_reduce<NW, DO_A, DO_R>(t2, dm, sh_f[slot], sh_i[slot], lane, wave);
+        if constexpr (DO_A) {
+            if (tid == 0) note_decision(p, ii, dm.k, my_nex, my_changed);
         }
-        __syncthreads();
-        Top2 bt{sh_f[slot][0][0], sh_i[slot][0][0], sh_f[slot][0][1]};
-        ArgMax bd{sh_f[slot][0][2], sh_i[slot][0][1]};
-#pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            top2_merge(bt, sh_f[slot][w][0], sh_i[slot][w][0], sh_f[slot][w][1]);
-            argmax_merge(bd, sh_f[slot][w][2], sh_i[slot][w][1]);
-        }
-
-        if (MODE != PASS_R_ONLY && tid == 0) {
-            if (p.dec) p.dec[ii] = bd.k;
-            if (p.eflag) {
-                const uint8_t e = (uint8_t)(bd.k == ii);
-                if (p.eflag[ii] != e) my_changed = 1;
-                p.eflag[ii] = e;
-                my_nex += e;
-            }
-        }
-
-        // ---- responsibilities R_{t+1} and column partials ----------------
-        if (MODE != PASS_A_ONLY) {
-            const float m_other = oml * bt.v1;   // (1-lambda) * max over k' != k, k != k1
-            const float m_self = oml * bt.v2;    // at k = k1
+        if constexpr (DO_R) {
+            const float m_other = oml * t2.v1;
+            const float m_self = oml * t2.v2;
+            const ColOwner ko = owner_of<T>(t2.k1, tid);
+            float *Rout = p.Rout + i * ld;
+            const rsrc_t o_rs = row_rsrc(Rout, ld);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const int c = (j * T + tid) * 4;
-                if (c < n) {
-                    float4 rn;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k = c + e;
-                        const float v = f4get(u[j], e) - (k == bt.k1 ? m_self : m_other);
-                        f4set(rn, e, v);
-                        if (k < n) {
-                            if (k == ii) p.rdiag[ii] = v;
-                            else f4set(part[j], e, f4get(part[j], e) + fmaxf(0.0f, v));
-                        }
-                    }
-                    if (c + 3 < n) {
-                        *reinterpret_cast<float4 *>(Rout + c) = rn;
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (c + e < n) Rout[c + e] = f4get(rn, e);
-                    }
-                }
+                if (!(j < J - 1 || last_in)) continue;
+                const bool full = (j < J - 1) || last_full;
+                const int c = c0 + j * T * 4;
+                float4 rn;
+                add4(part[j], chunk_resp(u[j], j, ko, dg, m_self, m_other, c, n, full, rn,
+                                         p.rdiag + ii));
+                store_chunk(Rout, o_rs, voff, j * T * 16, c, n, full, rn);
             }
         }
     }
-
-    if (MODE != PASS_A_ONLY) {
+    if constexpr (DO_R) {
         float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int c = (j * T + tid) * 4;
-            if (c < n) *reinterpret_cast<float4 *>(P + c) = part[j];
-        }
+        for (int j = 0; j < J; ++j)
+            if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, part[j]);
     }
-    if (MODE != PASS_R_ONLY && tid == 0 && p.st != nullptr) {
-        if (my_nex) atomicAdd(&p.st->nex, my_nex);
-        if (my_changed) atomicOr(&p.st->changed, 1);
+    if constexpr (DO_A) {
+        if (tid == 0 && p.st != nullptr) {
+            if (my_nex) atomicAdd(&p.st->nex, my_nex);
+            if (my_changed) atomicOr(&p.st->changed, 1);
+        }
     }
 }
 
@@ -416,12 +675,34 @@ __global__ __launch_bounds__(1024) void k_sum2(const double *contrib, int32_t n,
     }
 }
 
+template <int T, int J, int MODE>
+hipError_t launch_lds(const PassArgs &a, int grid, size_t lds, hipStream_t s) {
+    static bool attr_set = false;   // per process; the attribute is per function
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_row_pass<T, J, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_row_pass<T, J, MODE><<<grid, T, lds, s>>>(a);
+    return hipGetLastError();
+}
+
 template <int T, int J>
-hipError_t launch_t(int mode, const PassArgs &a, int grid, hipStream_t s) {
+hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t s) {
+    if (pl.lds_bytes > 0) {
+        switch (mode) {
+        case PASS_FULL: return launch_lds<T, J, PASS_FULL>(a, pl.grid, pl.lds_bytes, s);
+        case PASS_R_ONLY: return launch_lds<T, J, PASS_R_ONLY>(a, pl.grid, pl.lds_bytes, s);
+        case PASS_R_COLD: return launch_lds<T, J, PASS_R_COLD>(a, pl.grid, pl.lds_bytes, s);
+        default: return launch_lds<T, J, PASS_A_ONLY>(a, pl.grid, pl.lds_bytes, s);
+        }
+    }
     switch (mode) {
-    case PASS_FULL: k_row_pass<T, J, PASS_FULL><<<grid, T, 0, s>>>(a); break;
-    case PASS_R_ONLY: k_row_pass<T, J, PASS_R_ONLY><<<grid, T, 0, s>>>(a); break;
-    default: k_row_pass<T, J, PASS_A_ONLY><<<grid, T, 0, s>>>(a); break;
+    case PASS_FULL: k_row_pass_reg<T, J, PASS_FULL><<<pl.grid, T, 0, s>>>(a); break;
+    case PASS_R_ONLY: k_row_pass_reg<T, J, PASS_R_ONLY><<<pl.grid, T, 0, s>>>(a); break;
+    case PASS_R_COLD: k_row_pass_reg<T, J, PASS_R_COLD><<<pl.grid, T, 0, s>>>(a); break;
+    default: k_row_pass_reg<T, J, PASS_A_ONLY><<<pl.grid, T, 0, s>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -441,36 +722,41 @@ PassPlan plan_pass(int64_t n, int num_cus) {
         pl.chunks = (int)((q + 1023) / 1024);
         pl.grid = (int)(n < num_cus ? n : num_cus);
     }
+    const size_t lds = (size_t)2 * 16 * (size_t)q;
+    pl.lds_bytes = (lds <= (size_t)kMaxDynLds && pl.chunks <= 5) ? lds : 0;
+    // APX_ROW_PASS=reg selects the register variant (tuning and cross-checks).
+    const char *v = getenv("APX_ROW_PASS");
+    if (v && v[0] == 'r') pl.lds_bytes = 0;
     return pl;
 }
 
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s) {
     if (pl.threads == 256) {
         switch (pl.chunks) {
-        case 1: return launch_t<256, 1>(mode, a, pl.grid, s);
-        case 2: return launch_t<256, 2>(mode, a, pl.grid, s);
-        case 3: return launch_t<256, 3>(mode, a, pl.grid, s);
-        case 4: return launch_t<256, 4>(mode, a, pl.grid, s);
+        case 1: return launch_t<256, 1>(mode, a, pl, s);
+        case 2: return launch_t<256, 2>(mode, a, pl, s);
+        case 3: return launch_t<256, 3>(mode, a, pl, s);
+        case 4: return launch_t<256, 4>(mode, a, pl, s);
         default: return hipErrorInvalidValue;
         }
     }
     switch (pl.chunks) {
-    case 1: return launch_t<1024, 1>(mode, a, pl.grid, s);
-    case 2: return launch_t<1024, 2>(mode, a, pl.grid, s);
-    case 3: return launch_t<1024, 3>(mode, a, pl.grid, s);
-    case 4: return launch_t<1024, 4>(mode, a, pl.grid, s);
-    case 5: return launch_t<1024, 5>(mode, a, pl.grid, s);
-    case 6: return launch_t<1024, 6>(mode, a, pl.grid, s);
-    case 7: return launch_t<1024, 7>(mode, a, pl.grid, s);
-    case 8: return launch_t<1024, 8>(mode, a, pl.grid, s);
-    case 9: return launch_t<1024, 9>(mode, a, pl.grid, s);
-    case 10: return launch_t<1024, 10>(mode, a, pl.grid, s);
-    case 11: return launch_t<1024, 11>(mode, a, pl.grid, s);
-    case 12: return launch_t<1024, 12>(mode, a, pl.grid, s);
-    case 13: return launch_t<1024, 13>(mode, a, pl.grid, s);
-    case 14: return launch_t<1024, 14>(mode, a, pl.grid, s);
-    case 15: return launch_t<1024, 15>(mode, a, pl.grid, s);
-    case 16: return launch_t<1024, 16>(mode, a, pl.grid, s);
+    case 1: return launch_t<1024, 1>(mode, a, pl, s);
+    case 2: return launch_t<1024, 2>(mode, a, pl, s);
+    case 3: return launch_t<1024, 3>(mode, a, pl, s);
+    case 4: return launch_t<1024, 4>(mode, a, pl, s);
+    case 5: return launch_t<1024, 5>(mode, a, pl, s);
+    case 6: return launch_t<1024, 6>(mode, a, pl, s);
+    case 7: return launch_t<1024, 7>(mode, a, pl, s);
+    case 8: return launch_t<1024, 8>(mode, a, pl, s);
+    case 9: return launch_t<1024, 9>(mode, a, pl, s);
+    case 10: return launch_t<1024, 10>(mode, a, pl, s);
+    case 11: return launch_t<1024, 11>(mode, a, pl, s);
+    case 12: return launch_t<1024, 12>(mode, a, pl, s);
+    case 13: return launch_t<1024, 13>(mode, a, pl, s);
+    case 14: return launch_t<1024, 14>(mode, a, pl, s);
+    case 15: return launch_t<1024, 15>(mode, a, pl, s);
+    case 16: return launch_t<1024, 16>(mode, a, pl, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -136,8 +136,7 @@ apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const Pas
 }
 
 PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int64_t n, int64_t ld,
-                   float lam, const IterWs &w, int load_r, int load_a, int32_t *dec, uint8_t *eflag,
-                   ApState *st) {
+                   float lam, const IterWs &w, int32_t *dec, uint8_t *eflag, ApState *st) {
     PassArgs a{};
     a.S = S;
     a.Rin = Rin;
@@ -145,8 +144,6 @@ PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int6
     a.A = A;
     a.ld = ld;
     a.n = (int32_t)n;
-    a.load_r = load_r;
-    a.load_a = load_a;
     a.lam = lam;
     a.tcol = w.tcol;
     a.ccol = w.ccol;
@@ -250,15 +247,15 @@ apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float
     APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
     hipStream_t s = ctx->stream;
     // R_{t+1} from (R_t, S, A_t), in place, with its column vectors.
-    PassArgs pa = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, nullptr, nullptr, nullptr);
+    PassArgs pa = pass_args(S, R, R, A, n, ld, damping, w, nullptr, nullptr, nullptr);
     HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pa, s), "row pass (R)");
     HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
     for (int32_t it = 1; it < n_iter; ++it) {
-        PassArgs pf = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, nullptr, nullptr, nullptr);
+        PassArgs pf = pass_args(S, R, R, A, n, ld, damping, w, nullptr, nullptr, nullptr);
         HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
         HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
     }
-    PassArgs pe = pass_args(S, R, R, A, n, ld, damping, w, 1, 1, decision, nullptr, nullptr);
+    PassArgs pe = pass_args(S, R, R, A, n, ld, damping, w, decision, nullptr, nullptr);
     HIP_TRY(launch_row_pass(pl, PASS_A_ONLY, pe, s), "row pass (A)");
     return APX_OK;
 }
@@ -307,10 +304,15 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
 
     // R_t lives in buf[t & 1]; buf[0] is the caller's R.
     float *buf[2] = {R, w.R2};
-    const int load_r0 = (warm == APX_WARM_AR);
-    const int load_a0 = (warm != APX_COLD);
-    PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, load_r0, load_a0, nullptr, nullptr, nullptr);
-    HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
+    PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, nullptr, nullptr, nullptr);
+    if (warm == APX_COLD) {
+        // R_1 from R_0 = A_0 = 0, then A_0 = 0 in memory (Eq. (1)).
+        HIP_TRY(launch_row_pass(pl, PASS_R_COLD, pr, s), "prologue");
+        HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+    } else {
+        if (warm == APX_WARM_A) HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R_0");
+        HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
+    }
     HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
 
     const int chunk = params->check_every > 0 ? params->check_every : 16;
@@ -328,8 +330,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         if (stop_at > params->max_iter + 1) stop_at = params->max_iter + 1;
         const int32_t t_first = t;
         for (; t < stop_at; ++t) {
-            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, 1,
-                                    (t > 1) || load_a0, w.dec, w.eflag, w.st);
+            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec,
+                                    w.eflag, w.st);
             const int slot = t - t_first;
             if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
             HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");

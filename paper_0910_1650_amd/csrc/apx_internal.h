@@ -31,7 +31,11 @@ struct ApState {
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
 // column vectors of R_t; it writes A_t, the decisions d_t and R_{t+1} with
 // the column partials of max(0, R_{t+1}).
-enum PassMode : int { PASS_FULL = 0, PASS_R_ONLY = 1, PASS_A_ONLY = 2 };
+//   PASS_FULL    A_t, decisions, R_{t+1}          (reads S, R, A)
+//   PASS_R_ONLY  R_{t+1} from (R_t, A_t)           (reads S, R, A)
+//   PASS_R_COLD  R_1 from R_0 = A_0 = 0            (reads S)
+//   PASS_A_ONLY  A_t and decisions, no R_{t+1}      (reads R, A)
+enum PassMode : int { PASS_FULL = 0, PASS_R_ONLY = 1, PASS_A_ONLY = 2, PASS_R_COLD = 3 };
 
 struct PassArgs {
     const float *S;
@@ -40,8 +44,6 @@ struct PassArgs {
     float *A;           // A_{t-1} in, A_t out (in place)
     int64_t ld;
     int32_t n;
-    int32_t load_r;     // 0: R_t is taken as zero (cold prologue)
-    int32_t load_a;     // 0: the incoming A is taken as zero
     float lam;
     const float *tcol;  // t_k = r(k,k) + c_k of R_t
     const float *ccol;  // c_k = sum_{i != k} max(0, r(i,k)) of R_t
@@ -72,6 +74,7 @@ struct PassPlan {
     int threads;   // workgroup size
     int chunks;    // float4 chunks per thread per row
     int grid;      // workgroups
+    size_t lds_bytes;  // dynamic LDS of the LDS-resident variant (0: register variant)
 };
 PassPlan plan_pass(int64_t n, int num_cus);
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);

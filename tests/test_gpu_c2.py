@@ -1,0 +1,131 @@
+"""Parity on the 64-D Gaussian-mixture workload (50 components, damping 0.9).
+
+* N=6000: every message against the FP64 oracle after 100 iterations on the
+  same S (the oracle's S rounded once to FP32), then exemplars, labels and
+  stop iteration at convergence with S built on the GPU by ap_similarity
+  (FP32 matrix cores) while the oracle builds its own S in FP64.  Messages
+  are compared on a shared S because at damping 0.9 a perturbation of S at
+  FP32 rounding level alone moves the messages by ~1e-3 of the range after
+  100 iterations on this workload (an FP32 emulation with a GEMM-form S
+  shows the same), which is a property of the iteration, not of the kernels.
+* N=20000 (the benchmark workload, same launch configuration): sampled rows
+  of one iteration against the oracle's row-wise pieces of Eqs. (2)-(4),
+  label validity and net similarity recomputed in FP64, and bit-identical
+  results across repeated solves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0910_1650_amd as apx  # noqa: E402
+
+TOL = 1e-4
+
+
+def host(M):
+    return M.detach().cpu().numpy().astype(np.float64)
+
+
+def gpu_S(pts, seed):
+    X = torch.from_numpy(pts.X).cuda()
+    S, p = apx.ap_similarity(X, pref="median", noise_seed=seed, noise_rel=1e-12)
+    return S, p
+
+
+@pytest.fixture(scope="module")
+def mid():
+    n, seed = 6000, 2002
+    pts = synth.gaussian_mixture(n=n, d=64, k=50, seed=seed)
+    prep = oracle.prepare(oracle.similarity(pts.X), "median", seed=seed)
+    return n, seed, pts, prep
+
+
+def test_mid_messages_after_100(mid):
+    n, seed, pts, prep = mid
+    print(f"c2-family n={n} 100 iterations", flush=True)
+    _, p = gpu_S(pts, seed)
+    rng = prep.S.max() - prep.S.min()
+    assert abs(p - prep.pref) <= 1e-6 * rng
+    S = apx.to_matrix(torch.from_numpy(prep.S.astype(np.float32)))
+    R, A = apx.empty_matrix(n, fill=0.0), apx.empty_matrix(n, fill=0.0)
+    apx.ap_iterate(S, R, A, 0.9, 100)
+    ref = oracle.ap(prep.S, 0.9, 100, 0)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(host(R) - ref.R)) <= TOL * rng
+    assert np.max(np.abs(host(A) - ref.A)) <= TOL * rng
+
+
+def test_mid_converged_exemplars(mid):
+    n, seed, pts, prep = mid
+    print(f"c2-family n={n} to convergence", flush=True)
+    S, _ = gpu_S(pts, seed)
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    idx, res = apx.ap_solve(S, R, A, 0.9, 2000, 15)
+    ref = oracle.ap(prep.S, 0.9, 2000, 15)
+    assert ref.converged and res.converged
+    assert res.iterations == ref.iterations
+    assert np.array_equal(idx.cpu().numpy(), ref.idx)
+    rng = prep.S.max() - prep.S.min()
+    assert abs(res.netsim - ref.netsim) <= n * 1e-6 * rng
+
+
+@pytest.fixture(scope="module")
+def full():
+    n, seed = 20000, 2001
+    pts = synth.gaussian_mixture(n=n, d=64, k=50, seed=seed)
+    S, p = gpu_S(pts, seed)
+    return n, seed, pts, S
+
+
+def test_full_size_rows_of_one_iteration(full):
+    n, seed, pts, S = full
+    print(f"c2 n={n}: sampled rows of iteration 31", flush=True)
+    R, A = apx.empty_matrix(n, fill=0.0), apx.empty_matrix(n, fill=0.0)
+    apx.ap_iterate(S, R, A, 0.9, 30)
+    Rt, At = host(R), host(A)
+    apx.ap_iterate(S, R, A, 0.9, 1)
+    Sh = host(S)
+    R1, A1 = host(R), host(A)
+    rng = Sh.max() - Sh.min()
+    rows = np.random.default_rng(7).choice(n, size=64, replace=False)
+    ref_R = oracle.resp_rows(Sh, At, Rt, 0.9, rows)
+    assert np.max(np.abs(R1[rows] - ref_R)) <= 1e-5 * rng
+    ref_A = oracle.avail_rows(R1, At, 0.9, rows)
+    assert np.max(np.abs(A1[rows] - ref_A)) <= 1e-5 * rng
+
+
+def test_full_size_solve_valid_and_deterministic(full):
+    n, seed, pts, S = full
+    print(f"c2 n={n}: solve twice", flush=True)
+    runs = []
+    for _ in range(2):
+        R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+        idx, res = apx.ap_solve(S, R, A, 0.9, 2000, 15)
+        runs.append((R, A, idx, res))
+    (R0, A0, i0, r0), (R1, A1, i1, r1) = runs
+    assert r0.iterations == r1.iterations and r0.netsim == r1.netsim
+    assert torch.equal(i0, i1) and torch.equal(R0, R1) and torch.equal(A0, A1)
+    assert r0.converged
+    Sh = host(S)
+    lab = i0.cpu().numpy()
+    ex = np.flatnonzero(lab == np.arange(n))
+    assert ex.size == r0.n_exemplars > 0
+    # labels: the exemplar of largest similarity (lowest index on ties)
+    rows = np.random.default_rng(3).choice(n, size=500, replace=False)
+    for i in rows:
+        if lab[i] == i:
+            continue
+        v = Sh[i, ex]
+        assert lab[i] == ex[np.argmax(v)]
+    dp = sum(Sh[i, lab[i]] for i in range(n) if lab[i] != i)
+    ep = float(np.sum(np.diag(Sh)[ex]))
+    assert abs(dp - r0.dpsim) <= 1e-9 * abs(dp) + 1e-6
+    assert abs(ep - r0.expref) <= 1e-9 * abs(ep) + 1e-6

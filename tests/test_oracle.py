@@ -349,3 +349,15 @@ def test_lap_assignment_is_nearest_exemplar():
     want = ex[np.argmin(D, axis=1)]
     want[ex] = ex
     assert np.array_equal(lr.idx, want)
+
+
+def test_row_pieces_match_full_iteration():
+    """The row-wise oracle pieces reproduce one full iteration exactly."""
+    S = _rand_S(30, 21, asym=True)
+    a = oracle.ap(S, 0.7, 5, 0)
+    b = oracle.ap(S, 0.7, 6, 0)
+    rows = np.array([0, 3, 17, 29])
+    Rn = oracle.resp_rows(S, a.A, a.R, 0.7, np.arange(30))
+    assert np.array_equal(Rn, b.R)
+    An = oracle.avail_rows(b.R, a.A, 0.7, rows)
+    assert np.array_equal(An, b.A[rows])
