@@ -145,6 +145,46 @@ apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float
 apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
                     int32_t warm, const apx_params *params, int32_t *idx, apx_result *res);
 
+/* One instance of a batched solve: its own S (preferences on the diagonal),
+ * R, A (device, FP32, ld >= n, ld % 4 == 0) and labels idx (device, n). */
+typedef struct {
+    int64_t n;
+    int64_t ld;
+    const float *S;
+    float *R;
+    float *A;
+    int32_t *idx;
+} apx_instance;
+
+/*
+ * ap_solve_batched -- Algorithm 1 on `count` independent instances of uneven
+ * size (inst: host array) in one launch per half-iteration: a ragged table of
+ * row blocks covers every instance, each instance keeps its own stop rule and
+ * stops independently.  Per instance the arithmetic is that of ap_solve;
+ * only the grouping of the FP32 column partial sums differs (rows are split
+ * into blocks differently), so results agree with ap_solve to rounding.
+ * The results are deterministic.  res (host, count).  Instances need
+ * 2 <= n <= 12288.  Synchronises.
+ */
+apx_status ap_solve_batched(apx_ctx *ctx, int32_t count, const apx_instance *inst, int32_t warm,
+                            const apx_params *params, apx_result *res);
+
+/*
+ * pap_solve -- partition affinity propagation (Section 3, Algorithm 2).
+ * Step 1: the points are split into k parts; part j holds the points
+ * perm[offsets[j] .. offsets[j+1]-1] (perm: host, n entries, a permutation;
+ * NULL = identity; offsets: host, k+1 entries from 0 to n; NULL = the
+ * paper's split into k-1 parts of floor(n/k) points and a last part of the
+ * rest).  Step 2: AP on every diagonal block S_jj (with its diagonal, i.e.
+ * the global preferences), all blocks in one batch.  Step 3: A' holds each
+ * A_jj at its points' positions and zeros elsewhere.  Step 4: AP on S from
+ * A' with R_0 = 0.  Outputs as ap_solve; sub (host, k, nullable) receives
+ * the per-part results of Step 2.  Needs 1 <= k <= n.  Synchronises.
+ */
+apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                     int32_t k, const int64_t *perm, const int64_t *offsets,
+                     const apx_params *params, int32_t *idx, apx_result *res, apx_result *sub);
+
 #ifdef __cplusplus
 }
 #endif

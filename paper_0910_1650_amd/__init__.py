@@ -43,6 +43,11 @@ class apx_result(ctypes.Structure):
                 ("netsim", ctypes.c_double)]
 
 
+class apx_instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("S", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("A", ctypes.c_void_p), ("idx", ctypes.c_void_p)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -62,6 +67,10 @@ SIGNATURES = {
     "ap_iterate": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, ctypes.c_float, _I32, _P]),
     "ap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, ctypes.POINTER(apx_params), _P,
                                 ctypes.POINTER(apx_result)]),
+    "ap_solve_batched": (ctypes.c_int, [_P, _I32, ctypes.POINTER(apx_instance), _I32,
+                                        ctypes.POINTER(apx_params), ctypes.POINTER(apx_result)]),
+    "pap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, _P, _P, ctypes.POINTER(apx_params),
+                                 _P, ctypes.POINTER(apx_result), ctypes.POINTER(apx_result)]),
 }
 
 
@@ -226,3 +235,50 @@ def apx_profile_read(device=None) -> tuple[int, float]:
     n, ms = _I64(0), ctypes.c_double(0.0)
     _check(ctx, lib().apx_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms)), "apx_profile_read")
     return int(n.value), float(ms.value)
+
+
+def ap_solve_batched(S_list, R_list=None, A_list=None, damping: float = 0.5, max_iter: int = 200,
+                     conv_iter: int = 15, warm: int = APX_COLD, check_every: int = 0):
+    """Algorithm 1 on many instances in one batch; returns ([idx tensors], [Result])."""
+    count = len(S_list)
+    R_list = R_list or [empty_matrix(S.shape[0], device=S.device) for S in S_list]
+    A_list = A_list or [empty_matrix(S.shape[0], device=S.device) for S in S_list]
+    insts = (apx_instance * count)()
+    idxs = []
+    for j, (S, R, A) in enumerate(zip(S_list, R_list, A_list)):
+        Sp, n, ld = _mat(S, f"S[{j}]")
+        Rp, _, ldr = _mat(R, f"R[{j}]", n)
+        Ap, _, lda = _mat(A, f"A[{j}]", n)
+        if not (ld == ldr == lda):
+            raise ValueError("S, R and A of an instance must share one leading dimension")
+        idx = torch.empty(n, dtype=torch.int32, device=S.device)
+        idxs.append(idx)
+        insts[j] = apx_instance(n, ld, Sp, Rp, Ap, _P(idx.data_ptr()))
+    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    res = (apx_result * count)()
+    ctx = context(S_list[0].device)
+    _check(ctx, lib().ap_solve_batched(ctx, count, insts, warm, ctypes.byref(prm), res), "ap_solve_batched")
+    return idxs, [_res(r) for r in res]
+
+
+def pap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, k: int, perm=None, offsets=None,
+              damping: float = 0.5, max_iter: int = 200, conv_iter: int = 15, check_every: int = 0):
+    """Partition AP (Algorithm 2); returns (idx, Result, [Result per part])."""
+    import numpy as np
+    Sp, n, ld = _mat(S, "S")
+    Rp, _, ldr = _mat(R, "R", n)
+    Ap, _, lda = _mat(A, "A", n)
+    if not (ld == ldr == lda):
+        raise ValueError("S, R and A must share one leading dimension")
+    pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    of = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = torch.empty(n, dtype=torch.int32, device=S.device)
+    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    res = apx_result()
+    sub = (apx_result * k)()
+    ctx = context(S.device)
+    _check(ctx, lib().pap_solve(ctx, Sp, n, ld, Rp, Ap, k,
+                                None if pm is None else _P(pm.ctypes.data),
+                                None if of is None else _P(of.ctypes.data),
+                                ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res), sub), "pap_solve")
+    return idx, _res(res), [_res(r) for r in sub]

@@ -101,37 +101,49 @@ struct IterWs {
     double *contrib, *sums;
 };
 
-apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const PassPlan &pl, IterWs &w) {
+struct IterLayout {
+    size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, bytes;
+};
+
+IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
+    IterLayout o{};
     WsLayout L;
     const int64_t ldp = round4(n);
-    size_t o_t = L.take(sizeof(float) * ldp);
-    size_t o_c = L.take(sizeof(float) * ldp);
-    size_t o_d = L.take(sizeof(float) * ldp);
-    size_t o_p = L.take(sizeof(float) * ldp * (size_t)pl.grid);
-    size_t o_dec = L.take(sizeof(int32_t) * n);
-    size_t o_e = L.take((size_t)n);
-    size_t o_st = L.take(sizeof(ApState));
-    size_t o_ex = L.take(sizeof(int32_t) * n);
-    size_t o_nex = L.take(sizeof(int32_t));
-    size_t o_con = L.take(sizeof(double) * 2 * (size_t)n);
-    size_t o_sum = L.take(sizeof(double) * 2);
-    size_t o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
-    APX_TRY(ws_reserve(ctx, L.off));
-    char *b = static_cast<char *>(ctx->ws);
-    w.tcol = reinterpret_cast<float *>(b + o_t);
-    w.ccol = reinterpret_cast<float *>(b + o_c);
-    w.rdiag = reinterpret_cast<float *>(b + o_d);
-    w.partial = reinterpret_cast<float *>(b + o_p);
-    w.ldp = ldp;
+    o.o_t = L.take(sizeof(float) * ldp);
+    o.o_c = L.take(sizeof(float) * ldp);
+    o.o_d = L.take(sizeof(float) * ldp);
+    o.o_p = L.take(sizeof(float) * ldp * (size_t)grid);
+    o.o_dec = L.take(sizeof(int32_t) * n);
+    o.o_e = L.take((size_t)n);
+    o.o_st = L.take(sizeof(ApState));
+    o.o_ex = L.take(sizeof(int32_t) * n);
+    o.o_nex = L.take(sizeof(int32_t));
+    o.o_con = L.take(sizeof(double) * 2 * (size_t)n);
+    o.o_sum = L.take(sizeof(double) * 2);
+    o.o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
+    o.bytes = L.off;
+    return o;
+}
+
+// Workspace of one AP run on an n x n problem, carved from ctx->ws_base.
+apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const PassPlan &pl, IterWs &w) {
+    const IterLayout o = iter_layout(n, ld, second_r, pl.grid);
+    APX_TRY(ws_reserve(ctx, ctx->ws_base + o.bytes));
+    char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
+    w.tcol = reinterpret_cast<float *>(b + o.o_t);
+    w.ccol = reinterpret_cast<float *>(b + o.o_c);
+    w.rdiag = reinterpret_cast<float *>(b + o.o_d);
+    w.partial = reinterpret_cast<float *>(b + o.o_p);
+    w.ldp = round4(n);
     w.nparts = pl.grid;
-    w.dec = reinterpret_cast<int32_t *>(b + o_dec);
-    w.eflag = reinterpret_cast<uint8_t *>(b + o_e);
-    w.st = reinterpret_cast<ApState *>(b + o_st);
-    w.ex = reinterpret_cast<int32_t *>(b + o_ex);
-    w.nex = reinterpret_cast<int32_t *>(b + o_nex);
-    w.contrib = reinterpret_cast<double *>(b + o_con);
-    w.sums = reinterpret_cast<double *>(b + o_sum);
-    w.R2 = second_r ? reinterpret_cast<float *>(b + o_r2) : nullptr;
+    w.dec = reinterpret_cast<int32_t *>(b + o.o_dec);
+    w.eflag = reinterpret_cast<uint8_t *>(b + o.o_e);
+    w.st = reinterpret_cast<ApState *>(b + o.o_st);
+    w.ex = reinterpret_cast<int32_t *>(b + o.o_ex);
+    w.nex = reinterpret_cast<int32_t *>(b + o.o_nex);
+    w.contrib = reinterpret_cast<double *>(b + o.o_con);
+    w.sums = reinterpret_cast<double *>(b + o.o_sum);
+    w.R2 = second_r ? reinterpret_cast<float *>(b + o.o_r2) : nullptr;
     return APX_OK;
 }
 
@@ -173,6 +185,13 @@ ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep) {
 }
 
 }  // namespace
+
+namespace apx {
+size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus) {
+    const PassPlan pl = plan_pass(n, num_cus);
+    return iter_layout(n, ld, true, pl.grid).bytes;
+}
+}  // namespace apx
 
 extern "C" {
 

@@ -110,6 +110,7 @@ struct apx_ctx {
     std::string err;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    size_t ws_base = 0;       // start of the slice handed to the running solver
     void *pinned = nullptr;   // small pinned host buffer for state read-back
     // benchmark timing of full row passes (apx_profile)
     bool prof = false;
@@ -130,7 +131,22 @@ struct WsLayout {
     }
 };
 
+// Grow the workspace to at least `bytes` (contents are lost when it grows:
+// callers that keep data in [0, ws_base) reserve the total first).
 apx_status ws_reserve(apx_ctx *ctx, size_t bytes);
+
+// One instance of a batched solve (device pointers; ld >= n, ld % 4 == 0).
+struct BatchSpec {
+    int64_t n, ld;
+    const float *S;
+    float *R, *A;
+    int32_t *idx;
+};
+size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus);
+apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int32_t warm,
+                         const apx_params *params, apx_result *res);
+// Single-instance solve on the workspace slice starting at ctx->ws_base.
+size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus);
 apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
 apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what);
 

@@ -342,9 +342,9 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     size_t o_sel = L.take(sizeof(SelState));
     size_t o_h = L.take(sizeof(unsigned long long) * 2 * 2048);
     size_t o_r = L.take(sizeof(double) * 2);
-    apx_status st = ws_reserve(ctx, L.off);
+    apx_status st = ws_reserve(ctx, ctx->ws_base + L.off);
     if (st != APX_OK) return st;
-    char *b = static_cast<char *>(ctx->ws);
+    char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
     float *nrm = reinterpret_cast<float *>(b + o_n);
     uint32_t *mm = reinterpret_cast<uint32_t *>(b + o_mm);
     SelState *sel = reinterpret_cast<SelState *>(b + o_sel);
