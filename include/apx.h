@@ -185,6 +185,27 @@ apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float 
                      int32_t k, const int64_t *perm, const int64_t *offsets,
                      const apx_params *params, int32_t *idx, apx_result *res, apx_result *sub);
 
+/*
+ * lap_solve -- landmark affinity propagation (Section 4, Algorithm 3, Steps
+ * 1-2 without the per-class distance threshold).  Step 1: the landmark set M
+ * (host array `landmarks` of n_landmarks distinct indices, or NULL to draw a
+ * uniform sample without replacement from a SplitMix64 stream seeded with
+ * `seed`) gets its similarity matrix (ap_similarity: median preference, tie
+ * noise noise_rel from `seed`) and AP with `params`.  Step 2: every point
+ * goes to the exemplar of least squared Euclidean distance (exact: FP32
+ * distances with an FP64 recheck of every candidate within the FP32 error
+ * bound; lowest exemplar index on ties); exemplars label themselves.  The
+ * n x n similarity matrix is never formed.  X: device n x d (ldx).  idx:
+ * device, n global labels.  res: iterations/converged of the landmark AP,
+ * |E|, dpsim = -sum of squared distances of non-exemplars to their exemplar
+ * (FP64), expref = |E| * landmark preference, netsim.  exemplars_out (host,
+ * nullable, capacity n_landmarks) receives the exemplar indices ascending.
+ * Needs 2 <= n_landmarks <= n, d <= 4096.  Synchronises.
+ */
+apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
+                     int64_t n_landmarks, const int64_t *landmarks, uint64_t seed, double noise_rel,
+                     const apx_params *params, int32_t *idx, apx_result *res, int64_t *exemplars_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -299,9 +299,10 @@ class LAPResult:
 def lap(X: np.ndarray, landmarks: np.ndarray, seed: int = 0, lam: float = 0.9,
         max_iter: int = 2000, conv_iter: int = 15, noise_rel: float = 1e-12) -> LAPResult:
     """AP on the landmark points (median preference, tie noise), then every
-    point goes to its nearest exemplar by FP64 squared distance."""
+    point goes to its nearest exemplar by FP64 squared distance.  The
+    landmark matrix lists the landmarks in ascending point index."""
     X = np.ascontiguousarray(X, dtype=np.float32)
-    M = np.asarray(landmarks, dtype=np.int64)
+    M = np.sort(np.asarray(landmarks, dtype=np.int64))
     XM = np.ascontiguousarray(X[M])
     prep = prepare(similarity(XM), "median", seed, noise_rel)
     res = ap(prep.S, lam, max_iter, conv_iter)

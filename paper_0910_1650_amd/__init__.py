@@ -71,6 +71,8 @@ SIGNATURES = {
                                         ctypes.POINTER(apx_params), ctypes.POINTER(apx_result)]),
     "pap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, _P, _P, ctypes.POINTER(apx_params),
                                  _P, ctypes.POINTER(apx_result), ctypes.POINTER(apx_result)]),
+    "lap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
+                                 ctypes.POINTER(apx_params), _P, ctypes.POINTER(apx_result), _P]),
 }
 
 
@@ -282,3 +284,26 @@ def pap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, k: int, perm=No
                                 None if of is None else _P(of.ctypes.data),
                                 ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res), sub), "pap_solve")
     return idx, _res(res), [_res(r) for r in sub]
+
+
+def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, noise_rel: float = 1e-12,
+              damping: float = 0.9, max_iter: int = 2000, conv_iter: int = 15, check_every: int = 0):
+    """Landmark AP (Algorithm 3, Steps 1-2); returns (idx, Result, exemplar indices)."""
+    import numpy as np
+    if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
+        raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
+    n, d = X.shape
+    lm = None if landmarks is None else np.ascontiguousarray(landmarks, dtype=np.int64)
+    if lm is not None and lm.size != n_landmarks:
+        raise ValueError(f"landmarks has {lm.size} entries, expected {n_landmarks}")
+    idx = torch.empty(n, dtype=torch.int32, device=X.device)
+    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    res = apx_result()
+    ex = np.zeros(n_landmarks, dtype=np.int64)
+    ctx = context(X.device)
+    _check(ctx, lib().lap_solve(ctx, _P(X.data_ptr()), n, d, X.stride(0), n_landmarks,
+                                None if lm is None else _P(lm.ctypes.data), seed, noise_rel,
+                                ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res),
+                                _P(ex.ctypes.data)), "lap_solve")
+    r = _res(res)
+    return idx, r, ex[: r.n_exemplars].copy()

@@ -22,7 +22,7 @@ def declared_functions():
 
 def test_header_declares_entry_points():
     names = declared_functions()
-    for want in ("ap_similarity", "ap_iterate", "ap_solve", "ap_solve_batched", "pap_solve",
+    for want in ("ap_similarity", "ap_iterate", "ap_solve", "ap_solve_batched", "pap_solve", "lap_solve",
                  "apx_create", "apx_destroy"):
         assert want in names, want
 
