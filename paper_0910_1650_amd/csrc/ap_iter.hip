@@ -97,12 +97,19 @@ __device__ __forceinline__ void st4(float *p, const float4 &v) { *reinterpret_ca
 // gave run-to-run differences in this kernel on gfx950 for rows longer than
 // ~12k elements, while global memory operations are exact and reproducible.
 typedef const float *rsrc_t;
+typedef float v4f __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ rsrc_t row_rsrc(const float *base, int64_t) { return base; }
+// S, R and A are streamed once per iteration and never re-read in the same
+// pass: loads and stores carry the nontemporal hint.
 __device__ __forceinline__ float4 bld4(rsrc_t r, int voff, int soff) {
-    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(r) + voff + soff);
+    const v4f v = __builtin_nontemporal_load(
+        reinterpret_cast<const v4f *>(reinterpret_cast<const char *>(r) + voff + soff));
+    return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void bst4(rsrc_t r, int voff, int soff, const float4 &x) {
-    *reinterpret_cast<float4 *>(const_cast<char *>(reinterpret_cast<const char *>(r)) + voff + soff) = x;
+    const v4f v = {x.x, x.y, x.z, x.w};
+    __builtin_nontemporal_store(
+        v, reinterpret_cast<v4f *>(const_cast<char *>(reinterpret_cast<const char *>(r)) + voff + soff));
 }
 
 // ---- per-chunk pieces of the row pass ------------------------------------
@@ -518,15 +525,24 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
     }
 }
 
-__global__ void k_col_reduce(ColArgs a) {
+// Column sums: 64 columns per workgroup, 16 slices of the partial rows per
+// column summed in FP64, slices combined in a fixed order.
+__global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
     if (a.st != nullptr && a.st->frozen) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < a.n) {
-        double c = 0.0;
-        const float *P = a.partial + k;
-        for (int g = 0; g < a.nparts; ++g) c += (double)P[(int64_t)g * a.ldp];
-        a.tcol[k] = (float)((double)a.rdiag[k] + c);
-        a.ccol[k] = (float)c;
+    __shared__ double part[16][64];
+    const int cx = threadIdx.x & 63, gs = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + cx;
+    double c = 0.0;
+    if (k < a.n)
+        for (int g = gs; g < a.nparts; g += 16) c += (double)a.partial[(int64_t)g * a.ldp + k];
+    part[gs][cx] = c;
+    __syncthreads();
+    if (gs == 0 && k < a.n) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) tot += part[q][cx];
+        a.tcol[k] = (float)((double)a.rdiag[k] + tot);
+        a.ccol[k] = (float)tot;
     }
     if (a.bookkeep && a.st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
         ApState *st = a.st;
@@ -762,9 +778,8 @@ hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipS
 }
 
 hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s) {
-    const int threads = 256;
-    const int grid = (a.n + threads - 1) / threads;
-    k_col_reduce<<<grid, threads, 0, s>>>(a);
+    const int grid = (a.n + 63) / 64;
+    k_col_reduce<<<grid, 1024, 0, s>>>(a);
     return hipGetLastError();
 }
 
