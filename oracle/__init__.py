@@ -9,6 +9,8 @@ this wrapper marshals numpy arrays and composes the paper's algorithms:
 * Algorithm 1 (affinity propagation), Section 2, Eqs. (1)-(4)
 * Algorithm 2 (partition AP), Section 3
 * Algorithm 3 (landmark AP) Steps 1-2 with the nearest-exemplar rule, Section 4
+* the learned warm start (features, network, targets, A_0) in ``warm.py``,
+  a definition of this project's own: the paper has no learned part
 
 Readings of the paper that the oracle fixes (all listed in the design doc):
 R_0 = 0; R is updated and damped before A, and A uses the damped R; damping

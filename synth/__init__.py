@@ -116,3 +116,37 @@ def batch_instances(count: int = 512, n_lo: int = 100, n_hi: int = 2000,
         k = int(rng.integers(k_lo, k_hi + 1))
         out.append(gaussian_2d(n=n, k=k, seed=seed0 + j))
     return out
+
+
+# --------------------------------------------------------------------------
+# Inputs for the warm-start network (parameters, feature batches)
+# --------------------------------------------------------------------------
+MLP_SHAPES = ((16, 128), (128,), (128, 128), (128,), (128, 2), (2,))
+
+
+def mlp_params(seed: int, bias_std: float = 0.1) -> np.ndarray:
+    """Flat FP32 parameter vector (W1, b1, W2, b2, W3, b3, row-major): weights
+    uniform in +-1/sqrt(fan_in), biases N(0, bias_std^2)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            b = 1.0 / np.sqrt(shape[0])
+            parts.append(rng.uniform(-b, b, size=shape).ravel())
+        else:
+            parts.append(rng.normal(0.0, bias_std, size=shape))
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
+
+
+def mlp_batch(count: int, seed: int):
+    """Feature-like inputs (count x 16), targets (count x 2) and point weights
+    summing to 1, all FP32."""
+    rng = np.random.default_rng(seed)
+    F = rng.normal(0.0, 1.5, size=(count, 16))
+    F[:, :12] = -np.abs(F[:, :12])          # similarities are mostly negative
+    F[:, 14] = rng.uniform(0.0, 1.0, count)
+    F[:, 15] = rng.uniform(0.6, 1.1, count)
+    T = rng.normal(0.0, 2.0, size=(count, 2))
+    w = rng.uniform(0.5, 1.5, count)
+    w /= w.sum()
+    return _f32(F), _f32(T), _f32(w)
