@@ -7,6 +7,8 @@
  *                           exemplar decision, stop rules)
  *   Section 3, Algorithm 2  partition affinity propagation (PAP)
  *   Section 4, Algorithm 3  landmark affinity propagation (LAP), Steps 1-2
+ * plus a learned warm start that is this library's own addition (the paper
+ * starts from zero availabilities, Eq. (1), or from PAP's merge).
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -205,6 +207,86 @@ apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float 
 apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
                      int64_t n_landmarks, const int64_t *landmarks, uint64_t seed, double noise_rel,
                      const apx_params *params, int32_t *idx, apx_result *res, int64_t *exemplars_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  The paper starts Algorithm 1 from a(i,k) = 0 (Eq. (1))
+ * and warm-starts only through PAP's merged availabilities (Section 3,
+ * Algorithm 2, steps 3-4).  These calls predict the starting messages per
+ * point from its row of S with a small network instead; none of it is in the
+ * paper.  All pointers are DEVICE pointers; all calls are stream-ordered and
+ * do not synchronise (except when the context workspace has to grow).
+ * ------------------------------------------------------------------------- */
+
+/* Network 16 -> 128 -> 128 -> 2 (GELU after each hidden layer).  Parameters
+ * are one flat FP32 vector of APX_MLP_PARAMS values: W1 [16][128], b1 [128],
+ * W2 [128][128], b2 [128], W3 [128][2], b3 [2], each row-major, in that
+ * order; layer l computes z = h W_l + b_l.  The forward pass rounds the
+ * features, W1..W3 and both hidden activations to bfloat16 (nearest even)
+ * and accumulates in FP32 on the matrix cores; biases stay FP32. */
+#define APX_MLP_FEATURES 16
+#define APX_MLP_PARAMS 18946
+
+/*
+ * apx_features -- 16 features per point from S (n >= 2, preferences on the
+ * diagonal), written to F (n x 16, row-major, 16-byte aligned), and the scale
+ * sigma (one float) they are divided by.  With o_0 <= ... <= o_{m-1} the
+ * m = n-1 off-diagonal values of row k and mu_k = o_{floor((m-1)/2)}:
+ *   sigma    |lower median of mu_0..mu_{n-1}| (1 if that is 0 or not finite)
+ *   f0..f5   o_{m-1-min(j,m-1)}/sigma, j = 0,1,3,7,15,31 (1st..32nd largest)
+ *   f6       mean of the min(32,m) largest / sigma
+ *   f7..f11  o_{floor(q(m-1)/100)}/sigma, q = 1,10,25,50,75
+ *   f12      (s(k,k) - mu_k)/sigma         f13  (s(k,k) - f6 sigma)/sigma
+ *   f14      #{j != k : s(k,j) > s(k,k)} / m      f15  ln(n)/10
+ * Order statistics are exact; each feature is formed in FP64 and rounded to
+ * FP32 once.
+ */
+apx_status apx_features(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *F, float *sigma);
+
+/* apx_mlp_forward -- Y (count x 2) = network(theta, F (count x 16, 16-byte
+ * aligned)). */
+apx_status apx_mlp_forward(apx_ctx *ctx, const float *theta, const float *F, int64_t count, float *Y);
+
+/*
+ * apx_mlp_backward -- gradient of the loss
+ *   L = sum_p w_p sum_o huber(y_po - T_po),  huber(e) = e^2/2 (|e| <= 1), |e| - 1/2,
+ * with respect to the FP32 parameters, over the batch of `count` points
+ * rows[0..count-1] of F (x 16), T (x 2) and w (rows: device int64, nullable =
+ * points 0..count-1).  The bfloat16 roundings of the forward pass are treated
+ * as the identity.  grad (APX_MLP_PARAMS floats) is overwritten; loss
+ * (nullable, one double) receives L.  Reductions have a fixed order, so the
+ * result is deterministic.
+ */
+apx_status apx_mlp_backward(apx_ctx *ctx, const float *theta, const float *F, const float *T,
+                            const float *w, const int64_t *rows, int64_t count, float *grad,
+                            double *loss);
+
+/* apx_mlp_adam -- one Adam step (Kingma and Ba, 2015) on theta with moment
+ * buffers m, v (all count floats) and bias correction for step >= 1:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * theta -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps). */
+apx_status apx_mlp_adam(apx_ctx *ctx, float *theta, float *m, float *v, const float *grad,
+                        int64_t count, int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* apx_targets -- training targets from converged responsibilities R: with
+ * c_k = sum_{i != k} max(0, r(i,k)) and t_k = r(k,k) + c_k (the column
+ * quantities of Eqs. (3)-(4), summed in FP64), Y[k] = (t_k/sigma, c_k/sigma)
+ * (n x 2); sigma is a device float (as written by apx_features). */
+apx_status apx_targets(apx_ctx *ctx, const float *R, int64_t n, int64_t ld, const float *sigma, float *Y);
+
+/* apx_warm_a0 -- A_0 from per-point predictions Y (n x 2): a(i,k) =
+ * min(0, sigma Y[k][0]) for i != k, a(k,k) = max(0, sigma Y[k][1]) (FP32
+ * products), i.e. Eqs. (3)-(4) with the predicted column quantities. */
+apx_status apx_warm_a0(apx_ctx *ctx, const float *Y, const float *sigma, int64_t n, float *A, int64_t ld);
+
+/*
+ * ap_warmstart -- starting messages for ap_solve(..., APX_WARM_AR, ...):
+ * features of S, the network with parameters theta, A_0 as apx_warm_a0, and
+ * R_0 = the undamped responsibility update of Eq. (2) from A_0,
+ * r(i,k) = s(i,k) - max_{k' != k} (a_0(i,k') + s(i,k')).  Overwrites R and A.
+ * sigma (device, nullable) receives the feature scale.  Needs 2 <= n <= 65536.
+ */
+apx_status ap_warmstart(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, const float *theta,
+                        float *R, float *A, float *sigma);
 
 #ifdef __cplusplus
 }

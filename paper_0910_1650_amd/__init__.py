@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libapx.so")
 APX_OK, APX_EINVAL, APX_ENOMEM, APX_EDEVICE, APX_ENOTIMPL = range(5)
 APX_PREF_MEDIAN, APX_PREF_SCALAR, APX_PREF_VECTOR = range(3)
 APX_COLD, APX_WARM_A, APX_WARM_AR = range(3)
+APX_MLP_FEATURES, APX_MLP_PARAMS = 16, 18946
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTIMPL"}
 
 
@@ -73,6 +74,14 @@ SIGNATURES = {
                                  _P, ctypes.POINTER(apx_result), ctypes.POINTER(apx_result)]),
     "lap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
                                  ctypes.POINTER(apx_params), _P, ctypes.POINTER(apx_result), _P]),
+    "apx_features": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P]),
+    "apx_mlp_forward": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
+    "apx_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P, _P]),
+    "apx_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float]),
+    "apx_targets": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P]),
+    "apx_warm_a0": (ctypes.c_int, [_P, _P, _P, _I64, _P, _I64]),
+    "ap_warmstart": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _P, _P]),
 }
 
 
@@ -307,3 +316,102 @@ def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, 
                                 _P(ex.ctypes.data)), "lap_solve")
     r = _res(res)
     return idx, r, ex[: r.n_exemplars].copy()
+
+
+# --------------------------------------------------------------------------
+# Learned warm start
+# --------------------------------------------------------------------------
+def _vec(t: torch.Tensor, name: str, numel: int | None = None, dtype=torch.float32):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return _P(t.data_ptr())
+
+
+def apx_features(S: torch.Tensor, F: torch.Tensor | None = None, sigma: torch.Tensor | None = None):
+    """Per-point features (n, 16) of S and the scale sigma (1-element tensor)."""
+    Sp, n, ld = _mat(S, "S")
+    if F is None:
+        F = torch.empty((n, APX_MLP_FEATURES), dtype=torch.float32, device=S.device)
+    if sigma is None:
+        sigma = torch.empty(1, dtype=torch.float32, device=S.device)
+    ctx = context(S.device)
+    _check(ctx, lib().apx_features(ctx, Sp, n, ld, _vec(F, "F", n * APX_MLP_FEATURES),
+                                   _vec(sigma, "sigma", 1)), "apx_features")
+    return F, sigma
+
+
+def apx_mlp_forward(theta: torch.Tensor, F: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
+    """Network outputs (count, 2) for features F (count, 16)."""
+    count = F.shape[0]
+    if Y is None:
+        Y = torch.empty((count, 2), dtype=torch.float32, device=F.device)
+    ctx = context(F.device)
+    _check(ctx, lib().apx_mlp_forward(ctx, _vec(theta, "theta", APX_MLP_PARAMS),
+                                      _vec(F, "F", count * APX_MLP_FEATURES), count,
+                                      _vec(Y, "Y", count * 2)), "apx_mlp_forward")
+    return Y
+
+
+def apx_mlp_backward(theta, F, T, w, rows: torch.Tensor | None = None, grad=None, loss=None):
+    """Gradient of the weighted Huber loss over the batch; returns (grad, loss tensor)."""
+    total = F.shape[0]
+    count = total if rows is None else rows.numel()
+    if grad is None:
+        grad = torch.empty(APX_MLP_PARAMS, dtype=torch.float32, device=F.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=F.device)
+    rp = None if rows is None else _vec(rows, "rows", dtype=torch.int64)
+    ctx = context(F.device)
+    _check(ctx, lib().apx_mlp_backward(ctx, _vec(theta, "theta", APX_MLP_PARAMS),
+                                       _vec(F, "F", total * APX_MLP_FEATURES), _vec(T, "T", total * 2),
+                                       _vec(w, "w", total), rp, count, _vec(grad, "grad", APX_MLP_PARAMS),
+                                       _vec(loss, "loss", 1, torch.float64)), "apx_mlp_backward")
+    return grad, loss
+
+
+def apx_mlp_adam(theta, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8) -> None:
+    """One Adam step on theta in place (moments m, v updated in place)."""
+    count = theta.numel()
+    ctx = context(theta.device)
+    _check(ctx, lib().apx_mlp_adam(ctx, _vec(theta, "theta"), _vec(m, "m", count), _vec(v, "v", count),
+                                   _vec(grad, "grad", count), count, step, lr, beta1, beta2, eps),
+           "apx_mlp_adam")
+
+
+def apx_targets(R: torch.Tensor, sigma: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
+    """Training targets (n, 2) = (t_k, c_k) / sigma from converged responsibilities."""
+    Rp, n, ld = _mat(R, "R")
+    if Y is None:
+        Y = torch.empty((n, 2), dtype=torch.float32, device=R.device)
+    ctx = context(R.device)
+    _check(ctx, lib().apx_targets(ctx, Rp, n, ld, _vec(sigma, "sigma", 1), _vec(Y, "Y", n * 2)),
+           "apx_targets")
+    return Y
+
+
+def apx_warm_a0(Y: torch.Tensor, sigma: torch.Tensor, A: torch.Tensor) -> torch.Tensor:
+    """A_0 from predictions Y (n, 2) into A."""
+    Ap, n, ld = _mat(A, "A")
+    ctx = context(A.device)
+    _check(ctx, lib().apx_warm_a0(ctx, _vec(Y, "Y", n * 2), _vec(sigma, "sigma", 1), n, Ap, ld),
+           "apx_warm_a0")
+    return A
+
+
+def ap_warmstart(S: torch.Tensor, theta: torch.Tensor, R: torch.Tensor, A: torch.Tensor,
+                 sigma: torch.Tensor | None = None):
+    """Predicted (R_0, A_0) for ap_solve(..., warm=APX_WARM_AR); returns sigma."""
+    Sp, n, ld = _mat(S, "S")
+    Rp, _, ldr = _mat(R, "R", n)
+    Ap, _, lda = _mat(A, "A", n)
+    if not (ld == ldr == lda):
+        raise ValueError("S, R and A must share one leading dimension")
+    if sigma is None:
+        sigma = torch.empty(1, dtype=torch.float32, device=S.device)
+    ctx = context(S.device)
+    _check(ctx, lib().ap_warmstart(ctx, Sp, n, ld, _vec(theta, "theta", APX_MLP_PARAMS), Rp, Ap,
+                                   _vec(sigma, "sigma", 1)), "ap_warmstart")
+    return sigma

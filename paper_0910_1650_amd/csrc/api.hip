@@ -191,6 +191,24 @@ size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus) {
     const PassPlan pl = plan_pass(n, num_cus);
     return iter_layout(n, ld, true, pl.grid).bytes;
 }
+
+size_t resp_step_ws_bytes(int64_t n, int64_t ld, int num_cus) {
+    const PassPlan pl = plan_pass(n, num_cus);
+    return iter_layout(n, ld, false, pl.grid).bytes;
+}
+
+apx_status resp_step(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A) {
+    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    IterWs w{};
+    APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
+    hipStream_t s = ctx->stream;
+    // With damping 0 and R = 0 the responsibility pass computes
+    // 0 * 0 + 1 * s(i,k) - 1 * max(...) exactly: the plain update of Eq. (2).
+    HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R = 0");
+    PassArgs pa = pass_args(S, R, R, A, n, ld, 0.0f, w, nullptr, nullptr, nullptr);
+    HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pa, s), "responsibility step");
+    return APX_OK;
+}
 }  // namespace apx
 
 extern "C" {

@@ -147,6 +147,11 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
                          const apx_params *params, apx_result *res);
 // Single-instance solve on the workspace slice starting at ctx->ws_base.
 size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus);
+// R := the undamped responsibility update of Eq. (2) computed from (S, A),
+// i.e. r(i,k) = s(i,k) - max_{k' != k} (a(i,k') + s(i,k')); R's previous
+// contents are not used.  Workspace slice at ctx->ws_base.
+apx_status resp_step(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A);
+size_t resp_step_ws_bytes(int64_t n, int64_t ld, int num_cus);
 apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
 apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what);
 
