@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-warm-compare", action="store_true")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="short fixed sequence for rocprofv3 --pmc runs: 4 AP iterations at N, "
+                         "then a plain 1.6 GB device copy (the calibration kernel); prints no JSON")
     return ap.parse_args()
 
 
@@ -66,6 +69,16 @@ def cpu_baseline(pts, n_iter: int) -> dict:
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_n20000_d64_k50_seed2001.json")
+CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kernel
+
+# HBM bytes moved by one working full row pass at N=20000, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs of `bench.py --counter-run`, each scaled by
+# what the same counter reads for the 1.6 GB copy (profiles/
+# row_pass_n20000_hbm_counters.md).  Valid only for the row-pass source with
+# this SHA-256; otherwise the benchmark reports traffic as null.
+ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
+ROW_PASS_TRAFFIC = {"read": 4802892196, "write": 3224278347,
+                    "sha256": "6e7cfa613ebdbc3199b38e639902a2dc882485ba29fe45b4e4d3bb15bc948900"}
 PAP_K = 8
 
 
@@ -116,8 +129,36 @@ def time_to_exemplars(apx, S, n, pts_seed):
     return out
 
 
+def counter_run(n: int) -> None:
+    import torch
+
+    import paper_0910_1650_amd as apx
+    import synth
+    pts = synth.gaussian_mixture(n=n, d=D, k=K_MIX, seed=SEED)
+    X = torch.from_numpy(pts.X).cuda()
+    S, _ = apx.ap_similarity(X, pref="median", noise_seed=SEED, noise_rel=1e-12)
+    R, A = apx.empty_matrix(n, fill=0.0), apx.empty_matrix(n, fill=0.0)
+    apx.ap_iterate(S, R, A, LAMBDA, 4)      # R-only prologue, 3 full passes, A-only epilogue
+    torch.cuda.synchronize()
+    src = torch.ones(CALIB_ELEMS, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"counter run done: n={n}, copy of {CALIB_ELEMS * 4} bytes x2", file=sys.stderr, flush=True)
+
+
+def source_sha256(rel: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def main():
     args = parse()
+    if args.counter_run:
+        counter_run(args.n)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (a sharded run "
               "would split the rows of S, R and A and all-reduce the column sums each "
@@ -177,6 +218,10 @@ def main():
     avg_pass_ms = pass_ms / max(launches, 1)
     achieved = BYTES_PER_ELEM_ITER * elems / (avg_pass_ms * 1e-3) / 1e9
     r0 = results[-1]
+    traffic = None
+    if (ROW_PASS_TRAFFIC is not None and n == N
+            and source_sha256(ROW_PASS_SRC) == ROW_PASS_TRAFFIC["sha256"]):
+        traffic = round((ROW_PASS_TRAFFIC["read"] + ROW_PASS_TRAFFIC["write"]) / 1e9, 3)
     out = {
         "metric": "dense AP GB/s & iter/s at N=20k; time to oracle exemplars, plain vs warm-start",
         "value": round(gbs, 2),
@@ -202,9 +247,10 @@ def main():
         "similarity_ms": round(sim_ms, 3),
         "roofline": {"bound": "hbm", "kernel": "k_row_pass (full iteration pass)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launches": launches, "avg_launch_ms": round(avg_pass_ms, 4),
-                     "bytes_per_launch": BYTES_PER_ELEM_ITER * elems},
+                     "bytes_per_launch": BYTES_PER_ELEM_ITER * elems,
+                     "traffic_unit": "GB per launch (HBM read + write, counter-measured)"},
     }
     if not args.no_warm_compare:
         print("time to oracle exemplars: cold / PAP / learned ...", file=sys.stderr, flush=True)
