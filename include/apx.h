@@ -75,8 +75,16 @@ const char *apx_last_error(const apx_ctx *ctx);
 /* Bytes of device workspace currently held by the context. */
 size_t apx_workspace_bytes(const apx_ctx *ctx);
 
+/* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP
+ * graph (enable = 1, the default; the environment variable APX_GRAPHS=0
+ * turns it off at context creation) or launch every kernel from the host
+ * (enable = 0).  The graph runs on a private stream of the context, ordered
+ * after the context stream with an event; results are identical either way. */
+apx_status apx_set_graphs(apx_ctx *ctx, int enable);
+
 /* Kernel timing for benchmarks: while enabled, ap_solve brackets every full
- * row pass (the dominant kernel) with HIP events on the context stream and
+ * row pass (the dominant kernel) with HIP events on the context stream (the
+ * passes are then launched from the host, not replayed as a graph) and
  * accumulates the launch count and total duration of the passes that did
  * work.  apx_profile_read returns and clears the totals.  Timing never
  * changes results. */
@@ -90,7 +98,9 @@ typedef struct {
                             non-empty, for conv_iter consecutive iterations;
                             0 = run exactly max_iter iterations */
     int32_t check_every; /* iterations between host polls of the stop flag
-                            (0 = library default); never changes results */
+                            (0 = library default 16; odd values are rounded
+                            up to even, the length of one graph replay);
+                            never changes results */
 } apx_params;
 
 typedef struct {

@@ -62,6 +62,7 @@ SIGNATURES = {
     "apx_last_error": (ctypes.c_char_p, [_P]),
     "apx_workspace_bytes": (ctypes.c_size_t, [_P]),
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "ap_similarity": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _I32, _P, ctypes.c_float,
                                      ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
@@ -232,6 +233,12 @@ def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float =
     _check(ctx, lib().ap_solve(ctx, Sp, n, ld, Rp, Ap, warm, ctypes.byref(prm), _P(idx.data_ptr()),
                                ctypes.byref(res)), "ap_solve")
     return idx, _res(res)
+
+
+def apx_set_graphs(enable: bool, device=None) -> None:
+    """Replay ap_solve's iteration loop as a captured HIP graph (default) or not."""
+    ctx = context(device)
+    _check(ctx, lib().apx_set_graphs(ctx, int(bool(enable))), "apx_set_graphs")
 
 
 def apx_profile(enable: bool, device=None) -> None:

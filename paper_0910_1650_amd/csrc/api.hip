@@ -2,6 +2,7 @@
 // host side of the AP iteration loop (Algorithm 1, Section 2).
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "apx_internal.h"
@@ -186,6 +187,62 @@ ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep) {
 
 }  // namespace
 
+namespace {
+
+// Runs iterations t0 .. t0+chunk-1 of ap_solve as one replay of a captured
+// graph on the context's private stream, ordered after everything already
+// enqueued on ctx->stream, then copies the run state to the host and waits.
+// Returns APX_ENOTIMPL (and leaves nothing enqueued) when the capture itself
+// fails, so that the caller can run the chunk with plain launches.
+apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, const float *S, float *const buf[2], float *A,
+                       int64_t n, int64_t ld, float lam, const IterWs &w, int chunk, int32_t t0,
+                       ApState *hst) {
+    if (!ctx->cap) {
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking), "graph stream");
+        HIP_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "graph event");
+    }
+    uint32_t lam_bits;
+    std::memcpy(&lam_bits, &lam, sizeof lam_bits);
+    const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)(uintptr_t)buf[0], (uint64_t)(uintptr_t)buf[1],
+                              (uint64_t)(uintptr_t)A, (uint64_t)n, (uint64_t)ld, lam_bits, (uint64_t)chunk,
+                              (uint64_t)(t0 & 1), (uint64_t)(uintptr_t)w.st, (uint64_t)(uintptr_t)w.partial,
+                              (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.eflag, (uint64_t)pl.grid,
+                              (uint64_t)pl.threads, (uint64_t)pl.lds_bytes};
+    if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
+        if (ctx->gexec) {
+            (void)hipGraphExecDestroy(ctx->gexec);
+            ctx->gexec = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed), "begin capture");
+        hipError_t e = hipSuccess;
+        for (int u = 0; u < chunk && e == hipSuccess; ++u) {
+            const int32_t t = t0 + u;
+            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
+            e = launch_row_pass(pl, PASS_FULL, pf, ctx->cap);
+            if (e == hipSuccess) e = launch_col_reduce(col_args(w, n, w.st, 1), ctx->cap);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+        if (e == hipSuccess && e2 == hipSuccess && g != nullptr)
+            e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess || e2 != hipSuccess || ctx->gexec == nullptr) {
+            ctx->gexec = nullptr;
+            (void)hipGetLastError();
+            return APX_ENOTIMPL;
+        }
+        std::memcpy(ctx->gkey, key, sizeof key);
+    }
+    HIP_TRY(hipEventRecord(ctx->join, ctx->stream), "join");
+    HIP_TRY(hipStreamWaitEvent(ctx->cap, ctx->join, 0), "join");
+    HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->cap), "graph launch");
+    HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, ctx->cap), "state");
+    HIP_TRY(hipStreamSynchronize(ctx->cap), "sync");
+    return APX_OK;
+}
+
+}  // namespace
+
 namespace apx {
 size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus) {
     const PassPlan pl = plan_pass(n, num_cus);
@@ -229,6 +286,8 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return APX_ENOMEM;
     }
+    const char *gv = getenv("APX_GRAPHS");
+    if (gv && gv[0] == '0') ctx->graphs = false;
     *out = ctx;
     return APX_OK;
 }
@@ -238,6 +297,12 @@ void apx_destroy(apx_ctx *ctx) {
     DevGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->cap) {
+        (void)hipStreamSynchronize(ctx->cap);
+        (void)hipStreamDestroy(ctx->cap);
+    }
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
@@ -252,6 +317,12 @@ apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream) {
 const char *apx_last_error(const apx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 size_t apx_workspace_bytes(const apx_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+apx_status apx_set_graphs(apx_ctx *ctx, int enable) {
+    if (!ctx) return APX_EINVAL;
+    ctx->graphs = enable != 0;
+    return APX_OK;
+}
 
 apx_status apx_profile(apx_ctx *ctx, int enable) {
     if (!ctx) return APX_EINVAL;
@@ -352,7 +423,15 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     }
     HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
 
-    const int chunk = params->check_every > 0 ? params->check_every : 16;
+    // Host polls every `chunk` iterations (even, so every replay of the
+    // captured chunk starts on the same responsibility buffer).  Passes after
+    // the stop iteration are no-ops on the device, so results do not depend
+    // on the chunk.
+    int chunk = params->check_every > 0 ? params->check_every : 16;
+    chunk += chunk & 1;
+    // Kernel timing needs events on the host-launched passes (event records
+    // captured inside a graph cannot be timed), so timing runs eagerly.
+    bool use_graph = ctx->graphs && !ctx->prof;
     if (ctx->prof && (int)ctx->prof_ev.size() < 2 * chunk) {
         while ((int)ctx->prof_ev.size() < 2 * chunk) {
             hipEvent_t e;
@@ -366,17 +445,31 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         int32_t stop_at = t + chunk;
         if (stop_at > params->max_iter + 1) stop_at = params->max_iter + 1;
         const int32_t t_first = t;
-        for (; t < stop_at; ++t) {
-            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec,
-                                    w.eflag, w.st);
-            const int slot = t - t_first;
-            if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
-            HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
-            if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
-            HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1), s), "column reduce");
+        bool done = false;
+        if (use_graph && stop_at - t == chunk) {
+            const apx_status gs = graph_chunk(ctx, pl, S, buf, A, n, ld, lam, w, chunk, t, hst);
+            if (gs == APX_OK) {
+                t = stop_at;
+                done = true;
+            } else if (gs == APX_ENOTIMPL) {
+                use_graph = false;
+            } else {
+                return gs;
+            }
         }
-        HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, s), "state");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (!done) {
+            for (; t < stop_at; ++t) {
+                PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec,
+                                        w.eflag, w.st);
+                const int slot = t - t_first;
+                if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
+                HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
+                if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
+                HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1), s), "column reduce");
+            }
+            HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, s), "state");
+            HIP_TRY(hipStreamSynchronize(s), "sync");
+        }
         if (ctx->prof) {
             // only the passes that did work (iterations <= the stop iteration)
             for (int32_t u = t_first; u < t && u <= hst->iter; ++u) {

@@ -112,6 +112,13 @@ struct apx_ctx {
     size_t ws_bytes = 0;
     size_t ws_base = 0;       // start of the slice handed to the running solver
     void *pinned = nullptr;   // small pinned host buffer for state read-back
+    // hipGraph replay of the iteration loop: one captured chunk of
+    // (row pass, column reduce) pairs, re-captured when its arguments change
+    bool graphs = true;
+    hipStream_t cap = nullptr;        // private stream the graph runs on
+    hipEvent_t join = nullptr;        // orders the private stream after `stream`
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey[16] = {};
     // benchmark timing of full row passes (apx_profile)
     bool prof = false;
     std::vector<hipEvent_t> prof_ev;
