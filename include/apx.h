@@ -82,6 +82,38 @@ size_t apx_workspace_bytes(const apx_ctx *ctx);
  * after the context stream with an event; results are identical either way. */
 apx_status apx_set_graphs(apx_ctx *ctx, int enable);
 
+/* ---------------------------------------------------------------------------
+ * Autotuner.  Sizes are grouped into buckets that share one row-pass shape
+ * (n <= 4096: ceil(n/1024); above: 4 + ceil((n-4096)/4096)).  For a bucket
+ * the tuner times every instantiated row-pass workgroup size (256, 512, 1024
+ * threads) and variant (LDS-resident or register) on a scratch problem with
+ * the same row length and keeps the fastest; it also sets the host poll
+ * interval of the stop flag (used when apx_params.check_every is 0) so that
+ * a poll costs about 1% of the iterations between polls.  All candidates
+ * share the row -> workgroup map, so tuning never changes a result bit.
+ * The environment variable APX_TUNE_FILE names a file loaded at context
+ * creation; APX_AUTOTUNE=1 tunes unseen buckets on first use.
+ * ------------------------------------------------------------------------- */
+
+/* apx_autotune -- measure the bucket of n now (allocates and frees a scratch
+ * problem of up to 4 x #CU rows; synchronises the context stream). */
+apx_status apx_autotune(apx_ctx *ctx, int64_t n);
+/* apx_set_autotune -- tune unseen buckets automatically (enable = 1). */
+apx_status apx_set_autotune(apx_ctx *ctx, int enable);
+/* apx_tune_set -- set the bucket of n by hand (EINVAL if that workgroup size
+ * has no row pass for n). */
+apx_status apx_tune_set(apx_ctx *ctx, int64_t n, int32_t threads, int32_t lds, int32_t check_every);
+/* apx_tune_get -- the entry used for n (threads = 0 if none); lds reports the
+ * variant that actually runs at this n. */
+apx_status apx_tune_get(apx_ctx *ctx, int64_t n, int32_t *threads, int32_t *lds, int32_t *check_every,
+                        double *ms_per_iter);
+/* apx_tune_clear -- forget every entry (back to the default plans). */
+apx_status apx_tune_clear(apx_ctx *ctx);
+/* apx_tune_save / apx_tune_load -- the context's entries as JSON (path: host
+ * string).  Loading rejects a file tuned for another compute-unit count. */
+apx_status apx_tune_save(apx_ctx *ctx, const char *path);
+apx_status apx_tune_load(apx_ctx *ctx, const char *path);
+
 /* Kernel timing for benchmarks: while enabled, ap_solve brackets every full
  * row pass (the dominant kernel) with HIP events on the context stream (the
  * passes are then launched from the host, not replayed as a graph) and

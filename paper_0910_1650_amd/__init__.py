@@ -63,6 +63,14 @@ SIGNATURES = {
     "apx_workspace_bytes": (ctypes.c_size_t, [_P]),
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_autotune": (ctypes.c_int, [_P, _I64]),
+    "apx_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_tune_set": (ctypes.c_int, [_P, _I64, _I32, _I32, _I32]),
+    "apx_tune_get": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                    ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
+    "apx_tune_clear": (ctypes.c_int, [_P]),
+    "apx_tune_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "apx_tune_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "apx_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "ap_similarity": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _I32, _P, ctypes.c_float,
                                      ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
@@ -239,6 +247,47 @@ def apx_set_graphs(enable: bool, device=None) -> None:
     """Replay ap_solve's iteration loop as a captured HIP graph (default) or not."""
     ctx = context(device)
     _check(ctx, lib().apx_set_graphs(ctx, int(bool(enable))), "apx_set_graphs")
+
+
+def apx_autotune(n: int, device=None) -> dict:
+    """Tune the row pass for size n now; returns the chosen entry."""
+    ctx = context(device)
+    _check(ctx, lib().apx_autotune(ctx, n), "apx_autotune")
+    return apx_tune_get(n, device)
+
+
+def apx_set_autotune(enable: bool, device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_set_autotune(ctx, int(bool(enable))), "apx_set_autotune")
+
+
+def apx_tune_set(n: int, threads: int, lds: bool, check_every: int = 0, device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_tune_set(ctx, n, threads, int(bool(lds)), check_every), "apx_tune_set")
+
+
+def apx_tune_get(n: int, device=None) -> dict:
+    ctx = context(device)
+    t, l, c = _I32(), _I32(), _I32()
+    ms = ctypes.c_double()
+    _check(ctx, lib().apx_tune_get(ctx, n, ctypes.byref(t), ctypes.byref(l), ctypes.byref(c),
+                                   ctypes.byref(ms)), "apx_tune_get")
+    return dict(threads=t.value, lds=bool(l.value), check_every=c.value, ms_per_iter=ms.value)
+
+
+def apx_tune_clear(device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_tune_clear(ctx), "apx_tune_clear")
+
+
+def apx_tune_save(path: str, device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_tune_save(ctx, os.fsencode(path)), "apx_tune_save")
+
+
+def apx_tune_load(path: str, device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_tune_load(ctx, os.fsencode(path)), "apx_tune_load")
 
 
 def apx_profile(enable: bool, device=None) -> None:

@@ -725,22 +725,30 @@ hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t
 
 }  // namespace
 
-PassPlan plan_pass(int64_t n, int num_cus) {
+// Chunks (float4 per thread per row) instantiated for each workgroup size.
+int max_chunks(int threads) { return threads == 256 ? 4 : threads == 512 ? 8 : threads == 1024 ? 16 : 0; }
+
+PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds) {
     PassPlan pl{};
     const int64_t q = (n + 3) / 4;   // float4 chunks per row
-    if (n <= 4096) {
-        pl.threads = 256;
-        pl.chunks = (int)((q + 255) / 256);
-        int64_t g = 2LL * num_cus;
-        pl.grid = (int)(n < g ? n : g);
-    } else {
-        pl.threads = 1024;
-        pl.chunks = (int)((q + 1023) / 1024);
-        pl.grid = (int)(n < num_cus ? n : num_cus);
+    // The row -> workgroup map depends on n only, so every variant computes
+    // the same column partial sums and gives bit-identical results.
+    const int64_t g = n <= 4096 ? 2LL * num_cus : (int64_t)num_cus;
+    pl.grid = (int)(n < g ? n : g);
+    pl.threads = threads;
+    pl.chunks = (int)((q + threads - 1) / threads);
+    if (pl.chunks > max_chunks(threads)) {
+        pl.threads = 0;           // not instantiated
+        return pl;
     }
-    const size_t lds = (size_t)2 * 16 * (size_t)q;
-    pl.lds_bytes = (lds <= (size_t)kMaxDynLds && pl.chunks <= 5) ? lds : 0;
-    // APX_ROW_PASS=reg selects the register variant (tuning and cross-checks).
+    const size_t bytes = (size_t)2 * 16 * (size_t)q;
+    pl.lds_bytes = (lds && bytes <= (size_t)kMaxDynLds && pl.chunks <= 5) ? bytes : 0;
+    return pl;
+}
+
+PassPlan plan_pass(int64_t n, int num_cus) {
+    PassPlan pl = plan_pass_variant(n, num_cus, n <= 4096 ? 256 : 1024, true);
+    // APX_ROW_PASS=reg selects the register variant (cross-checks).
     const char *v = getenv("APX_ROW_PASS");
     if (v && v[0] == 'r') pl.lds_bytes = 0;
     return pl;
@@ -756,6 +764,20 @@ hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipS
         default: return hipErrorInvalidValue;
         }
     }
+    if (pl.threads == 512) {
+        switch (pl.chunks) {
+        case 1: return launch_t<512, 1>(mode, a, pl, s);
+        case 2: return launch_t<512, 2>(mode, a, pl, s);
+        case 3: return launch_t<512, 3>(mode, a, pl, s);
+        case 4: return launch_t<512, 4>(mode, a, pl, s);
+        case 5: return launch_t<512, 5>(mode, a, pl, s);
+        case 6: return launch_t<512, 6>(mode, a, pl, s);
+        case 7: return launch_t<512, 7>(mode, a, pl, s);
+        case 8: return launch_t<512, 8>(mode, a, pl, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (pl.threads != 1024) return hipErrorInvalidValue;
     switch (pl.chunks) {
     case 1: return launch_t<1024, 1>(mode, a, pl, s);
     case 2: return launch_t<1024, 2>(mode, a, pl, s);

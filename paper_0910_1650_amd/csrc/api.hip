@@ -255,7 +255,8 @@ size_t resp_step_ws_bytes(int64_t n, int64_t ld, int num_cus) {
 }
 
 apx_status resp_step(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A) {
-    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    PassPlan pl{};
+    APX_TRY(ctx_plan(ctx, n, &pl, nullptr));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
     hipStream_t s = ctx->stream;
@@ -288,6 +289,11 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
     }
     const char *gv = getenv("APX_GRAPHS");
     if (gv && gv[0] == '0') ctx->graphs = false;
+    const char *av = getenv("APX_AUTOTUNE");
+    if (av && av[0] == '1') ctx->autotune = true;
+    const char *tf = getenv("APX_TUNE_FILE");
+    if (tf && tf[0]) (void)apx_tune_load(ctx, tf);   // a missing or foreign file leaves the defaults
+    ctx->err.clear();
     *out = ctx;
     return APX_OK;
 }
@@ -350,7 +356,8 @@ apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float
     if (!(damping >= 0.0f && damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
     if (n_iter < 1) return set_err(ctx, APX_EINVAL, "n_iter must be >= 1");
     DevGuard g(ctx->device);
-    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    PassPlan pl{};
+    APX_TRY(ctx_plan(ctx, n, &pl, nullptr));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
     hipStream_t s = ctx->stream;
@@ -404,7 +411,9 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         return APX_OK;
     }
 
-    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    PassPlan pl{};
+    int tuned_chunk = 0;
+    APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
     HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, s), "state init");
@@ -427,7 +436,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     // captured chunk starts on the same responsibility buffer).  Passes after
     // the stop iteration are no-ops on the device, so results do not depend
     // on the chunk.
-    int chunk = params->check_every > 0 ? params->check_every : 16;
+    int chunk = params->check_every > 0 ? params->check_every : (tuned_chunk > 0 ? tuned_chunk : 16);
     chunk += chunk & 1;
     // Kernel timing needs events on the host-launched passes (event records
     // captured inside a graph cannot be timed), so timing runs eagerly.

@@ -77,6 +77,9 @@ struct PassPlan {
     size_t lds_bytes;  // dynamic LDS of the LDS-resident variant (0: register variant)
 };
 PassPlan plan_pass(int64_t n, int num_cus);
+// The same row -> workgroup map with a chosen workgroup size and variant;
+// threads = 0 in the result when that combination is not instantiated.
+PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds);
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);
 hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s);
 hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, hipStream_t s);
@@ -100,6 +103,17 @@ struct FinalArgs {
 };
 hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
 
+// Autotuned choices for one problem-size bucket (see tune.hip).
+struct TuneEntry {
+    int64_t bucket;
+    int64_t n;          // size it was measured at
+    int threads;        // row-pass workgroup size
+    int lds;            // 1: LDS-resident variant
+    int check_every;    // host poll interval of the stop flag
+    double ms_per_iter; // measured (row pass + column reduce)
+};
+int64_t tune_bucket(int64_t n);
+
 }  // namespace apx
 
 // Context ------------------------------------------------------------------
@@ -119,6 +133,9 @@ struct apx_ctx {
     hipEvent_t join = nullptr;        // orders the private stream after `stream`
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey[16] = {};
+    // autotuner (tune.hip)
+    bool autotune = false;            // tune unseen size buckets on first use
+    std::vector<apx::TuneEntry> tune;
     // benchmark timing of full row passes (apx_profile)
     bool prof = false;
     std::vector<hipEvent_t> prof_ev;
@@ -160,6 +177,10 @@ size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus);
 apx_status resp_step(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A);
 size_t resp_step_ws_bytes(int64_t n, int64_t ld, int num_cus);
 apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
+// Row-pass plan for n on this context: the default plan with the tuned
+// workgroup size and variant applied (tuning first if enabled and unseen);
+// *check_every (nullable) receives the tuned poll interval or 0.
+apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every);
 apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what);
 
 }  // namespace apx
