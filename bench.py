@@ -13,9 +13,13 @@ parts) and from the learned warm start, reporting wall time to the stop rule
 and whether the exemplar set is the FP64 oracle's ("time_to_exemplars").
 
 Prints one JSON line (see the fields below).  `value` is the algorithmic
-message traffic of the AP iterations (20 bytes per matrix element and
-iteration: read S, R, A and write A, R) divided by the whole step time, so
-similarity, preference and finalize time count against it.
+message traffic of the AP iterations divided by the whole step time, so
+similarity, preference and finalize time count against it.  An iteration
+with implicit responsibilities (the library's path at this size: R rebuilt
+from S and a short per-row state) moves 12 bytes per matrix element (read S,
+A; write A); one with explicit R moves 20 (read S, R, A; write A, R).
+`iteration_path` reports which ran and the rate the explicit form would need
+for the same iterations per second.
 """
 from __future__ import annotations
 
@@ -31,7 +35,8 @@ if ROOT not in sys.path:
 
 N, D, K_MIX, SEED = 20000, 64, 50, 2001
 LAMBDA, MAX_ITER, CONV_ITER = 0.9, 2000, 15
-BYTES_PER_ELEM_ITER = 20          # read S, R, A; write A, R (FP32)
+BYTES_EXPLICIT = 20               # explicit R: read S, R, A; write A, R (FP32)
+BYTES_IMPLICIT = 12               # implicit R: read S, A; write A (FP32)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -45,7 +50,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-warm-compare", action="store_true")
     ap.add_argument("--counter-run", action="store_true",
-                    help="short fixed sequence for rocprofv3 --pmc runs: 4 AP iterations at N, "
+                    help="short fixed sequence for rocprofv3 --pmc runs: 4 AP iterations at N "
+                         "(ap_solve, fixed count), "
                          "then a plain 1.6 GB device copy (the calibration kernel); prints no JSON")
     return ap.parse_args()
 
@@ -60,12 +66,13 @@ def cpu_baseline(pts, n_iter: int) -> dict:
     dt = time.perf_counter() - t0
     n = S.shape[0]
     it_s = n_iter / dt
-    return {"value": round(it_s * BYTES_PER_ELEM_ITER * n * n / 1e9, 3), "unit": "GB/s",
+    return {"value": round(it_s * BYTES_EXPLICIT * n * n / 1e9, 3), "unit": "GB/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "iter_per_s": round(it_s, 4),
             "sample": f"{n_iter} FP64 oracle iterations of dense AP on the same N={n} matrix "
-                      f"(similarity/preference setup untimed); GB/s counts the same "
-                      f"{BYTES_PER_ELEM_ITER} B per element and iteration as the GPU figure"}
+                      f"(similarity/preference setup untimed); GB/s counts the "
+                      f"{BYTES_EXPLICIT} B per element and iteration of explicit R, the form "
+                      f"the oracle runs"}
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_n20000_d64_k50_seed2001.json")
@@ -77,8 +84,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row_pass_n20000_hbm_counters.md).  Valid only for the row-pass source with
 # this SHA-256; otherwise the benchmark reports traffic as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 4802892196, "write": 3224278347,
-                    "sha256": "6e7cfa613ebdbc3199b38e639902a2dc882485ba29fe45b4e4d3bb15bc948900"}
+ROW_PASS_TRAFFIC = {"read": 3204067369, "write": 1625317168, "implicit": True,
+                    "sha256": "c9da37445f4202dafb030c3ad878cf52cc35c6545adbd3ff591a95c6937b6762"}
 PAP_K = 8
 
 
@@ -137,8 +144,8 @@ def counter_run(n: int) -> None:
     pts = synth.gaussian_mixture(n=n, d=D, k=K_MIX, seed=SEED)
     X = torch.from_numpy(pts.X).cuda()
     S, _ = apx.ap_similarity(X, pref="median", noise_seed=SEED, noise_rel=1e-12)
-    R, A = apx.empty_matrix(n, fill=0.0), apx.empty_matrix(n, fill=0.0)
-    apx.ap_iterate(S, R, A, LAMBDA, 4)      # R-only prologue, 3 full passes, A-only epilogue
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    apx.ap_solve(S, R, A, LAMBDA, 4, 0)     # prologue and 4 full passes, as the benchmark runs them
     torch.cuda.synchronize()
     src = torch.ones(CALIB_ELEMS, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -191,12 +198,17 @@ def main():
     apx.apx_profile(True)
     apx.apx_profile_read()
     iters = 0
+    alg_bytes = 0
+    imp_iters = exp_iters = 0
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         _, res = step()
         iters += res.iterations
+        ni, ne = apx.apx_last_solve_info()
+        imp_iters += ni
+        exp_iters += ne
         results.append(res)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -214,12 +226,16 @@ def main():
 
     elems = n * n
     ms_step = dt * 1e3 / args.steps
-    gbs = iters * BYTES_PER_ELEM_ITER * elems / dt / 1e9
+    alg_bytes = (imp_iters * BYTES_IMPLICIT + exp_iters * BYTES_EXPLICIT) * elems
+    gbs = alg_bytes / dt / 1e9
     avg_pass_ms = pass_ms / max(launches, 1)
-    achieved = BYTES_PER_ELEM_ITER * elems / (avg_pass_ms * 1e-3) / 1e9
+    implicit = imp_iters > 0 and exp_iters == 0
+    per_launch = (BYTES_IMPLICIT if implicit else BYTES_EXPLICIT) * elems
+    achieved = per_launch / (avg_pass_ms * 1e-3) / 1e9
     r0 = results[-1]
     traffic = None
-    if (ROW_PASS_TRAFFIC is not None and n == N
+    kernel = "k_row_imp (full iteration pass, implicit R)" if implicit else "k_row_pass (full iteration pass)"
+    if (ROW_PASS_TRAFFIC is not None and n == N and implicit == ROW_PASS_TRAFFIC["implicit"]
             and source_sha256(ROW_PASS_SRC) == ROW_PASS_TRAFFIC["sha256"]):
         traffic = round((ROW_PASS_TRAFFIC["read"] + ROW_PASS_TRAFFIC["write"]) / 1e9, 3)
     out = {
@@ -245,11 +261,14 @@ def main():
         "n_exemplars": r0.n_exemplars,
         "netsim": r0.netsim,
         "similarity_ms": round(sim_ms, 3),
-        "roofline": {"bound": "hbm", "kernel": "k_row_pass (full iteration pass)",
+        "iteration_path": {"implicit_R_iterations": imp_iters, "explicit_R_iterations": exp_iters,
+                           "bytes_per_element": {"implicit": BYTES_IMPLICIT, "explicit": BYTES_EXPLICIT},
+                           "explicit_R_equivalent_GBps": round(iters * BYTES_EXPLICIT * elems / dt / 1e9, 2)},
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launches": launches, "avg_launch_ms": round(avg_pass_ms, 4),
-                     "bytes_per_launch": BYTES_PER_ELEM_ITER * elems,
+                     "bytes_per_launch": per_launch,
                      "traffic_unit": "GB per launch (HBM read + write, counter-measured)"},
     }
     if not args.no_warm_compare:

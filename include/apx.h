@@ -75,6 +75,25 @@ const char *apx_last_error(const apx_ctx *ctx);
 /* Bytes of device workspace currently held by the context. */
 size_t apx_workspace_bytes(const apx_ctx *ctx);
 
+/* apx_set_implicit -- list capacity of the implicit responsibilities used by
+ * ap_solve when R_0 = 0 (APX_COLD, APX_WARM_A): unrolling the damped Eq. (2)
+ * gives R_t(i,k) = (1 - lambda^t) s(i,k) - beta_t(i) + gamma_t(i,k), where
+ * gamma_t(i,.) is non-zero only on the columns that were row i's argmax of
+ * a+s at an earlier iteration; each row keeps beta and up to list_capacity
+ * (column, gamma) pairs, so an iteration reads S and A and writes A
+ * (12 bytes per matrix element instead of 20).  When a row needs more
+ * entries, R is made explicit and the run continues with explicit R.
+ * 0 = always explicit R; default 16 (the maximum); the environment variable
+ * APX_IMPLICIT_K sets it at context creation.  Only problems with
+ * n >= min_n use it (default 8192: below that the explicit pass is faster).
+ * Results agree with explicit R to rounding (the same arithmetic in another
+ * order). */
+apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n);
+
+/* apx_last_solve_info -- how many iterations of the last ap_solve on this
+ * context ran with implicit R and how many with explicit R. */
+apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters);
+
 /* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP
  * graph (enable = 1, the default; the environment variable APX_GRAPHS=0
  * turns it off at context creation) or launch every kernel from the host

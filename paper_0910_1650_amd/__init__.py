@@ -63,6 +63,8 @@ SIGNATURES = {
     "apx_workspace_bytes": (ctypes.c_size_t, [_P]),
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
+    "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "apx_autotune": (ctypes.c_int, [_P, _I64]),
     "apx_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_tune_set": (ctypes.c_int, [_P, _I64, _I32, _I32, _I32]),
@@ -241,6 +243,21 @@ def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float =
     _check(ctx, lib().ap_solve(ctx, Sp, n, ld, Rp, Ap, warm, ctypes.byref(prm), _P(idx.data_ptr()),
                                ctypes.byref(res)), "ap_solve")
     return idx, _res(res)
+
+
+def apx_set_implicit(list_capacity: int, min_n: int = 8192, device=None) -> None:
+    """Implicit responsibilities in ap_solve for n >= min_n: list capacity
+    1..16, or 0 for explicit R."""
+    ctx = context(device)
+    _check(ctx, lib().apx_set_implicit(ctx, list_capacity, min_n), "apx_set_implicit")
+
+
+def apx_last_solve_info(device=None) -> tuple[int, int]:
+    """(iterations with implicit R, iterations with explicit R) of the last ap_solve."""
+    ctx = context(device)
+    a, b = _I32(), _I32()
+    _check(ctx, lib().apx_last_solve_info(ctx, ctypes.byref(a), ctypes.byref(b)), "apx_last_solve_info")
+    return a.value, b.value
 
 
 def apx_set_graphs(enable: bool, device=None) -> None:

@@ -17,6 +17,7 @@
 #include "apx_internal.h"
 
 #include <cfloat>
+#include <cmath>
 #include <cstdlib>
 
 namespace apx {
@@ -26,6 +27,8 @@ constexpr float kNegInf = -INFINITY;
 // Dynamic LDS of the row pass (u and column partials): 160 KB per CU on
 // gfx950, minus the static reduction scratch.
 constexpr int kMaxDynLds = 160 * 1024 - 1024;
+// The implicit pass keeps its row state in static LDS as well.
+constexpr int kMaxDynLdsImp = 160 * 1024 - 2048;
 
 struct Top2 {
     float v1;   // largest a+s
@@ -557,6 +560,8 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
             st->frozen = 1;
         } else if (t >= st->max_iter) {
             st->frozen = 1;
+        } else if (st->imp_abort) {
+            st->frozen = 2;   // an implicit-R list overflowed: the host continues with explicit R
         }
         st->nex = 0;
         st->changed = 0;
@@ -723,6 +728,361 @@ hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t
     return hipGetLastError();
 }
 
+
+// ---- implicit responsibilities ---------------------------------------------
+// R_t(i,k) = alpha_t s(i,k) - beta_t(i) + gamma_t(i,k), see ImpArgs.  A pass
+// reads S and A and writes A (12 bytes per element instead of 20); R is
+// rebuilt in registers from the row's state.  alpha_t comes from one
+// function of t, so the partials formed for R_{t+1} in pass t and the values
+// pass t+1 rebuilds are the same numbers.
+__device__ __forceinline__ float imp_alpha(float lam, int t) {
+    return (float)(1.0 - pow((double)lam, (double)t));
+}
+
+template <int T, int J, int KIND, bool PREF>
+__global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
+#pragma clang fp contract(off)
+    constexpr bool DO_A = (KIND == IMP_FULL);
+    constexpr bool LD_A = (KIND != IMP_PRO_COLD);
+    constexpr int NW = T / 64;
+    constexpr int NOWN = 2;                      // listed columns a thread keeps in registers
+
+    if (p.st != nullptr && p.st->frozen) return;
+    __shared__ float sh_f[2][NW][3];
+    __shared__ int sh_i[2][NW][2];
+    // Row state, three slots: the state of row i+1 is staged during row i
+    // before the reduction barrier, which orders it before its use; the slot
+    // it overwrites was last read in row i-2, before row i-1's barrier.
+    __shared__ int st_col[3][IMP_K];
+    __shared__ float st_gam[3][IMP_K];
+    __shared__ float st_beta[3];
+    __shared__ int st_cnt[3];
+    extern __shared__ float4 dyn[];
+    const int q = (p.n + 3) >> 2;
+    float4 *lpart = dyn;                         // column partials, q entries
+    float4 *ls = dyn + q;                        // S of the current row (PREF), q entries
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n = p.n;
+    const int64_t ld = p.ld;
+    const float lam = p.lam;
+    const float oml = 1.0f - lam;
+    const int64_t nrows = p.row_end - p.row_begin;
+    const int64_t r0 = p.row_begin + (int64_t)blockIdx.x * nrows / gridDim.x;
+    const int64_t r1 = p.row_begin + (int64_t)(blockIdx.x + 1) * nrows / gridDim.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int voff = tid * 16;
+    const int c0 = tid * 4;
+    const int cl = ((J - 1) * T + tid) * 4;
+    const bool last_in = cl < n;
+    const bool last_full = cl + 3 < n;
+    const int tpass = p.pass_t >= 0 ? p.pass_t : p.st->iter + 1;
+    const float al = imp_alpha(lam, tpass);      // alpha_t
+    const float al1 = imp_alpha(lam, tpass + 1); // alpha_{t+1}
+
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if (j < J - 1 || last_in) lpart[j * T + tid] = z4;
+    int my_nex = 0, my_changed = 0;
+
+    auto load_state = [&](int64_t i) {
+        const int sl = (int)(i % 3);
+        if (tid < IMP_K) st_col[sl][tid] = p.col_in[i * IMP_K + tid];
+        else if (tid < 2 * IMP_K) st_gam[sl][tid - IMP_K] = p.gam_in[i * IMP_K + tid - IMP_K];
+        else if (tid == 2 * IMP_K) st_beta[sl] = p.beta_in[i];
+        else if (tid == 2 * IMP_K + 1) st_cnt[sl] = p.cnt_in[i];
+    };
+    // The prefetching variant holds the next row's S and A in registers; the
+    // other (long rows) holds only S and reads A chunk by chunk.
+    float4 s4[J], a4[(LD_A && PREF) ? J : 1];
+    auto load_row = [&](int64_t i) {
+        const rsrc_t srs = row_rsrc(p.S + i * ld, ld);
+        const rsrc_t ars = row_rsrc(p.A + i * ld, ld);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (j < J - 1 || last_in) {
+                s4[j] = bld4(srs, voff, j * T * 16);
+                if constexpr (LD_A && PREF) a4[j] = bld4(ars, voff, j * T * 16);
+            }
+        }
+    };
+    if (r0 < r1) {
+        load_state(r0);
+        load_row(r0);
+    }
+    __syncthreads();
+
+    for (int64_t i = r0; i < r1; ++i) {
+        const int ii = (int)i;
+        const int sl = (int)(i % 3);
+        const ColOwner dg = owner_of<T>(ii, tid);
+        float *Arow = p.A + i * ld;
+        const rsrc_t a_rs = row_rsrc(Arow, ld);
+        // state of R_t for this row; the listed columns this thread owns go
+        // to registers (local index 4*chunk + element, gamma, list slot)
+        const float beta = st_beta[sl];
+        const int cnt = st_cnt[sl];
+        int own_le[NOWN], own_q[NOWN];
+        float own_g[NOWN];
+#pragma unroll
+        for (int o = 0; o < NOWN; ++o) {
+            own_le[o] = -1;
+            own_q[o] = -1;
+            own_g[o] = 0.0f;
+        }
+        int nown = 0;
+        for (int qq = 0; qq < cnt; ++qq) {
+            const int c = st_col[sl][qq];
+            if (((c >> 2) % T) == tid) {
+                const int le = ((c >> 2) / T) * 4 + (c & 3);
+#pragma unroll
+                for (int o = 0; o < NOWN; ++o) {
+                    const bool put = nown == o;
+                    own_le[o] = put ? le : own_le[o];
+                    own_q[o] = put ? qq : own_q[o];
+                    own_g[o] = put ? st_gam[sl][qq] : own_g[o];
+                }
+                ++nown;
+            }
+        }
+        float ci = 0.0f;
+        if constexpr (DO_A) ci = p.ccol[ii];
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+        int l1 = -1, dl = -1;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            const float4 sv = s4[j];
+            float4 a = z4;
+            if constexpr (LD_A) {
+                if constexpr (PREF) a = a4[j];
+                else a = bld4(a_rs, voff, j * T * 16);
+            }
+            float4 r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float rv = al * f4get(sv, e) - beta;
+                if (nown > 0) {
+#pragma unroll
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) rv = rv + own_g[o];
+                }
+                f4set(r, e, rv);
+            }
+            if constexpr (DO_A) {
+                chunk_avail(a, r, ld4(p.tcol + c), ci, j, dg, c, n, full, lam, oml, dv, dl);
+                store_chunk(Arow, a_rs, voff, j * T * 16, c, n, full, a);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (full || c + e < n) {
+                    const float v = f4get(a, e) + f4get(sv, e);
+                    const bool gt = v > v1;
+                    v2 = gt ? v1 : fmaxf(v2, v);
+                    l1 = gt ? 4 * j + e : l1;
+                    v1 = gt ? v : v1;
+                }
+            }
+            if constexpr (PREF) ls[j * T + tid] = sv;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < r1) {
+            load_state(i + 1);
+            if constexpr (PREF) load_row(i + 1);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
+        wg_reduce<NW, DO_A, true>(t2, dm, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        if constexpr (DO_A) {
+            if (tid == 0) {
+                const int k = dm.k;
+                if (p.dec) p.dec[ii] = k;
+                if (p.eflag) {
+                    const uint8_t ef = (uint8_t)(k == ii);
+                    if (p.eflag[ii] != ef) my_changed = 1;
+                    p.eflag[ii] = ef;
+                    my_nex += ef;
+                }
+            }
+        }
+
+        // State of R_{t+1}: beta' = lam beta + (1-lam) v1; every gamma decays
+        // by lam and column k1 gains d = (1-lam)(v1 - v2).
+        const int k1 = t2.k1;
+        const float d = oml * (t2.v1 - t2.v2);
+        const float beta1 = lam * beta + oml * t2.v1;
+        // A new column k1 overflows the row when the list is full or when the
+        // thread owning k1 already keeps NOWN listed columns (every thread
+        // evaluates the same test, so the decision is uniform).
+        int pos1 = -1, k1_owner_has = 0;
+        const int k1_owner = (k1 >> 2) % T;
+        for (int qq = 0; qq < cnt; ++qq) {
+            const int c = st_col[sl][qq];
+            pos1 = (c == k1) ? qq : pos1;
+            k1_owner_has += (((c >> 2) % T) == k1_owner) ? 1 : 0;
+        }
+        const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);
+        if (tid == 0) {
+            p.beta_out[ii] = beta1;
+            if (ovf) {
+                p.cnt_out[ii] = -1;
+                p.st->imp_abort = 1;
+            } else {
+                for (int qq = 0; qq < cnt; ++qq) {
+                    p.col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
+                    p.gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
+                }
+                if (pos1 < 0) {
+                    p.col_out[(int64_t)ii * IMP_K + cnt] = k1;
+                    p.gam_out[(int64_t)ii * IMP_K + cnt] = d;
+                }
+                p.cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
+            }
+        }
+        float own_g1[NOWN];
+#pragma unroll
+        for (int o = 0; o < NOWN; ++o) own_g1[o] = lam * own_g[o] + (own_q[o] == pos1 ? d : 0.0f);
+        const bool k1_mine = pos1 < 0 && k1_owner == tid;
+        const int k1_le = ((k1 >> 2) / T) * 4 + (k1 & 3);
+
+        // Column partials of max(0, R_{t+1}); on overflow the row of R_{t+1}
+        // is also written explicitly.
+        float *Rx = p.Rx + i * ld;
+        const rsrc_t x_rs = row_rsrc(Rx, ld);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            float4 sv;
+            if constexpr (PREF) sv = ls[j * T + tid];
+            else sv = s4[j];
+            float4 pos;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = c + e;
+                float rv = al1 * f4get(sv, e) - beta1;
+                if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
+                if (nown > 0) {
+#pragma unroll
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
+                }
+                const bool diag = dg.mine && dg.j == j && dg.e == e;
+                f4set(pos, e, (diag || !(full || k < n)) ? 0.0f : fmaxf(0.0f, rv));
+                if (diag) p.rdiag[ii] = rv;
+            }
+            float4 acc = lpart[j * T + tid];
+            add4(acc, pos);
+            lpart[j * T + tid] = acc;
+        }
+        if (ovf) {
+            // the overflowing row of R_{t+1}, written explicitly (same values)
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (!(j < J - 1 || last_in)) continue;
+                const bool full = (j < J - 1) || last_full;
+                const int c = c0 + j * T * 4;
+                float4 sv;
+                if constexpr (PREF) sv = ls[j * T + tid];
+                else sv = s4[j];
+                float4 rn;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float rv = al1 * f4get(sv, e) - beta1;
+                    if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
+#pragma unroll
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
+                    f4set(rn, e, rv);
+                }
+                store_chunk(Rx, x_rs, voff, j * T * 16, c, n, full, rn);
+            }
+        }
+        if constexpr (!PREF) {
+            if (i + 1 < r1) load_row(i + 1);
+        }
+    }
+
+    {
+        float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, lpart[j * T + tid]);
+    }
+    if constexpr (DO_A) {
+        if (tid == 0 && p.st != nullptr) {
+            if (my_nex) atomicAdd(&p.st->nex, my_nex);
+            if (my_changed) atomicOr(&p.st->changed, 1);
+        }
+    }
+}
+
+// R(i,k) = alpha_t s(i,k) - beta(i) + gamma(i,k) for every row with a list;
+// the same expression (and rounding) as the passes use.
+__global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float al,
+                                  const float *beta, const int32_t *cnt, const int32_t *col,
+                                  const float *gam) {
+#pragma clang fp contract(off)
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int c = cnt[i];
+        if (c < 0) continue;
+        const float b = beta[i];
+        const float *srow = S + i * ld;
+        float *rrow = R + i * ld;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) rrow[k] = al * srow[k] - b;
+        __syncthreads();
+        if (threadIdx.x < c) {
+            const int64_t k = col[i * IMP_K + threadIdx.x];
+            rrow[k] = (al * srow[k] - b) + gam[i * IMP_K + threadIdx.x];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_state_resume(ApState *st) {
+    if (threadIdx.x == 0) {
+        st->frozen = 0;
+        st->imp_abort = 0;
+    }
+}
+
+template <int T, int J, int KIND, bool PREF>
+hipError_t launch_imp_k(const ImpArgs &a, int grid, size_t lds, hipStream_t s) {
+    static bool attr_set = false;   // per process; the attribute is per function
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_row_imp<T, J, KIND, PREF>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsImp);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_row_imp<T, J, KIND, PREF><<<grid, T, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int T, int J, bool PREF>
+hipError_t launch_imp_tj(int kind, const ImpArgs &a, const PassPlan &pl, hipStream_t s) {
+    switch (kind) {
+    case IMP_FULL: return launch_imp_k<T, J, IMP_FULL, PREF>(a, pl.grid, pl.lds_bytes, s);
+    case IMP_PRO_COLD: return launch_imp_k<T, J, IMP_PRO_COLD, PREF>(a, pl.grid, pl.lds_bytes, s);
+    default: return launch_imp_k<T, J, IMP_PRO_WARM, PREF>(a, pl.grid, pl.lds_bytes, s);
+    }
+}
+
+template <int T, int J>
+hipError_t launch_imp_t(int kind, const ImpArgs &a, const PassPlan &pl, hipStream_t s) {
+    // prefetching variant whenever the current row of S fits next to the partials
+    if constexpr (J <= 5) {
+        if (pl.lds_bytes >= (size_t)32 * (size_t)((a.n + 3) / 4)) return launch_imp_tj<T, J, true>(kind, a, pl, s);
+    }
+    return launch_imp_tj<T, J, false>(kind, a, pl, s);
+}
+
 }  // namespace
 
 // Chunks (float4 per thread per row) instantiated for each workgroup size.
@@ -838,6 +1198,65 @@ hipError_t launch_finalize(const FinalArgs &a, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_sum2<<<1, 1024, 0, s>>>(a.contrib, a.n, a.sums);
+    return hipGetLastError();
+}
+
+
+bool imp_plan(int64_t n, int num_cus, PassPlan *pl) {
+    const int64_t q = (n + 3) / 4;
+    const int threads = n <= 4096 ? 256 : 1024;
+    const int maxj = threads == 256 ? 4 : 10;
+    PassPlan p{};
+    const int64_t g = n <= 4096 ? 2LL * num_cus : (int64_t)num_cus;
+    p.grid = (int)(n < g ? n : g);
+    p.threads = threads;
+    p.chunks = (int)((q + threads - 1) / threads);
+    if (p.chunks > maxj) return false;
+    const size_t with_s = (size_t)32 * (size_t)q, part_only = (size_t)16 * (size_t)q;
+    if (p.chunks <= 5 && with_s <= (size_t)kMaxDynLdsImp) p.lds_bytes = with_s;
+    else if (part_only <= (size_t)kMaxDynLdsImp) p.lds_bytes = part_only;
+    else return false;
+    *pl = p;
+    return true;
+}
+
+hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStream_t s) {
+    if (pl.threads == 256) {
+        switch (pl.chunks) {
+        case 1: return launch_imp_t<256, 1>(kind, a, pl, s);
+        case 2: return launch_imp_t<256, 2>(kind, a, pl, s);
+        case 3: return launch_imp_t<256, 3>(kind, a, pl, s);
+        case 4: return launch_imp_t<256, 4>(kind, a, pl, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (pl.threads != 1024) return hipErrorInvalidValue;
+    switch (pl.chunks) {
+    case 1: return launch_imp_t<1024, 1>(kind, a, pl, s);
+    case 2: return launch_imp_t<1024, 2>(kind, a, pl, s);
+    case 3: return launch_imp_t<1024, 3>(kind, a, pl, s);
+    case 4: return launch_imp_t<1024, 4>(kind, a, pl, s);
+    case 5: return launch_imp_t<1024, 5>(kind, a, pl, s);
+    case 6: return launch_imp_t<1024, 6>(kind, a, pl, s);
+    case 7: return launch_imp_t<1024, 7>(kind, a, pl, s);
+    case 8: return launch_imp_t<1024, 8>(kind, a, pl, s);
+    case 9: return launch_imp_t<1024, 9>(kind, a, pl, s);
+    case 10: return launch_imp_t<1024, 10>(kind, a, pl, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float lam, int32_t t,
+                                  const float *beta, const int32_t *cnt, const int32_t *col,
+                                  const float *gam, hipStream_t s) {
+    const float al = (float)(1.0 - std::pow((double)lam, (double)t));
+    const int g = n < 8192 ? n : 8192;
+    k_imp_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(S, R, ld, n, al, beta, cnt, col, gam);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_resume(ApState *st, hipStream_t s) {
+    k_state_resume<<<1, 64, 0, s>>>(st);
     return hipGetLastError();
 }
 

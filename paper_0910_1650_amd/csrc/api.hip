@@ -98,12 +98,16 @@ struct IterWs {
     uint8_t *eflag;
     ApState *st;
     float *R2;            // second responsibility buffer (ap_solve)
+    float *beta[2];       // implicit-R state by parity (ap_solve)
+    int32_t *cnt[2], *col[2];
+    float *gam[2];
     int32_t *ex, *nex;
     double *contrib, *sums;
 };
 
 struct IterLayout {
     size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, bytes;
+    size_t o_beta[2], o_cnt[2], o_col[2], o_gam[2];
 };
 
 IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
@@ -122,6 +126,12 @@ IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
     o.o_con = L.take(sizeof(double) * 2 * (size_t)n);
     o.o_sum = L.take(sizeof(double) * 2);
     o.o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
+    for (int q = 0; q < 2; ++q) {
+        o.o_beta[q] = second_r ? L.take(sizeof(float) * (size_t)n) : 0;
+        o.o_cnt[q] = second_r ? L.take(sizeof(int32_t) * (size_t)n) : 0;
+        o.o_col[q] = second_r ? L.take(sizeof(int32_t) * (size_t)n * IMP_K) : 0;
+        o.o_gam[q] = second_r ? L.take(sizeof(float) * (size_t)n * IMP_K) : 0;
+    }
     o.bytes = L.off;
     return o;
 }
@@ -145,6 +155,12 @@ apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const Pas
     w.contrib = reinterpret_cast<double *>(b + o.o_con);
     w.sums = reinterpret_cast<double *>(b + o.o_sum);
     w.R2 = second_r ? reinterpret_cast<float *>(b + o.o_r2) : nullptr;
+    for (int q = 0; q < 2; ++q) {
+        w.beta[q] = second_r ? reinterpret_cast<float *>(b + o.o_beta[q]) : nullptr;
+        w.cnt[q] = second_r ? reinterpret_cast<int32_t *>(b + o.o_cnt[q]) : nullptr;
+        w.col[q] = second_r ? reinterpret_cast<int32_t *>(b + o.o_col[q]) : nullptr;
+        w.gam[q] = second_r ? reinterpret_cast<float *>(b + o.o_gam[q]) : nullptr;
+    }
     return APX_OK;
 }
 
@@ -166,6 +182,41 @@ PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int6
     a.dec = dec;
     a.eflag = eflag;
     a.st = st;
+    a.row_begin = 0;
+    a.row_end = n;
+    return a;
+}
+
+// Implicit pass of iteration t (state R_t in parity t & 1); t = 0 is the
+// prologue, which needs the iteration number explicitly.
+ImpArgs imp_args(const float *S, float *A, int64_t n, int64_t ld, float lam, const IterWs &w,
+                 float *const buf[2], int32_t t, bool prologue, int kmax) {
+    ImpArgs a{};
+    const int pi = t & 1, po = (t + 1) & 1;
+    a.S = S;
+    a.A = A;
+    a.ld = ld;
+    a.n = (int32_t)n;
+    a.lam = lam;
+    a.tcol = w.tcol;
+    a.ccol = w.ccol;
+    a.partial = w.partial;
+    a.ldp = w.ldp;
+    a.rdiag = w.rdiag;
+    a.dec = prologue ? nullptr : w.dec;
+    a.eflag = prologue ? nullptr : w.eflag;
+    a.st = w.st;
+    a.beta_in = w.beta[pi];
+    a.cnt_in = w.cnt[pi];
+    a.col_in = w.col[pi];
+    a.gam_in = w.gam[pi];
+    a.beta_out = w.beta[po];
+    a.cnt_out = w.cnt[po];
+    a.col_out = w.col[po];
+    a.gam_out = w.gam[po];
+    a.Rx = buf[po];
+    a.kmax = kmax;
+    a.pass_t = prologue ? 0 : -1;
     a.row_begin = 0;
     a.row_end = n;
     return a;
@@ -194,8 +245,8 @@ namespace {
 // enqueued on ctx->stream, then copies the run state to the host and waits.
 // Returns APX_ENOTIMPL (and leaves nothing enqueued) when the capture itself
 // fails, so that the caller can run the chunk with plain launches.
-apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, const float *S, float *const buf[2], float *A,
-                       int64_t n, int64_t ld, float lam, const IterWs &w, int chunk, int32_t t0,
+apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const float *S, float *const buf[2],
+                       float *A, int64_t n, int64_t ld, float lam, const IterWs &w, int chunk, int32_t t0,
                        ApState *hst) {
     if (!ctx->cap) {
         HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking), "graph stream");
@@ -206,7 +257,8 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, const float *S, float *
     const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)(uintptr_t)buf[0], (uint64_t)(uintptr_t)buf[1],
                               (uint64_t)(uintptr_t)A, (uint64_t)n, (uint64_t)ld, lam_bits, (uint64_t)chunk,
                               (uint64_t)(t0 & 1), (uint64_t)(uintptr_t)w.st, (uint64_t)(uintptr_t)w.partial,
-                              (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.eflag, (uint64_t)pl.grid,
+                              (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.beta[0],
+                              (uint64_t)pl.grid | ((uint64_t)implicit << 32) | ((uint64_t)ctx->implicit_k << 40),
                               (uint64_t)pl.threads, (uint64_t)pl.lds_bytes};
     if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
         if (ctx->gexec) {
@@ -217,8 +269,13 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, const float *S, float *
         hipError_t e = hipSuccess;
         for (int u = 0; u < chunk && e == hipSuccess; ++u) {
             const int32_t t = t0 + u;
-            PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
-            e = launch_row_pass(pl, PASS_FULL, pf, ctx->cap);
+            if (implicit) {
+                e = launch_row_imp(pl, IMP_FULL, imp_args(S, A, n, ld, lam, w, buf, t, false, ctx->implicit_k),
+                                   ctx->cap);
+            } else {
+                PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
+                e = launch_row_pass(pl, PASS_FULL, pf, ctx->cap);
+            }
             if (e == hipSuccess) e = launch_col_reduce(col_args(w, n, w.st, 1), ctx->cap);
         }
         hipGraph_t g = nullptr;
@@ -289,6 +346,11 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
     }
     const char *gv = getenv("APX_GRAPHS");
     if (gv && gv[0] == '0') ctx->graphs = false;
+    const char *iv = getenv("APX_IMPLICIT_K");
+    if (iv && iv[0]) {
+        const int k = atoi(iv);
+        ctx->implicit_k = k < 0 ? 0 : (k > IMP_K ? IMP_K : k);
+    }
     const char *av = getenv("APX_AUTOTUNE");
     if (av && av[0] == '1') ctx->autotune = true;
     const char *tf = getenv("APX_TUNE_FILE");
@@ -323,6 +385,23 @@ apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream) {
 const char *apx_last_error(const apx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 size_t apx_workspace_bytes(const apx_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n) {
+    if (!ctx) return APX_EINVAL;
+    if (list_capacity < 0 || list_capacity > IMP_K)
+        return set_err(ctx, APX_EINVAL, "list capacity must be in [0, %d]", IMP_K);
+    if (min_n < 0) return set_err(ctx, APX_EINVAL, "min_n < 0");
+    ctx->implicit_k = list_capacity;
+    ctx->implicit_min_n = min_n;
+    return APX_OK;
+}
+
+apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters) {
+    if (!ctx || !implicit_iters || !explicit_iters) return APX_EINVAL;
+    *implicit_iters = ctx->last_imp_iters;
+    *explicit_iters = ctx->last_exp_iters;
+    return APX_OK;
+}
 
 apx_status apx_set_graphs(apx_ctx *ctx, int enable) {
     if (!ctx) return APX_EINVAL;
@@ -419,16 +498,29 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, s), "state init");
     HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
 
-    // R_t lives in buf[t & 1]; buf[0] is the caller's R.
+    // R_t lives in buf[t & 1]; buf[0] is the caller's R.  With R_0 = 0 (cold
+    // start or A_0 only) R is kept implicitly (ImpArgs) unless disabled.
     float *buf[2] = {R, w.R2};
-    PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, nullptr, nullptr, nullptr);
-    if (warm == APX_COLD) {
-        // R_1 from R_0 = A_0 = 0, then A_0 = 0 in memory (Eq. (1)).
-        HIP_TRY(launch_row_pass(pl, PASS_R_COLD, pr, s), "prologue");
-        HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+    PassPlan ipl{};
+    bool implicit = ctx->implicit_k > 0 && n >= ctx->implicit_min_n && warm != APX_WARM_AR &&
+                    imp_plan(n, ctx->num_cus, &ipl);
+    int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
+    if (implicit) {
+        HIP_TRY(launch_fill_f32_rows(w.beta[0], 1, n, n, 0.0f, s), "implicit state");
+        HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.cnt[0]), 4 * n, 0, s), "implicit state");
+        const ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, 0, true, ctx->implicit_k);
+        HIP_TRY(launch_row_imp(ipl, warm == APX_COLD ? IMP_PRO_COLD : IMP_PRO_WARM, ia, s), "prologue");
+        if (warm == APX_COLD) HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
     } else {
-        if (warm == APX_WARM_A) HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R_0");
-        HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
+        PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, nullptr, nullptr, nullptr);
+        if (warm == APX_COLD) {
+            // R_1 from R_0 = A_0 = 0, then A_0 = 0 in memory (Eq. (1)).
+            HIP_TRY(launch_row_pass(pl, PASS_R_COLD, pr, s), "prologue");
+            HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+        } else {
+            if (warm == APX_WARM_A) HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R_0");
+            HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
+        }
     }
     HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
 
@@ -456,7 +548,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         const int32_t t_first = t;
         bool done = false;
         if (use_graph && stop_at - t == chunk) {
-            const apx_status gs = graph_chunk(ctx, pl, S, buf, A, n, ld, lam, w, chunk, t, hst);
+            const apx_status gs = graph_chunk(ctx, implicit ? ipl : pl, implicit, S, buf, A, n, ld, lam, w,
+                                              chunk, t, hst);
             if (gs == APX_OK) {
                 t = stop_at;
                 done = true;
@@ -472,7 +565,12 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                                         w.eflag, w.st);
                 const int slot = t - t_first;
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
-                HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
+                if (implicit)
+                    HIP_TRY(launch_row_imp(ipl, IMP_FULL,
+                                           imp_args(S, A, n, ld, lam, w, buf, t, false, ctx->implicit_k), s),
+                            "row pass");
+                else
+                    HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
                 HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1), s), "column reduce");
             }
@@ -489,12 +587,34 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                 ctx->prof_launches += 1;
             }
         }
+        if (hst->frozen == 2) {
+            // A row's implicit list overflowed in pass t_a: R_{t_a+1} is made
+            // explicit (overflowed rows were written by the pass itself), its
+            // column vectors are rebuilt, and the run continues with explicit R.
+            const int32_t ta = hst->iter;
+            const int po = (ta + 1) & 1;
+            HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, lam, ta + 1, w.beta[po], w.cnt[po],
+                                           w.col[po], w.gam[po], s), "materialize R");
+            HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
+            HIP_TRY(launch_state_resume(w.st, s), "resume");
+            implicit = false;
+            imp_until = ta;
+            t = ta + 1;
+            continue;
+        }
         if (hst->frozen || t > params->max_iter) break;
     }
     const int32_t T = hst->iter;
     res->iterations = T;
     res->converged = hst->converged;
-    if (T & 1) HIP_TRY(launch_copy_rows(R, w.R2, n, n, ld, s), "copy R");
+    ctx->last_imp_iters = imp_until < T ? imp_until : T;
+    ctx->last_exp_iters = T - ctx->last_imp_iters;
+    if (implicit) {
+        HIP_TRY(launch_imp_materialize(S, R, ld, (int32_t)n, lam, T, w.beta[T & 1], w.cnt[T & 1], w.col[T & 1],
+                                       w.gam[T & 1], s), "materialize R");
+    } else if (T & 1) {
+        HIP_TRY(launch_copy_rows(R, w.R2, n, n, ld, s), "copy R");
+    }
 
     FinalArgs fa{};
     fa.S = S;

@@ -25,7 +25,8 @@ struct ApState {
     int32_t max_iter;
     int32_t conv_iter;
     int32_t last_nex;   // |E| of the last completed iteration
-    int32_t pad[7];
+    int32_t imp_abort;  // an implicit-R row overflowed its list (see ImpArgs)
+    int32_t pad[6];
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -89,6 +90,52 @@ hipError_t launch_fill_f32_rows(float *p, int64_t rows, int64_t cols, int64_t ld
 hipError_t launch_copy_rows(float *dst, const float *src, int64_t rows, int64_t cols, int64_t ld,
                             hipStream_t s);
 
+// Implicit responsibilities (ap_iter.hip).  With R_0 = 0 the damped Eq. (2)
+// unrolls to R_t(i,k) = alpha_t s(i,k) - beta_t(i) + gamma_t(i,k) with
+// alpha_t = 1 - lambda^t, beta_{t+1} = lambda beta_t + (1-lambda) v1_t,
+// gamma_{t+1}(i,k) = lambda gamma_t(i,k) + (1-lambda)(v1_t - v2_t)[k = k1_t],
+// where gamma_t(i,.) is non-zero only on the columns that were row i's
+// argmax of a+s at an earlier iteration: a short list per row.  State for
+// R_t lives in parity t & 1 of the state arrays.
+constexpr int IMP_K = 16;            // list capacity per row
+enum ImpKind : int { IMP_FULL = 0, IMP_PRO_COLD = 1, IMP_PRO_WARM = 2 };
+
+struct ImpArgs {
+    const float *S;
+    float *A;
+    int64_t ld;
+    int32_t n;
+    float lam;
+    const float *tcol, *ccol;   // column vectors of R_t (full passes)
+    float *partial;             // [gridDim.x][ldp] partials of max(0, R_{t+1})
+    int64_t ldp;
+    float *rdiag;               // r_{t+1}(k,k)
+    int32_t *dec;
+    uint8_t *eflag;
+    ApState *st;                // iteration counter, frozen flag, overflow flag
+    const float *beta_in;       // state of R_t
+    const int32_t *cnt_in, *col_in;
+    const float *gam_in;
+    float *beta_out;            // state of R_{t+1}
+    int32_t *cnt_out, *col_out;
+    float *gam_out;
+    float *Rx;                  // R_{t+1} rows written explicitly on list overflow
+    int32_t kmax;               // list capacity in use (<= IMP_K)
+    int32_t pass_t;             // t of this pass, or -1: t = st->iter + 1
+    int64_t row_begin, row_end;
+};
+// Plan of the implicit pass for n (same row -> workgroup map as plan_pass);
+// false when no implicit variant is instantiated for n.
+bool imp_plan(int64_t n, int num_cus, PassPlan *pl);
+hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStream_t s);
+// R (rows of the implicit state) = alpha_t S - beta 1^T + gamma; rows whose
+// state is -1 (overflowed) are left alone.
+hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float lam, int32_t t,
+                                  const float *beta, const int32_t *cnt, const int32_t *col,
+                                  const float *gam, hipStream_t s);
+// Clears the frozen and overflow flags after an overflow hand-over.
+hipError_t launch_state_resume(ApState *st, hipStream_t s);
+
 // Finalize: labels and FP64 dpsim / expref.
 struct FinalArgs {
     const float *S;
@@ -133,6 +180,11 @@ struct apx_ctx {
     hipEvent_t join = nullptr;        // orders the private stream after `stream`
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey[16] = {};
+    // implicit responsibilities: list capacity in use (0 = explicit R only)
+    int implicit_k = apx::IMP_K;
+    int64_t implicit_min_n = 8192;    // smaller problems run explicit R (faster there)
+    int32_t last_imp_iters = 0;       // iterations of the last ap_solve run with implicit R
+    int32_t last_exp_iters = 0;       // ... and with explicit R
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
     std::vector<apx::TuneEntry> tune;
