@@ -757,6 +757,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
     __shared__ int st_cnt[3];
+    __shared__ float st_ci[3];
     extern __shared__ float4 dyn[];
     const int q = (p.n + 3) >> 2;
     float4 *lpart = dyn;                         // column partials, q entries
@@ -786,12 +787,23 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         if (j < J - 1 || last_in) lpart[j * T + tid] = z4;
     int my_nex = 0, my_changed = 0;
 
-    auto load_state = [&](int64_t i) {
+    // Row state is fetched into a register one row ahead (by threads
+    // 0..2K+2) and written to its LDS slot later, so the loads overlap a row.
+    auto fetch_state = [&](int64_t i) -> uint32_t {
+        if (tid < IMP_K) return (uint32_t)p.col_in[i * IMP_K + tid];
+        if (tid < 2 * IMP_K) return __float_as_uint(p.gam_in[i * IMP_K + tid - IMP_K]);
+        if (tid == 2 * IMP_K) return __float_as_uint(p.beta_in[i]);
+        if (tid == 2 * IMP_K + 1) return (uint32_t)p.cnt_in[i];
+        if (tid == 2 * IMP_K + 2 && DO_A) return __float_as_uint(p.ccol[i]);
+        return 0u;
+    };
+    auto put_state = [&](int64_t i, uint32_t v) {
         const int sl = (int)(i % 3);
-        if (tid < IMP_K) st_col[sl][tid] = p.col_in[i * IMP_K + tid];
-        else if (tid < 2 * IMP_K) st_gam[sl][tid - IMP_K] = p.gam_in[i * IMP_K + tid - IMP_K];
-        else if (tid == 2 * IMP_K) st_beta[sl] = p.beta_in[i];
-        else if (tid == 2 * IMP_K + 1) st_cnt[sl] = p.cnt_in[i];
+        if (tid < IMP_K) st_col[sl][tid] = (int)v;
+        else if (tid < 2 * IMP_K) st_gam[sl][tid - IMP_K] = __uint_as_float(v);
+        else if (tid == 2 * IMP_K) st_beta[sl] = __uint_as_float(v);
+        else if (tid == 2 * IMP_K + 1) st_cnt[sl] = (int)v;
+        else if (tid == 2 * IMP_K + 2) st_ci[sl] = __uint_as_float(v);
     };
     // The prefetching variant holds the next row's S and A in registers; the
     // other (long rows) holds only S and reads A chunk by chunk.
@@ -808,7 +820,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         }
     };
     if (r0 < r1) {
-        load_state(r0);
+        put_state(r0, fetch_state(r0));
         load_row(r0);
     }
     __syncthreads();
@@ -823,6 +835,8 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         // to registers (local index 4*chunk + element, gamma, list slot)
         const float beta = st_beta[sl];
         const int cnt = st_cnt[sl];
+        uint32_t next_state = 0u;
+        if constexpr (PREF) next_state = (i + 1 < r1) ? fetch_state(i + 1) : 0u;
         int own_le[NOWN], own_q[NOWN];
         float own_g[NOWN];
 #pragma unroll
@@ -847,7 +861,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             }
         }
         float ci = 0.0f;
-        if constexpr (DO_A) ci = p.ccol[ii];
+        if constexpr (DO_A) ci = st_ci[sl];
         float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
         int l1 = -1, dl = -1;
 #pragma unroll
@@ -890,8 +904,12 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         }
         __builtin_amdgcn_sched_barrier(0);
         if (i + 1 < r1) {
-            load_state(i + 1);
-            if constexpr (PREF) load_row(i + 1);
+            if constexpr (PREF) {
+                put_state(i + 1, next_state);
+                load_row(i + 1);
+            } else {
+                put_state(i + 1, fetch_state(i + 1));
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
 
