@@ -62,11 +62,16 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
     const int64_t row0 = bi * BM, col0 = bj * BM;
 
     __shared__ float smem[BM * (BM + 1)];          // 66 KB: staging, then the C tile
+    __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
     constexpr int LDA = BM + 1;                     // padded: conflict-free transposed stores
     float *As = smem;                               // [KB][LDA]
     float *Bs = smem + KB * LDA;                    // [KB][LDA]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    for (int e = tid; e < BM; e += NT) {
+        nr[e] = row0 + e < a.n ? a.nrm[row0 + e] : 0.0f;
+        nc[e] = col0 + e < a.n ? a.nrm[col0 + e] : 0.0f;
+    }
 
     v16f acc[2][2];
 #pragma unroll
@@ -119,30 +124,52 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
 
     uint32_t kmin = 0xffffffffu, kmax = 0u;
     const bool diag_tile = (bi == bj);
-    // Direct tile: rows row0+m, columns col0+c.  On a diagonal tile the value
-    // at (m,c) is taken from the upper entry min/max(m,c) so it is symmetric.
-    for (int e = tid; e < BM * BM; e += NT) {
-        const int m = e / BM, c = e % BM;
+    // Direct tile, four columns per store: rows row0+m, columns col0+c.  On a
+    // diagonal tile the value at (m,c) is taken from the upper entry
+    // min/max(m,c) so it is symmetric.  The diagonal element itself gets a
+    // value too; the preference pass overwrites it.
+    for (int e = tid; e < BM * BM / 4; e += NT) {
+        const int m = e / (BM / 4), c = (e % (BM / 4)) * 4;
         const int64_t i = row0 + m, k = col0 + c;
-        if (i >= a.n || k >= a.n || i == k) continue;
-        float g = smem[m * LDC + c];
-        if (diag_tile && m > c) g = smem[c * LDC + m];
-        const float s = 2.0f * g - (a.nrm[i] + a.nrm[k]);
-        a.S[i * a.ld + k] = s;
-        if (!diag_tile || m < c) {
-            const uint32_t key = fkey(s);
-            kmin = min(kmin, key);
-            kmax = max(kmax, key);
+        if (i >= a.n || k >= a.n) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float g = smem[m * LDC + c + q];
+            if (diag_tile && m > c + q) g = smem[(c + q) * LDC + m];
+            v[q] = 2.0f * g - (nr[m] + nc[c + q]);
+            if (k + q < a.n && i != k + q && (!diag_tile || m < c + q)) {
+                const uint32_t key = fkey(v[q]);
+                kmin = min(kmin, key);
+                kmax = max(kmax, key);
+            }
+        }
+        float *dst = a.S + i * a.ld + k;
+        if (k + 3 < a.n) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k + q < a.n) dst[q] = v[q];
         }
     }
     if (!diag_tile) {
-        // Mirror: S[col0+c][row0+m] = s(row0+m, col0+c).
-        for (int e = tid; e < BM * BM; e += NT) {
-            const int c = e / BM, m = e % BM;
+        // Mirror, four rows per store: S[col0+c][row0+m..m+3] = s(row0+m.., col0+c).
+        for (int e = tid; e < BM * BM / 4; e += NT) {
+            const int c = e / (BM / 4), m = (e % (BM / 4)) * 4;
             const int64_t i = row0 + m, k = col0 + c;
             if (i >= a.n || k >= a.n) continue;
-            const float s = 2.0f * smem[m * LDC + c] - (a.nrm[i] + a.nrm[k]);
-            a.S[k * a.ld + i] = s;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = 2.0f * smem[(m + q) * LDC + c] - (nr[m + q] + nc[c]);
+            float *dst = a.S + k * a.ld + i;
+            if (i + 3 < a.n) {
+                *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i + q < a.n) dst[q] = v[q];
+            }
         }
     }
     // Block min/max of the upper off-diagonal entries.
