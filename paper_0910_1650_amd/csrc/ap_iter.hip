@@ -528,6 +528,12 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
     }
 }
 
+// alpha_t = 1 - lambda^t of the implicit responsibilities, from one function
+// of t so every pass and the materialisation use the same rounding.
+__device__ __forceinline__ float imp_alpha(float lam, int t) {
+    return (float)(1.0 - pow((double)lam, (double)t));
+}
+
 // Column sums: 64 columns per workgroup, 16 slices of the partial rows per
 // column summed in FP64, slices combined in a fixed order.
 __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
@@ -551,6 +557,10 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
         ApState *st = a.st;
         const int t = st->iter + 1;
         const int same = (t > 1) && (st->changed == 0);
+        // alphas of the implicit-R passes t+1 and t+2 (the pass just run was t)
+        st->imp_al_prev = st->imp_al;
+        st->imp_al = st->imp_al1;
+        st->imp_al1 = imp_alpha(st->imp_lam, t + 2);
         const int run = same ? st->run + 1 : 1;
         st->iter = t;
         st->run = run;
@@ -568,11 +578,15 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
     }
 }
 
-__global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter) {
+__global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam) {
     if (threadIdx.x == 0) {
         ApState s{};
         s.max_iter = max_iter;
         s.conv_iter = conv_iter;
+        s.imp_lam = lam;
+        s.imp_al = imp_alpha(lam, 1);
+        s.imp_al1 = imp_alpha(lam, 2);
+        s.imp_al_prev = 0.0f;
         *st = s;
     }
 }
@@ -732,12 +746,9 @@ hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t
 // ---- implicit responsibilities ---------------------------------------------
 // R_t(i,k) = alpha_t s(i,k) - beta_t(i) + gamma_t(i,k), see ImpArgs.  A pass
 // reads S and A and writes A (12 bytes per element instead of 20); R is
-// rebuilt in registers from the row's state.  alpha_t comes from one
-// function of t, so the partials formed for R_{t+1} in pass t and the values
-// pass t+1 rebuilds are the same numbers.
-__device__ __forceinline__ float imp_alpha(float lam, int t) {
-    return (float)(1.0 - pow((double)lam, (double)t));
-}
+// rebuilt in registers from the row's state.  alpha_t, alpha_{t+1} are read
+// from the run state, so the partials formed for R_{t+1} in pass t and the
+// values pass t+1 rebuilds use the same numbers.
 
 template <int T, int J, int KIND, bool PREF>
 __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
@@ -778,9 +789,23 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     const int cl = ((J - 1) * T + tid) * 4;
     const bool last_in = cl < n;
     const bool last_full = cl + 3 < n;
-    const int tpass = p.pass_t >= 0 ? p.pass_t : p.st->iter + 1;
-    const float al = imp_alpha(lam, tpass);      // alpha_t
-    const float al1 = imp_alpha(lam, tpass + 1); // alpha_{t+1}
+    // alpha_t, alpha_{t+1} and the iteration come from the run state (kept
+    // there by the column reduce), so replays of a captured pass stay valid.
+    const int tpass = p.prologue ? 0 : p.st->iter + 1;
+    const float al = p.prologue ? 0.0f : p.st->imp_al;       // alpha_t
+    const float al1 = p.prologue ? p.st->imp_al : p.st->imp_al1;  // alpha_{t+1}
+    const ImpLayout L = imp_layout(n);
+    const char *sin = p.state + (int64_t)(tpass & 1) * p.stride;
+    char *sout = p.state + (int64_t)((tpass + 1) & 1) * p.stride;
+    const float *beta_in = reinterpret_cast<const float *>(sin + L.beta);
+    const int32_t *cnt_in = reinterpret_cast<const int32_t *>(sin + L.cnt);
+    const int32_t *col_in = reinterpret_cast<const int32_t *>(sin + L.col);
+    const float *gam_in = reinterpret_cast<const float *>(sin + L.gam);
+    float *beta_out = reinterpret_cast<float *>(sout + L.beta);
+    int32_t *cnt_out = reinterpret_cast<int32_t *>(sout + L.cnt);
+    int32_t *col_out = reinterpret_cast<int32_t *>(sout + L.col);
+    float *gam_out = reinterpret_cast<float *>(sout + L.gam);
+    float *const Rx_base = p.Rx[(tpass + 1) & 1];
 
 #pragma unroll
     for (int j = 0; j < J; ++j)
@@ -790,10 +815,10 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     // Row state is fetched into a register one row ahead (by threads
     // 0..2K+2) and written to its LDS slot later, so the loads overlap a row.
     auto fetch_state = [&](int64_t i) -> uint32_t {
-        if (tid < IMP_K) return (uint32_t)p.col_in[i * IMP_K + tid];
-        if (tid < 2 * IMP_K) return __float_as_uint(p.gam_in[i * IMP_K + tid - IMP_K]);
-        if (tid == 2 * IMP_K) return __float_as_uint(p.beta_in[i]);
-        if (tid == 2 * IMP_K + 1) return (uint32_t)p.cnt_in[i];
+        if (tid < IMP_K) return (uint32_t)col_in[i * IMP_K + tid];
+        if (tid < 2 * IMP_K) return __float_as_uint(gam_in[i * IMP_K + tid - IMP_K]);
+        if (tid == 2 * IMP_K) return __float_as_uint(beta_in[i]);
+        if (tid == 2 * IMP_K + 1) return (uint32_t)cnt_in[i];
         if (tid == 2 * IMP_K + 2 && DO_A) return __float_as_uint(p.ccol[i]);
         return 0u;
     };
@@ -829,6 +854,8 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         const int ii = (int)i;
         const int sl = (int)(i % 3);
         const ColOwner dg = owner_of<T>(ii, tid);
+        const int dle = dg.mine ? 4 * dg.j + dg.e : -1;     // local index of the diagonal
+        const bool wave_diag = __any(dg.mine);
         float *Arow = p.A + i * ld;
         const rsrc_t a_rs = row_rsrc(Arow, ld);
         // state of R_t for this row; the listed columns this thread owns go
@@ -860,6 +887,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
                 ++nown;
             }
         }
+        const bool wave_own = __any(nown > 0);
         float ci = 0.0f;
         if constexpr (DO_A) ci = st_ci[sl];
         float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
@@ -877,17 +905,29 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             }
             float4 r;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float rv = al * f4get(sv, e) - beta;
-                if (nown > 0) {
+            for (int e = 0; e < 4; ++e) f4set(r, e, al * f4get(sv, e) - beta);
+            if (wave_own) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) rv = rv + own_g[o];
-                }
-                f4set(r, e, rv);
+                        if (own_le[o] == 4 * j + e) f4set(r, e, f4get(r, e) + own_g[o]);
             }
             if constexpr (DO_A) {
-                chunk_avail(a, r, ld4(p.tcol + c), ci, j, dg, c, n, full, lam, oml, dv, dl);
+                const float4 tv = ld4(p.tcol + c);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (full || c + e < n) {
+                        float upd = fminf(0.0f, f4get(tv, e) - fmaxf(0.0f, f4get(r, e)));
+                        if (wave_diag && dle == 4 * j + e) upd = ci;
+                        const float an = lam * f4get(a, e) + oml * upd;
+                        f4set(a, e, an);
+                        const float v = an + f4get(r, e);
+                        const bool gt = v > dv;
+                        dl = gt ? 4 * j + e : dl;
+                        dv = gt ? v : dv;
+                    }
+                }
                 store_chunk(Arow, a_rs, voff, j * T * 16, c, n, full, a);
             }
 #pragma unroll
@@ -946,20 +986,20 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         }
         const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);
         if (tid == 0) {
-            p.beta_out[ii] = beta1;
+            beta_out[ii] = beta1;
             if (ovf) {
-                p.cnt_out[ii] = -1;
+                cnt_out[ii] = -1;
                 p.st->imp_abort = 1;
             } else {
                 for (int qq = 0; qq < cnt; ++qq) {
-                    p.col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
-                    p.gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
+                    col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
+                    gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
                 }
                 if (pos1 < 0) {
-                    p.col_out[(int64_t)ii * IMP_K + cnt] = k1;
-                    p.gam_out[(int64_t)ii * IMP_K + cnt] = d;
+                    col_out[(int64_t)ii * IMP_K + cnt] = k1;
+                    gam_out[(int64_t)ii * IMP_K + cnt] = d;
                 }
-                p.cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
+                cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
             }
         }
         float own_g1[NOWN];
@@ -967,10 +1007,11 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         for (int o = 0; o < NOWN; ++o) own_g1[o] = lam * own_g[o] + (own_q[o] == pos1 ? d : 0.0f);
         const bool k1_mine = pos1 < 0 && k1_owner == tid;
         const int k1_le = ((k1 >> 2) / T) * 4 + (k1 & 3);
+        const bool wave_k1 = __any(k1_mine);
 
         // Column partials of max(0, R_{t+1}); on overflow the row of R_{t+1}
         // is also written explicitly.
-        float *Rx = p.Rx + i * ld;
+        float *Rx = Rx_base + i * ld;
         const rsrc_t x_rs = row_rsrc(Rx, ld);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -980,20 +1021,32 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             float4 sv;
             if constexpr (PREF) sv = ls[j * T + tid];
             else sv = s4[j];
-            float4 pos;
+            float4 rv4;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = c + e;
-                float rv = al1 * f4get(sv, e) - beta1;
-                if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
-                if (nown > 0) {
+            for (int e = 0; e < 4; ++e) f4set(rv4, e, al1 * f4get(sv, e) - beta1);
+            if (wave_k1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k1_mine && k1_le == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + d);
+            }
+            if (wave_own) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
-                }
-                const bool diag = dg.mine && dg.j == j && dg.e == e;
-                f4set(pos, e, (diag || !(full || k < n)) ? 0.0f : fmaxf(0.0f, rv));
-                if (diag) p.rdiag[ii] = rv;
+                        if (own_le[o] == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + own_g1[o]);
+            }
+            float4 pos;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                f4set(pos, e, (full || c + e < n) ? fmaxf(0.0f, f4get(rv4, e)) : 0.0f);
+            if (wave_diag) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (dle == 4 * j + e) {
+                        f4set(pos, e, 0.0f);
+                        p.rdiag[ii] = f4get(rv4, e);
+                    }
             }
             float4 acc = lpart[j * T + tid];
             add4(acc, pos);
@@ -1041,12 +1094,17 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     }
 }
 
-// R(i,k) = alpha_t s(i,k) - beta(i) + gamma(i,k) for every row with a list;
+// R(i,k) = alpha s(i,k) - beta(i) + gamma(i,k) for every row with a list;
 // the same expression (and rounding) as the passes use.
-__global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float al,
-                                  const float *beta, const int32_t *cnt, const int32_t *col,
-                                  const float *gam) {
+__global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
+                                  const char *state) {
 #pragma clang fp contract(off)
+    const ImpLayout L = imp_layout(n);
+    const float *beta = reinterpret_cast<const float *>(state + L.beta);
+    const int32_t *cnt = reinterpret_cast<const int32_t *>(state + L.cnt);
+    const int32_t *col = reinterpret_cast<const int32_t *>(state + L.col);
+    const float *gam = reinterpret_cast<const float *>(state + L.gam);
+    const float al = *alpha;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int c = cnt[i];
         if (c < 0) continue;
@@ -1183,8 +1241,8 @@ hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, hipStream_t s) {
-    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter);
+hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s) {
+    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter, lam);
     return hipGetLastError();
 }
 
@@ -1231,7 +1289,10 @@ bool imp_plan(int64_t n, int num_cus, PassPlan *pl) {
     p.chunks = (int)((q + threads - 1) / threads);
     if (p.chunks > maxj) return false;
     const size_t with_s = (size_t)32 * (size_t)q, part_only = (size_t)16 * (size_t)q;
-    if (p.chunks <= 5 && with_s <= (size_t)kMaxDynLdsImp) p.lds_bytes = with_s;
+    // APX_IMP_PREFETCH=0 keeps S out of LDS (the non-prefetching variant; cross-checks)
+    const char *v = getenv("APX_IMP_PREFETCH");
+    const bool pref = !(v && v[0] == '0');
+    if (pref && p.chunks <= 5 && with_s <= (size_t)kMaxDynLdsImp) p.lds_bytes = with_s;
     else if (part_only <= (size_t)kMaxDynLdsImp) p.lds_bytes = part_only;
     else return false;
     *pl = p;
@@ -1264,12 +1325,10 @@ hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStr
     }
 }
 
-hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float lam, int32_t t,
-                                  const float *beta, const int32_t *cnt, const int32_t *col,
-                                  const float *gam, hipStream_t s) {
-    const float al = (float)(1.0 - std::pow((double)lam, (double)t));
+hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
+                                  const char *state_parity, hipStream_t s) {
     const int g = n < 8192 ? n : 8192;
-    k_imp_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(S, R, ld, n, al, beta, cnt, col, gam);
+    k_imp_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(S, R, ld, n, alpha, state_parity);
     return hipGetLastError();
 }
 

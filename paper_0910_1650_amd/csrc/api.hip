@@ -98,16 +98,14 @@ struct IterWs {
     uint8_t *eflag;
     ApState *st;
     float *R2;            // second responsibility buffer (ap_solve)
-    float *beta[2];       // implicit-R state by parity (ap_solve)
-    int32_t *cnt[2], *col[2];
-    float *gam[2];
+    char *imp;            // implicit-R state, two parities (ap_solve)
+    int64_t imp_stride;
     int32_t *ex, *nex;
     double *contrib, *sums;
 };
 
 struct IterLayout {
-    size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, bytes;
-    size_t o_beta[2], o_cnt[2], o_col[2], o_gam[2];
+    size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, o_imp, bytes;
 };
 
 IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
@@ -126,12 +124,7 @@ IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
     o.o_con = L.take(sizeof(double) * 2 * (size_t)n);
     o.o_sum = L.take(sizeof(double) * 2);
     o.o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
-    for (int q = 0; q < 2; ++q) {
-        o.o_beta[q] = second_r ? L.take(sizeof(float) * (size_t)n) : 0;
-        o.o_cnt[q] = second_r ? L.take(sizeof(int32_t) * (size_t)n) : 0;
-        o.o_col[q] = second_r ? L.take(sizeof(int32_t) * (size_t)n * IMP_K) : 0;
-        o.o_gam[q] = second_r ? L.take(sizeof(float) * (size_t)n * IMP_K) : 0;
-    }
+    o.o_imp = second_r ? L.take(2 * (size_t)imp_layout(n).stride) : 0;
     o.bytes = L.off;
     return o;
 }
@@ -155,12 +148,8 @@ apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const Pas
     w.contrib = reinterpret_cast<double *>(b + o.o_con);
     w.sums = reinterpret_cast<double *>(b + o.o_sum);
     w.R2 = second_r ? reinterpret_cast<float *>(b + o.o_r2) : nullptr;
-    for (int q = 0; q < 2; ++q) {
-        w.beta[q] = second_r ? reinterpret_cast<float *>(b + o.o_beta[q]) : nullptr;
-        w.cnt[q] = second_r ? reinterpret_cast<int32_t *>(b + o.o_cnt[q]) : nullptr;
-        w.col[q] = second_r ? reinterpret_cast<int32_t *>(b + o.o_col[q]) : nullptr;
-        w.gam[q] = second_r ? reinterpret_cast<float *>(b + o.o_gam[q]) : nullptr;
-    }
+    w.imp = second_r ? b + o.o_imp : nullptr;
+    w.imp_stride = imp_layout(n).stride;
     return APX_OK;
 }
 
@@ -187,12 +176,11 @@ PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int6
     return a;
 }
 
-// Implicit pass of iteration t (state R_t in parity t & 1); t = 0 is the
-// prologue, which needs the iteration number explicitly.
+// Implicit pass (state R_t in parity t & 1, t from the run state); the
+// prologue is the t = 0 pass.
 ImpArgs imp_args(const float *S, float *A, int64_t n, int64_t ld, float lam, const IterWs &w,
-                 float *const buf[2], int32_t t, bool prologue, int kmax) {
+                 float *const buf[2], bool prologue, int kmax) {
     ImpArgs a{};
-    const int pi = t & 1, po = (t + 1) & 1;
     a.S = S;
     a.A = A;
     a.ld = ld;
@@ -206,17 +194,12 @@ ImpArgs imp_args(const float *S, float *A, int64_t n, int64_t ld, float lam, con
     a.dec = prologue ? nullptr : w.dec;
     a.eflag = prologue ? nullptr : w.eflag;
     a.st = w.st;
-    a.beta_in = w.beta[pi];
-    a.cnt_in = w.cnt[pi];
-    a.col_in = w.col[pi];
-    a.gam_in = w.gam[pi];
-    a.beta_out = w.beta[po];
-    a.cnt_out = w.cnt[po];
-    a.col_out = w.col[po];
-    a.gam_out = w.gam[po];
-    a.Rx = buf[po];
+    a.state = w.imp;
+    a.stride = w.imp_stride;
+    a.Rx[0] = buf[0];
+    a.Rx[1] = buf[1];
     a.kmax = kmax;
-    a.pass_t = prologue ? 0 : -1;
+    a.prologue = prologue ? 1 : 0;
     a.row_begin = 0;
     a.row_end = n;
     return a;
@@ -257,7 +240,7 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const fl
     const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)(uintptr_t)buf[0], (uint64_t)(uintptr_t)buf[1],
                               (uint64_t)(uintptr_t)A, (uint64_t)n, (uint64_t)ld, lam_bits, (uint64_t)chunk,
                               (uint64_t)(t0 & 1), (uint64_t)(uintptr_t)w.st, (uint64_t)(uintptr_t)w.partial,
-                              (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.beta[0],
+                              (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.imp,
                               (uint64_t)pl.grid | ((uint64_t)implicit << 32) | ((uint64_t)ctx->implicit_k << 40),
                               (uint64_t)pl.threads, (uint64_t)pl.lds_bytes};
     if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
@@ -270,7 +253,7 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const fl
         for (int u = 0; u < chunk && e == hipSuccess; ++u) {
             const int32_t t = t0 + u;
             if (implicit) {
-                e = launch_row_imp(pl, IMP_FULL, imp_args(S, A, n, ld, lam, w, buf, t, false, ctx->implicit_k),
+                e = launch_row_imp(pl, IMP_FULL, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k),
                                    ctx->cap);
             } else {
                 PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
@@ -495,7 +478,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
-    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, s), "state init");
+    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, lam, s), "state init");
     HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
 
     // R_t lives in buf[t & 1]; buf[0] is the caller's R.  With R_0 = 0 (cold
@@ -506,9 +489,12 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                     imp_plan(n, ctx->num_cus, &ipl);
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
     if (implicit) {
-        HIP_TRY(launch_fill_f32_rows(w.beta[0], 1, n, n, 0.0f, s), "implicit state");
-        HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.cnt[0]), 4 * n, 0, s), "implicit state");
-        const ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, 0, true, ctx->implicit_k);
+        // parity 0 holds R_0 = 0: beta = 0 and empty lists
+        const ImpLayout il = imp_layout(n);
+        HIP_TRY(launch_fill_f32_rows(reinterpret_cast<float *>(w.imp + il.beta), 1, n, n, 0.0f, s),
+                "implicit state");
+        HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.imp + il.cnt), 4 * n, 0, s), "implicit state");
+        const ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, true, ctx->implicit_k);
         HIP_TRY(launch_row_imp(ipl, warm == APX_COLD ? IMP_PRO_COLD : IMP_PRO_WARM, ia, s), "prologue");
         if (warm == APX_COLD) HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
     } else {
@@ -567,7 +553,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
                 if (implicit)
                     HIP_TRY(launch_row_imp(ipl, IMP_FULL,
-                                           imp_args(S, A, n, ld, lam, w, buf, t, false, ctx->implicit_k), s),
+                                           imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k), s),
                             "row pass");
                 else
                     HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
@@ -593,8 +579,9 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             // column vectors are rebuilt, and the run continues with explicit R.
             const int32_t ta = hst->iter;
             const int po = (ta + 1) & 1;
-            HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, lam, ta + 1, w.beta[po], w.cnt[po],
-                                           w.col[po], w.gam[po], s), "materialize R");
+            // alpha_{t_a+1} is the run state's current alpha after the reduce of pass t_a
+            HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, &w.st->imp_al,
+                                           w.imp + po * w.imp_stride, s), "materialize R");
             HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
             HIP_TRY(launch_state_resume(w.st, s), "resume");
             implicit = false;
@@ -610,8 +597,9 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     ctx->last_imp_iters = imp_until < T ? imp_until : T;
     ctx->last_exp_iters = T - ctx->last_imp_iters;
     if (implicit) {
-        HIP_TRY(launch_imp_materialize(S, R, ld, (int32_t)n, lam, T, w.beta[T & 1], w.cnt[T & 1], w.col[T & 1],
-                                       w.gam[T & 1], s), "materialize R");
+        // alpha_T is the previous alpha after the reduce of pass T
+        HIP_TRY(launch_imp_materialize(S, R, ld, (int32_t)n, &w.st->imp_al_prev,
+                                       w.imp + (T & 1) * w.imp_stride, s), "materialize R");
     } else if (T & 1) {
         HIP_TRY(launch_copy_rows(R, w.R2, n, n, ld, s), "copy R");
     }

@@ -26,7 +26,11 @@ struct ApState {
     int32_t conv_iter;
     int32_t last_nex;   // |E| of the last completed iteration
     int32_t imp_abort;  // an implicit-R row overflowed its list (see ImpArgs)
-    int32_t pad[6];
+    float imp_lam;      // damping of the run
+    float imp_al;       // alpha_t for the next full pass t (1 - lambda^t)
+    float imp_al1;      // alpha_{t+1}
+    float imp_al_prev;  // alpha of the last full pass that ran
+    int32_t pad[2];
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -83,7 +87,7 @@ PassPlan plan_pass(int64_t n, int num_cus);
 PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds);
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);
 hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s);
-hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, hipStream_t s);
+hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f32_rows(float *p, int64_t rows, int64_t cols, int64_t ld, float v,
                                 hipStream_t s);
@@ -113,26 +117,38 @@ struct ImpArgs {
     int32_t *dec;
     uint8_t *eflag;
     ApState *st;                // iteration counter, frozen flag, overflow flag
-    const float *beta_in;       // state of R_t
-    const int32_t *cnt_in, *col_in;
-    const float *gam_in;
-    float *beta_out;            // state of R_{t+1}
-    int32_t *cnt_out, *col_out;
-    float *gam_out;
-    float *Rx;                  // R_{t+1} rows written explicitly on list overflow
+    char *state;                // row state, two parities of `stride` bytes each (ImpLayout)
+    int64_t stride;
+    float *Rx[2];               // R_{t+1} rows written explicitly on list overflow, by parity of t+1
     int32_t kmax;               // list capacity in use (<= IMP_K)
-    int32_t pass_t;             // t of this pass, or -1: t = st->iter + 1
+    int32_t prologue;           // 1: the t = 0 pass (alpha_0 = 0, alpha_1 from st)
     int64_t row_begin, row_end;
 };
+// Byte layout of one parity of the implicit-R state for n rows: beta (n
+// floats), list length (n ints, -1 after an overflow), columns (n x IMP_K
+// ints), gammas (n x IMP_K floats).
+struct ImpLayout {
+    int64_t beta, cnt, col, gam, stride;
+};
+// Each part starts on a 256-byte boundary.
+__host__ __device__ inline ImpLayout imp_layout(int64_t n) {
+    const int64_t a = (4 * n + 255) & ~int64_t(255), b = (4 * n * IMP_K + 255) & ~int64_t(255);
+    ImpLayout L{};
+    L.beta = 0;
+    L.cnt = a;
+    L.col = 2 * a;
+    L.gam = 2 * a + b;
+    L.stride = 2 * a + 2 * b;
+    return L;
+}
 // Plan of the implicit pass for n (same row -> workgroup map as plan_pass);
 // false when no implicit variant is instantiated for n.
 bool imp_plan(int64_t n, int num_cus, PassPlan *pl);
 hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStream_t s);
 // R (rows of the implicit state) = alpha_t S - beta 1^T + gamma; rows whose
 // state is -1 (overflowed) are left alone.
-hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, float lam, int32_t t,
-                                  const float *beta, const int32_t *cnt, const int32_t *col,
-                                  const float *gam, hipStream_t s);
+hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
+                                  const char *state_parity, hipStream_t s);
 // Clears the frozen and overflow flags after an overflow hand-over.
 hipError_t launch_state_resume(ApState *st, hipStream_t s);
 
