@@ -206,7 +206,7 @@ def main():
     for s in range(args.steps):
         _, res = step()
         iters += res.iterations
-        ni, ne = apx.apx_last_solve_info()
+        ni, ne, _ = apx.apx_last_solve_info()
         imp_iters += ni
         exp_iters += ne
         results.append(res)

@@ -90,9 +90,26 @@ size_t apx_workspace_bytes(const apx_ctx *ctx);
  * order). */
 apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n);
 
+/* apx_set_implicit_a -- exception list capacity of the implicit
+ * availabilities used by ap_solve on a cold start (A_0 = 0) together with
+ * implicit R.  By Eq. (3) with damping, every off-diagonal a(i,k) whose
+ * responsibility r(i,k) has never been positive equals one value per column,
+ * acol_t(k) = lambda acol_{t-1}(k) + (1 - lambda) min(0, r(k,k) + sum_{i' != k}
+ * max(0, r(i',k))), and by Eq. (4) the diagonal is a column vector as well.
+ * Each row keeps the other elements (columns where its responsibility was
+ * ever positive) as up to list_capacity (column, value) pairs, so an
+ * iteration reads S and writes no matrix (4 bytes per element).  When a row
+ * needs more entries, A is made explicit and the run continues with
+ * explicit A.  0 = explicit A; default 1024 (the maximum); the environment
+ * variable APX_IMPLICIT_A sets it at context creation.  A is the same
+ * arithmetic as the explicit update, element for element. */
+apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity);
+
 /* apx_last_solve_info -- how many iterations of the last ap_solve on this
- * context ran with implicit R and how many with explicit R. */
-apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters);
+ * context ran with implicit R and how many with explicit R; and (nullable)
+ * how many ran with implicit A. */
+apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters,
+                               int32_t *implicit_a_iters);
 
 /* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP
  * graph (enable = 1, the default; the environment variable APX_GRAPHS=0

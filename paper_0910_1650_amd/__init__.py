@@ -64,7 +64,8 @@ SIGNATURES = {
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
-    "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "apx_set_implicit_a": (ctypes.c_int, [_P, _I32]),
+    "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "apx_autotune": (ctypes.c_int, [_P, _I64]),
     "apx_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_tune_set": (ctypes.c_int, [_P, _I64, _I32, _I32, _I32]),
@@ -252,12 +253,21 @@ def apx_set_implicit(list_capacity: int, min_n: int = 8192, device=None) -> None
     _check(ctx, lib().apx_set_implicit(ctx, list_capacity, min_n), "apx_set_implicit")
 
 
-def apx_last_solve_info(device=None) -> tuple[int, int]:
-    """(iterations with implicit R, iterations with explicit R) of the last ap_solve."""
+def apx_set_implicit_a(list_capacity: int, device=None) -> None:
+    """Implicit availabilities in ap_solve on a cold start (with implicit R):
+    exception list capacity 1..1024 per row, or 0 for explicit A."""
     ctx = context(device)
-    a, b = _I32(), _I32()
-    _check(ctx, lib().apx_last_solve_info(ctx, ctypes.byref(a), ctypes.byref(b)), "apx_last_solve_info")
-    return a.value, b.value
+    _check(ctx, lib().apx_set_implicit_a(ctx, list_capacity), "apx_set_implicit_a")
+
+
+def apx_last_solve_info(device=None) -> tuple[int, int, int]:
+    """(iterations with implicit R, iterations with explicit R, iterations
+    with implicit A) of the last ap_solve."""
+    ctx = context(device)
+    a, b, c = _I32(), _I32(), _I32()
+    _check(ctx, lib().apx_last_solve_info(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "apx_last_solve_info")
+    return a.value, b.value, c.value
 
 
 def apx_set_graphs(enable: bool, device=None) -> None:

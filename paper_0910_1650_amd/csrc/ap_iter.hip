@@ -537,6 +537,7 @@ __device__ __forceinline__ float imp_alpha(float lam, int t) {
 // Column sums: 64 columns per workgroup, 16 slices of the partial rows per
 // column summed in FP64, slices combined in a fixed order.
 __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
+#pragma clang fp contract(off)
     if (a.st != nullptr && a.st->frozen) return;
     __shared__ double part[16][64];
     const int cx = threadIdx.x & 63, gs = threadIdx.x >> 6;
@@ -550,8 +551,15 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
         double tot = 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) tot += part[q][cx];
-        a.tcol[k] = (float)((double)a.rdiag[k] + tot);
-        a.ccol[k] = (float)tot;
+        const float tf = (float)((double)a.rdiag[k] + tot), cf = (float)tot;
+        a.tcol[k] = tf;
+        a.ccol[k] = cf;
+        if (a.acol_out != nullptr) {
+            // the explicit update of Eqs. (3), (4) for elements with r <= 0, in its rounding
+            const float oml = 1.0f - a.lam;
+            a.acol_out[k] = a.lam * a.acol_in[k] + oml * fminf(0.0f, tf);
+            a.adiag_out[k] = a.lam * a.adiag_in[k] + oml * cf;
+        }
     }
     if (a.bookkeep && a.st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
         ApState *st = a.st;
@@ -989,7 +997,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             beta_out[ii] = beta1;
             if (ovf) {
                 cnt_out[ii] = -1;
-                p.st->imp_abort = 1;
+                atomicOr(&p.st->imp_abort, 1);
             } else {
                 for (int qq = 0; qq < cnt; ++qq) {
                     col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
@@ -1094,6 +1102,537 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     }
 }
 
+// ---- implicit availabilities -----------------------------------------------
+// Pass t with R_t implicit (as in k_row_imp) and A_{t-1} implicit (see
+// XLayout): it reads S and short per-row lists and writes no matrix.  An
+// off-diagonal element outside the row's exception list takes acol_t(k), the
+// diagonal takes adiag_t(i); listed elements are excluded from the row scan
+// and updated from their stored value by the thread that holds the list
+// entry; an element whose responsibility turns positive for the first time
+// is updated from acol_{t-1}(k) (exactly what the explicit update gives it)
+// and appended to the list.  The column partials of max(0, R_{t+1}) are only
+// touched where a value is positive (adding zeros changes nothing).
+// Exception lists and their column masks (one byte per float4 chunk) use
+// NXS LDS slots: row i+1's slot is filled during row i before the reduction
+// barrier; row i's mask bits are cleared during row i+1 after it, which is
+// two barriers before the slot is filled again.
+// GP: the partials accumulate in the workgroup's global partial row (rows too
+// long for LDS).  PREF: the next row's S is loaded into a second register
+// set during the current row.
+constexpr int NXS = 4;
+constexpr int kMaxDynLdsIa = 160 * 1024 - 36 * 1024;
+
+__device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) << 3) + (k & 3)); }
+
+template <int T, int J, bool PREF, bool GP>
+__global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
+#pragma clang fp contract(off)
+    constexpr int NW = T / 64;
+    constexpr int NOWN = 2;
+    constexpr int EPT = (IMP_KA + T - 1) / T;    // list entries per thread
+
+    if (p.st->frozen) return;
+    __shared__ float sh_f[2][NW][3];
+    __shared__ int sh_i[2][NW][2];
+    __shared__ int st_col[3][IMP_K];
+    __shared__ float st_gam[3][IMP_K];
+    __shared__ float st_beta[3];
+    __shared__ int st_cnt[3];
+    __shared__ float st_ad[3];
+    __shared__ int xa_col[NXS][IMP_KA];
+    __shared__ float xa_val[NXS][IMP_KA];
+    __shared__ int xa_new[NXS];
+    extern __shared__ float4 dyn[];
+    const int q = (p.n + 3) >> 2;
+    const int mw = (q + 3) >> 2;                 // mask words per slot
+    float4 *lpart = dyn;                         // column partials (LDS variant), q entries
+    uint32_t *mask = reinterpret_cast<uint32_t *>(dyn + (GP ? 0 : q));
+    int *rcnt = reinterpret_cast<int *>(mask + NXS * mw);   // list lengths of this workgroup's rows
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n = p.n;
+    const int64_t ld = p.ld;
+    const float lam = p.lam;
+    const float oml = 1.0f - lam;
+    const int64_t nrows = p.row_end - p.row_begin;
+    const int64_t r0 = p.row_begin + (int64_t)blockIdx.x * nrows / gridDim.x;
+    const int64_t r1 = p.row_begin + (int64_t)(blockIdx.x + 1) * nrows / gridDim.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int c0 = tid * 4;
+    const int cl = ((J - 1) * T + tid) * 4;
+    const bool last_in = cl < n;
+    const bool last_full = cl + 3 < n;
+    const int tpass = p.st->iter + 1;
+    const float al = p.st->imp_al;               // alpha_t
+    const float al1 = p.st->imp_al1;             // alpha_{t+1}
+    const ImpLayout L = imp_layout(n);
+    const char *sin = p.state + (int64_t)(tpass & 1) * p.stride;
+    char *sout = p.state + (int64_t)((tpass + 1) & 1) * p.stride;
+    const float *beta_in = reinterpret_cast<const float *>(sin + L.beta);
+    const int32_t *cnt_in = reinterpret_cast<const int32_t *>(sin + L.cnt);
+    const int32_t *col_in = reinterpret_cast<const int32_t *>(sin + L.col);
+    const float *gam_in = reinterpret_cast<const float *>(sin + L.gam);
+    float *beta_out = reinterpret_cast<float *>(sout + L.beta);
+    int32_t *cnt_out = reinterpret_cast<int32_t *>(sout + L.cnt);
+    int32_t *col_out = reinterpret_cast<int32_t *>(sout + L.col);
+    float *gam_out = reinterpret_cast<float *>(sout + L.gam);
+    float *const Rx_base = p.Rx[(tpass + 1) & 1];
+    const XLayout X = x_layout(n);
+    const char *xin = p.xstate + (int64_t)((tpass + 1) & 1) * p.xstride;   // lists of A_{t-1}
+    char *xout = p.xstate + (int64_t)(tpass & 1) * p.xstride;             // lists of A_t
+    const int32_t *xcnt_in = reinterpret_cast<const int32_t *>(xin + X.cnt);
+    const int32_t *xcol_in = reinterpret_cast<const int32_t *>(xin + X.col);
+    const float *xval_in = reinterpret_cast<const float *>(xin + X.val);
+    int32_t *xcnt_out = reinterpret_cast<int32_t *>(xout + X.cnt);
+    int32_t *xcol_out = reinterpret_cast<int32_t *>(xout + X.col);
+    float *xval_out = reinterpret_cast<float *>(xout + X.val);
+    const float *acol_t = p.acol[tpass & 1];
+    const float *acol_p = p.acol[(tpass + 1) & 1];
+    const float *adiag_t = p.adiag[tpass & 1];
+    const int xcap = p.xcap;
+    float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (j < J - 1 || last_in) {
+            if constexpr (GP) st4(P + c0 + j * T * 4, z4);
+            else lpart[j * T + tid] = z4;
+        }
+    }
+    for (int w = tid; w < NXS * mw; w += T) mask[w] = 0u;
+    for (int64_t r = r0 + tid; r < r1; r += T) {
+        const int c = xcnt_in[r];
+        rcnt[r - r0] = c < 0 ? 0 : (c > IMP_KA ? IMP_KA : c);
+    }
+    int my_nex = 0, my_changed = 0;
+    __syncthreads();
+
+    auto fetch_state = [&](int64_t i) -> uint32_t {
+        if (tid < IMP_K) return (uint32_t)col_in[i * IMP_K + tid];
+        if (tid < 2 * IMP_K) return __float_as_uint(gam_in[i * IMP_K + tid - IMP_K]);
+        if (tid == 2 * IMP_K) return __float_as_uint(beta_in[i]);
+        if (tid == 2 * IMP_K + 1) return (uint32_t)cnt_in[i];
+        if (tid == 2 * IMP_K + 2) return __float_as_uint(adiag_t[i]);
+        return 0u;
+    };
+    auto put_state = [&](int64_t i, uint32_t v) {
+        const int sl = (int)(i % 3);
+        if (tid < IMP_K) st_col[sl][tid] = (int)v;
+        else if (tid < 2 * IMP_K) st_gam[sl][tid - IMP_K] = __uint_as_float(v);
+        else if (tid == 2 * IMP_K) st_beta[sl] = __uint_as_float(v);
+        else if (tid == 2 * IMP_K + 1) st_cnt[sl] = (int)v;
+        else if (tid == 2 * IMP_K + 2) st_ad[sl] = __uint_as_float(v);
+    };
+    // exception list of a row: thread tid holds entries tid + u*T
+    auto fetch_x = [&](int64_t i, int *xc, float *xv) {
+        const int len = rcnt[i - r0];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int qx = tid + u * T;
+            if (qx < len) {
+                xc[u] = xcol_in[i * IMP_KA + qx];
+                xv[u] = xval_in[i * IMP_KA + qx];
+            }
+        }
+    };
+    auto put_x = [&](int64_t i, const int *xc, const float *xv) {
+        const int xs = (int)(i % NXS);
+        const int len = rcnt[i - r0];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int qx = tid + u * T;
+            if (qx < len) {
+                xa_col[xs][qx] = xc[u];
+                xa_val[xs][qx] = xv[u];
+                if ((unsigned)xc[u] < (unsigned)n) atomicOr(&mask[xs * mw + (xc[u] >> 4)], xbit(xc[u]));
+            }
+        }
+        if (tid == 0) xa_new[xs] = 0;
+    };
+    float4 s4[J], s4n[PREF ? J : 1];
+    auto load_row = [&](int64_t i, float4 *dst) {
+        const rsrc_t srs = row_rsrc(p.S + i * ld, ld);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < J - 1 || last_in) dst[j] = bld4(srs, tid * 16, j * T * 16);
+    };
+    if (r0 < r1) {
+        put_state(r0, fetch_state(r0));
+        int xc[EPT];
+        float xv[EPT];
+        fetch_x(r0, xc, xv);
+        put_x(r0, xc, xv);
+        load_row(r0, s4);
+    }
+    __syncthreads();
+
+    for (int64_t i = r0; i < r1; ++i) {
+        const int ii = (int)i;
+        const int sl = (int)(i % 3);
+        const int xs = (int)(i % NXS);
+        const ColOwner dg = owner_of<T>(ii, tid);
+        const int dle = dg.mine ? 4 * dg.j + dg.e : -1;
+        const bool wave_diag = __any(dg.mine);
+        const float beta = st_beta[sl];
+        const int cnt = st_cnt[sl];
+        const float adg = st_ad[sl];
+        const int xcnt = rcnt[i - r0];
+        // next row's state and list, in flight during this row
+        uint32_t nstate = 0u;
+        int xn_c[EPT];
+        float xn_v[EPT];
+        if (i + 1 < r1) {
+            nstate = fetch_state(i + 1);
+            fetch_x(i + 1, xn_c, xn_v);
+        }
+        // this row's exceptions: s(i,k) and t_k of the entries this thread holds
+        int xk[EPT];
+        bool xok[EPT];
+        float xa[EPT], xsv[EPT], xtv[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int qx = tid + u * T;
+            xk[u] = qx < xcnt ? xa_col[xs][qx] : -1;
+            xok[u] = (unsigned)xk[u] < (unsigned)n;
+            xa[u] = xsv[u] = xtv[u] = 0.0f;
+            if (xok[u]) {
+                xa[u] = xa_val[xs][qx];
+                xsv[u] = p.S[i * ld + xk[u]];
+                xtv[u] = p.tcol[xk[u]];
+            }
+        }
+        int own_le[NOWN], own_q[NOWN];
+        float own_g[NOWN];
+#pragma unroll
+        for (int o = 0; o < NOWN; ++o) {
+            own_le[o] = -1;
+            own_q[o] = -1;
+            own_g[o] = 0.0f;
+        }
+        int nown = 0;
+        for (int qq = 0; qq < cnt; ++qq) {
+            const int c = st_col[sl][qq];
+            if (((c >> 2) % T) == tid) {
+                const int le = ((c >> 2) / T) * 4 + (c & 3);
+#pragma unroll
+                for (int o = 0; o < NOWN; ++o) {
+                    const bool put = nown == o;
+                    own_le[o] = put ? le : own_le[o];
+                    own_q[o] = put ? qq : own_q[o];
+                    own_g[o] = put ? st_gam[sl][qq] : own_g[o];
+                }
+                ++nown;
+            }
+        }
+        const bool wave_own = __any(nown > 0);
+        const uint8_t *mb8 = reinterpret_cast<const uint8_t *>(mask + xs * mw);
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+        int l1 = -1, dl = -1;
+        uint64_t npm = 0;    // elements whose responsibility is positive for the first time
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            const float4 sv = s4[j];
+            const float4 av = ld4(acol_t + c);
+            const uint32_t mb = mb8[j * T + tid];
+            float4 r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f4set(r, e, al * f4get(sv, e) - beta);
+            if (wave_own) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) f4set(r, e, f4get(r, e) + own_g[o]);
+            }
+            float4 a;
+            uint32_t np = 0u;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool inb = full || c + e < n;
+                const bool listed = (mb >> e) & 1u;
+                const bool fresh = inb && !listed && f4get(r, e) > 0.0f;
+                // listed and fresh elements are merged after the scan
+                f4set(a, e, (listed || fresh || !inb) ? kNegInf : f4get(av, e));
+                np |= fresh ? (1u << e) : 0u;
+            }
+            if (wave_diag) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (dle == 4 * j + e) {
+                        f4set(a, e, adg);
+                        np &= ~(1u << e);
+                    }
+            }
+            npm |= (uint64_t)np << (4 * j);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = f4get(a, e) + f4get(r, e);
+                const bool gt = v > dv;
+                dl = gt ? 4 * j + e : dl;
+                dv = gt ? v : dv;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = f4get(a, e) + f4get(sv, e);
+                const bool gt = v > v1;
+                v2 = gt ? v1 : fmaxf(v2, v);
+                l1 = gt ? 4 * j + e : l1;
+                v1 = gt ? v : v1;
+            }
+        }
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
+        if (__any(npm != 0)) {
+            // first positive responsibility: A from acol_{t-1} (the explicit
+            // update of a never-positive element), and a new list entry
+            uint64_t m = npm;
+            while (m) {
+                const int le = __builtin_ctzll(m);
+                m &= m - 1;
+                const int k = local_to_col<T>(le, tid);
+                const float sv = p.S[i * ld + k];
+                float r = al * sv - beta;
+#pragma unroll
+                for (int o = 0; o < NOWN; ++o)
+                    if (own_le[o] == le) r = r + own_g[o];
+                const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
+                argmax_merge(dm, an + r, k);
+                top2_merge(t2, an + sv, k, kNegInf);
+                const int pos = xcnt + atomicAdd(&xa_new[xs], 1);
+                if (pos < xcap) {
+                    xcol_out[i * IMP_KA + pos] = k;
+                    xval_out[i * IMP_KA + pos] = an;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            if (xok[u]) {
+                // listed element: r as the row scan forms it, A from its stored value
+                const int qx = tid + u * T;
+                float r = al * xsv[u] - beta;
+                for (int qq = 0; qq < cnt; ++qq)
+                    if (st_col[sl][qq] == xk[u]) r = r + st_gam[sl][qq];
+                const float an = lam * xa[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
+                argmax_merge(dm, an + r, xk[u]);
+                top2_merge(t2, an + xsv[u], xk[u], kNegInf);
+                xa_val[xs][qx] = an;
+                xcol_out[i * IMP_KA + qx] = xk[u];
+                xval_out[i * IMP_KA + qx] = an;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < r1) {
+            put_state(i + 1, nstate);
+            put_x(i + 1, xn_c, xn_v);
+            if constexpr (PREF) load_row(i + 1, s4n);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        wg_reduce<NW, true, true>(t2, dm, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        if (tid == 0) {
+            const int k = dm.k;
+            if (p.dec) p.dec[ii] = k;
+            const uint8_t ef = (uint8_t)(k == ii);
+            if (p.eflag[ii] != ef) my_changed = 1;
+            p.eflag[ii] = ef;
+            my_nex += ef;
+        }
+        const int xnew = xa_new[xs];
+        const bool xovf = xcnt + xnew > xcap;
+        if (tid == 0) {
+            xcnt_out[ii] = xovf ? -1 : xcnt + xnew;
+            if (xovf) atomicOr(&p.st->imp_abort, 2);
+        }
+
+        // State of R_{t+1} (as in k_row_imp).
+        const int k1 = t2.k1;
+        const float d = oml * (t2.v1 - t2.v2);
+        const float beta1 = lam * beta + oml * t2.v1;
+        int pos1 = -1, k1_owner_has = 0;
+        const int k1_owner = (k1 >> 2) % T;
+        for (int qq = 0; qq < cnt; ++qq) {
+            const int c = st_col[sl][qq];
+            pos1 = (c == k1) ? qq : pos1;
+            k1_owner_has += (((c >> 2) % T) == k1_owner) ? 1 : 0;
+        }
+        const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);
+        if (tid == 0) {
+            beta_out[ii] = beta1;
+            if (ovf) {
+                cnt_out[ii] = -1;
+                atomicOr(&p.st->imp_abort, 1);
+            } else {
+                for (int qq = 0; qq < cnt; ++qq) {
+                    col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
+                    gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
+                }
+                if (pos1 < 0) {
+                    col_out[(int64_t)ii * IMP_K + cnt] = k1;
+                    gam_out[(int64_t)ii * IMP_K + cnt] = d;
+                }
+                cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
+            }
+        }
+        float own_g1[NOWN];
+#pragma unroll
+        for (int o = 0; o < NOWN; ++o) own_g1[o] = lam * own_g[o] + (own_q[o] == pos1 ? d : 0.0f);
+        const bool k1_mine = pos1 < 0 && k1_owner == tid;
+        const int k1_le = ((k1 >> 2) / T) * 4 + (k1 & 3);
+        const bool wave_k1 = __any(k1_mine);
+
+        // previous row's mask bits (its slot is refilled two barriers later)
+        if (i > r0) {
+            const int ps = (int)((i - 1) % NXS);
+            const int len = rcnt[i - 1 - r0];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int qx = tid + u * T;
+                if (qx < len) {
+                    const int xc = xa_col[ps][qx];
+                    if ((unsigned)xc < (unsigned)n) atomicAnd(&mask[ps * mw + (xc >> 4)], ~xbit(xc));
+                }
+            }
+        }
+
+        // Column partials of max(0, R_{t+1}), touched only where positive.
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(j < J - 1 || last_in)) continue;
+            const bool full = (j < J - 1) || last_full;
+            const int c = c0 + j * T * 4;
+            const float4 sv = s4[j];
+            float4 rv4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f4set(rv4, e, al1 * f4get(sv, e) - beta1);
+            if (wave_k1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k1_mine && k1_le == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + d);
+            }
+            if (wave_own) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + own_g1[o]);
+            }
+            float4 pos;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                f4set(pos, e, ((full || c + e < n) && f4get(rv4, e) > 0.0f) ? f4get(rv4, e) : 0.0f);
+            if (wave_diag) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (dle == 4 * j + e) {
+                        f4set(pos, e, 0.0f);
+                        p.rdiag[ii] = f4get(rv4, e);
+                    }
+            }
+            const bool anyp = (pos.x > 0.0f) | (pos.y > 0.0f) | (pos.z > 0.0f) | (pos.w > 0.0f);
+            if constexpr (GP) {
+                if (anyp) {
+                    float4 acc = ld4(P + c);
+                    add4(acc, pos);
+                    st4(P + c, acc);
+                }
+            } else {
+                if (__any(anyp)) {
+                    float4 acc = lpart[j * T + tid];
+                    add4(acc, pos);
+                    lpart[j * T + tid] = acc;
+                }
+            }
+        }
+        // Overflowing rows (at most once per run): R_{t+1} and A_t written
+        // explicitly, same values; S is read again so that nothing of the row
+        // scan stays live for this path.
+        if (ovf) {
+            float *Rx = Rx_base + i * ld;
+#pragma unroll 1
+            for (int j = 0; j < J; ++j) {
+                const int c = c0 + j * T * 4;
+                for (int e = 0; e < 4; ++e) {
+                    const int k = c + e;
+                    if (k >= n) break;
+                    float rv = al1 * p.S[i * ld + k] - beta1;
+                    if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
+                    Rx[k] = rv;
+                }
+            }
+        }
+        if (xovf) {
+            float *Arow = p.A + i * ld;
+#pragma unroll 1
+            for (int j = 0; j < J; ++j) {
+                const int c = c0 + j * T * 4;
+                const uint32_t mb = mb8[j * T + tid];
+                for (int e = 0; e < 4; ++e) {
+                    const int k = c + e;
+                    if (k >= n) break;
+                    const float sv = p.S[i * ld + k];
+                    float r = al * sv - beta;
+                    for (int o = 0; o < NOWN; ++o)
+                        if (own_le[o] == 4 * j + e) r = r + own_g[o];
+                    float a = acol_t[k];
+                    if (k == ii) {
+                        a = adg;
+                    } else if ((mb >> e) & 1u) {
+                        for (int qq = 0; qq < xcnt; ++qq)
+                            if (xa_col[xs][qq] == k) a = xa_val[xs][qq];
+                    } else if (r > 0.0f) {
+                        a = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
+                    }
+                    Arow[k] = a;
+                }
+            }
+        }
+        if constexpr (PREF) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) s4[j] = s4n[j];
+        } else {
+            if (i + 1 < r1) load_row(i + 1, s4);
+        }
+    }
+
+    if constexpr (!GP) {
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, lpart[j * T + tid]);
+    }
+    if (tid == 0) {
+        if (my_nex) atomicAdd(&p.st->nex, my_nex);
+        if (my_changed) atomicOr(&p.st->changed, 1);
+    }
+}
+
+// A = acol off the diagonal, adiag on it, then the listed exceptions.
+__global__ void k_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
+                                 const char *xs) {
+    const XLayout X = x_layout(n);
+    const int32_t *cnt = reinterpret_cast<const int32_t *>(xs + X.cnt);
+    const int32_t *col = reinterpret_cast<const int32_t *>(xs + X.col);
+    const float *val = reinterpret_cast<const float *>(xs + X.val);
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int c = cnt[i];
+        if (c < 0) continue;
+        float *row = A + i * ld;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) row[k] = (k == i) ? adiag[i] : acol[k];
+        __syncthreads();
+        for (int qq = threadIdx.x; qq < c && qq < IMP_KA; qq += blockDim.x) {
+            const int k = col[i * IMP_KA + qq];
+            if ((unsigned)k < (unsigned)n) row[k] = val[i * IMP_KA + qq];
+        }
+        __syncthreads();
+    }
+}
+
 // R(i,k) = alpha s(i,k) - beta(i) + gamma(i,k) for every row with a list;
 // the same expression (and rounding) as the passes use.
 __global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
@@ -1157,6 +1696,45 @@ hipError_t launch_imp_t(int kind, const ImpArgs &a, const PassPlan &pl, hipStrea
         if (pl.lds_bytes >= (size_t)32 * (size_t)((a.n + 3) / 4)) return launch_imp_tj<T, J, true>(kind, a, pl, s);
     }
     return launch_imp_tj<T, J, false>(kind, a, pl, s);
+}
+
+template <int T, int J, bool PREF, bool GP>
+hipError_t launch_ia_k(const ImpArgs &a, int grid, size_t lds, hipStream_t s) {
+    static bool attr_set = false;   // per process; the attribute is per function
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_row_ia<T, J, PREF, GP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsIa);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_row_ia<T, J, PREF, GP><<<grid, T, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+// LDS of the implicit-A pass: partials (unless GP), NXS mask slots, the
+// list lengths of a workgroup's rows.
+size_t ia_lds(int64_t n, int grid, bool gp) {
+    const int64_t q = (n + 3) / 4, mw = (q + 3) / 4;
+    const int64_t rows = (n + grid - 1) / grid + 1;
+    return (size_t)(gp ? 0 : 16 * q) + (size_t)(NXS * mw * 4) + (size_t)(4 * rows);
+}
+
+template <int T, int J>
+hipError_t launch_ia_t(const ImpArgs &a, const PassPlan &pl, hipStream_t s) {
+    const bool gp = pl.lds_bytes < ia_lds(a.n, pl.grid, false);
+    // APX_IA_PREFETCH=0 selects the variant without the second S register set
+    static const bool pref = [] {
+        const char *v = getenv("APX_IA_PREFETCH");
+        return !(v && v[0] == '0');
+    }();
+    if constexpr (J >= 7) {
+        if (gp) return pref ? launch_ia_k<T, J, true, true>(a, pl.grid, pl.lds_bytes, s)
+                            : launch_ia_k<T, J, false, true>(a, pl.grid, pl.lds_bytes, s);
+    } else {
+        if (gp) return hipErrorInvalidValue;
+    }
+    return pref ? launch_ia_k<T, J, true, false>(a, pl.grid, pl.lds_bytes, s)
+                : launch_ia_k<T, J, false, false>(a, pl.grid, pl.lds_bytes, s);
 }
 
 }  // namespace
@@ -1323,6 +1901,58 @@ hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStr
     case 10: return launch_imp_t<1024, 10>(kind, a, pl, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+bool ia_plan(int64_t n, int num_cus, PassPlan *pl) {
+    const int64_t q = (n + 3) / 4;
+    const int threads = n <= 4096 ? 256 : 1024;
+    const int maxj = threads == 256 ? 4 : 10;
+    PassPlan p{};
+    const int64_t g = n <= 4096 ? 2LL * num_cus : (int64_t)num_cus;
+    p.grid = (int)(n < g ? n : g);
+    p.threads = threads;
+    p.chunks = (int)((q + threads - 1) / threads);
+    if (n < 1 || p.chunks > maxj) return false;
+    // APX_IMPLICIT_A_GP=1 keeps the partials in global memory (cross-checks)
+    const char *v = getenv("APX_IMPLICIT_A_GP");
+    bool gp = ia_lds(n, p.grid, false) > (size_t)kMaxDynLdsIa || (v && v[0] == '1' && p.chunks >= 7);
+    p.lds_bytes = ia_lds(n, p.grid, gp);
+    if (p.lds_bytes > (size_t)kMaxDynLdsIa) return false;
+    *pl = p;
+    return true;
+}
+
+hipError_t launch_row_ia(const PassPlan &pl, const ImpArgs &a, hipStream_t s) {
+    if (pl.threads == 256) {
+        switch (pl.chunks) {
+        case 1: return launch_ia_t<256, 1>(a, pl, s);
+        case 2: return launch_ia_t<256, 2>(a, pl, s);
+        case 3: return launch_ia_t<256, 3>(a, pl, s);
+        case 4: return launch_ia_t<256, 4>(a, pl, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (pl.threads != 1024) return hipErrorInvalidValue;
+    switch (pl.chunks) {
+    case 1: return launch_ia_t<1024, 1>(a, pl, s);
+    case 2: return launch_ia_t<1024, 2>(a, pl, s);
+    case 3: return launch_ia_t<1024, 3>(a, pl, s);
+    case 4: return launch_ia_t<1024, 4>(a, pl, s);
+    case 5: return launch_ia_t<1024, 5>(a, pl, s);
+    case 6: return launch_ia_t<1024, 6>(a, pl, s);
+    case 7: return launch_ia_t<1024, 7>(a, pl, s);
+    case 8: return launch_ia_t<1024, 8>(a, pl, s);
+    case 9: return launch_ia_t<1024, 9>(a, pl, s);
+    case 10: return launch_ia_t<1024, 10>(a, pl, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
+                                 const char *x_parity, hipStream_t s) {
+    const int g = n < 8192 ? n : 8192;
+    k_ia_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(A, ld, n, acol, adiag, x_parity);
+    return hipGetLastError();
 }
 
 hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,

@@ -100,12 +100,15 @@ struct IterWs {
     float *R2;            // second responsibility buffer (ap_solve)
     char *imp;            // implicit-R state, two parities (ap_solve)
     int64_t imp_stride;
+    float *acol[2], *adiag[2];   // implicit-A column vectors by parity (ap_solve)
+    char *xst;            // implicit-A exception lists, two parities
+    int64_t xstride;
     int32_t *ex, *nex;
     double *contrib, *sums;
 };
 
 struct IterLayout {
-    size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, o_imp, bytes;
+    size_t o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_r2, o_imp, o_acol, o_x, bytes;
 };
 
 IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
@@ -125,6 +128,8 @@ IterLayout iter_layout(int64_t n, int64_t ld, bool second_r, int grid) {
     o.o_sum = L.take(sizeof(double) * 2);
     o.o_r2 = second_r ? L.take(sizeof(float) * (size_t)n * (size_t)ld) : 0;
     o.o_imp = second_r ? L.take(2 * (size_t)imp_layout(n).stride) : 0;
+    o.o_acol = second_r ? L.take(4 * sizeof(float) * (size_t)ldp) : 0;
+    o.o_x = second_r ? L.take(2 * (size_t)x_layout(n).stride) : 0;
     o.bytes = L.off;
     return o;
 }
@@ -150,6 +155,12 @@ apx_status iter_ws(apx_ctx *ctx, int64_t n, int64_t ld, bool second_r, const Pas
     w.R2 = second_r ? reinterpret_cast<float *>(b + o.o_r2) : nullptr;
     w.imp = second_r ? b + o.o_imp : nullptr;
     w.imp_stride = imp_layout(n).stride;
+    for (int q = 0; q < 2; ++q) {
+        w.acol[q] = second_r ? reinterpret_cast<float *>(b + o.o_acol) + q * w.ldp : nullptr;
+        w.adiag[q] = second_r ? reinterpret_cast<float *>(b + o.o_acol) + (2 + q) * w.ldp : nullptr;
+    }
+    w.xst = second_r ? b + o.o_x : nullptr;
+    w.xstride = x_layout(n).stride;
     return APX_OK;
 }
 
@@ -179,8 +190,15 @@ PassArgs pass_args(const float *S, const float *Rin, float *Rout, float *A, int6
 // Implicit pass (state R_t in parity t & 1, t from the run state); the
 // prologue is the t = 0 pass.
 ImpArgs imp_args(const float *S, float *A, int64_t n, int64_t ld, float lam, const IterWs &w,
-                 float *const buf[2], bool prologue, int kmax) {
+                 float *const buf[2], bool prologue, int kmax, int xcap = 0) {
     ImpArgs a{};
+    for (int q = 0; q < 2; ++q) {
+        a.acol[q] = w.acol[q];
+        a.adiag[q] = w.adiag[q];
+    }
+    a.xstate = w.xst;
+    a.xstride = w.xstride;
+    a.xcap = xcap;
     a.S = S;
     a.A = A;
     a.ld = ld;
@@ -205,8 +223,17 @@ ImpArgs imp_args(const float *S, float *A, int64_t n, int64_t ld, float lam, con
     return a;
 }
 
-ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep) {
+// ia_pass >= 0: the reduce after implicit-A pass ia_pass (0 = prologue) also
+// advances the availability column vectors to iteration ia_pass + 1.
+ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep, int32_t ia_pass = -1, float lam = 0.0f) {
     ColArgs c{};
+    if (ia_pass >= 0) {
+        c.acol_in = w.acol[ia_pass & 1];
+        c.adiag_in = w.adiag[ia_pass & 1];
+        c.acol_out = w.acol[(ia_pass + 1) & 1];
+        c.adiag_out = w.adiag[(ia_pass + 1) & 1];
+        c.lam = lam;
+    }
     c.partial = w.partial;
     c.ldp = w.ldp;
     c.nparts = w.nparts;
@@ -223,12 +250,16 @@ ColArgs col_args(const IterWs &w, int64_t n, ApState *st, int bookkeep) {
 
 namespace {
 
+// How ap_solve keeps the messages: both explicit; R implicit (ImpArgs);
+// R and A implicit (XLayout, cold start).
+enum SolveMode : int { SOLVE_EXPLICIT = 0, SOLVE_IMPLICIT_R = 1, SOLVE_IMPLICIT_A = 2 };
+
 // Runs iterations t0 .. t0+chunk-1 of ap_solve as one replay of a captured
 // graph on the context's private stream, ordered after everything already
 // enqueued on ctx->stream, then copies the run state to the host and waits.
 // Returns APX_ENOTIMPL (and leaves nothing enqueued) when the capture itself
 // fails, so that the caller can run the chunk with plain launches.
-apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const float *S, float *const buf[2],
+apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *S, float *const buf[2],
                        float *A, int64_t n, int64_t ld, float lam, const IterWs &w, int chunk, int32_t t0,
                        ApState *hst) {
     if (!ctx->cap) {
@@ -241,7 +272,8 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const fl
                               (uint64_t)(uintptr_t)A, (uint64_t)n, (uint64_t)ld, lam_bits, (uint64_t)chunk,
                               (uint64_t)(t0 & 1), (uint64_t)(uintptr_t)w.st, (uint64_t)(uintptr_t)w.partial,
                               (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.imp,
-                              (uint64_t)pl.grid | ((uint64_t)implicit << 32) | ((uint64_t)ctx->implicit_k << 40),
+                              (uint64_t)pl.grid | ((uint64_t)mode << 32) | ((uint64_t)ctx->implicit_k << 40) |
+                                  ((uint64_t)ctx->implicit_a << 48),
                               (uint64_t)pl.threads, (uint64_t)pl.lds_bytes};
     if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
         if (ctx->gexec) {
@@ -252,14 +284,18 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, bool implicit, const fl
         hipError_t e = hipSuccess;
         for (int u = 0; u < chunk && e == hipSuccess; ++u) {
             const int32_t t = t0 + u;
-            if (implicit) {
+            if (mode == SOLVE_IMPLICIT_A) {
+                e = launch_row_ia(pl, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a),
+                                  ctx->cap);
+            } else if (mode == SOLVE_IMPLICIT_R) {
                 e = launch_row_imp(pl, IMP_FULL, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k),
                                    ctx->cap);
             } else {
                 PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
                 e = launch_row_pass(pl, PASS_FULL, pf, ctx->cap);
             }
-            if (e == hipSuccess) e = launch_col_reduce(col_args(w, n, w.st, 1), ctx->cap);
+            if (e == hipSuccess)
+                e = launch_col_reduce(col_args(w, n, w.st, 1, mode == SOLVE_IMPLICIT_A ? t : -1, lam), ctx->cap);
         }
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
@@ -334,6 +370,11 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
         const int k = atoi(iv);
         ctx->implicit_k = k < 0 ? 0 : (k > IMP_K ? IMP_K : k);
     }
+    const char *xv = getenv("APX_IMPLICIT_A");
+    if (xv && xv[0]) {
+        const int k = atoi(xv);
+        ctx->implicit_a = k < 0 ? 0 : (k > IMP_KA ? IMP_KA : k);
+    }
     const char *av = getenv("APX_AUTOTUNE");
     if (av && av[0] == '1') ctx->autotune = true;
     const char *tf = getenv("APX_TUNE_FILE");
@@ -379,10 +420,20 @@ apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n) 
     return APX_OK;
 }
 
-apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters) {
+apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity) {
+    if (!ctx) return APX_EINVAL;
+    if (list_capacity < 0 || list_capacity > IMP_KA)
+        return set_err(ctx, APX_EINVAL, "exception list capacity must be in [0, %d]", IMP_KA);
+    ctx->implicit_a = list_capacity;
+    return APX_OK;
+}
+
+apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters,
+                               int32_t *implicit_a_iters) {
     if (!ctx || !implicit_iters || !explicit_iters) return APX_EINVAL;
     *implicit_iters = ctx->last_imp_iters;
     *explicit_iters = ctx->last_exp_iters;
+    if (implicit_a_iters) *implicit_a_iters = ctx->last_ia_iters;
     return APX_OK;
 }
 
@@ -488,6 +539,10 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     bool implicit = ctx->implicit_k > 0 && n >= ctx->implicit_min_n && warm != APX_WARM_AR &&
                     imp_plan(n, ctx->num_cus, &ipl);
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
+    // Cold start: A is kept implicitly too (XLayout) unless disabled.
+    PassPlan apl{};
+    bool imp_a = implicit && warm == APX_COLD && ctx->implicit_a > 0 && ia_plan(n, ctx->num_cus, &apl);
+    int32_t ia_until = imp_a ? INT32_MAX : 0;       // last iteration run with implicit A
     if (implicit) {
         // parity 0 holds R_0 = 0: beta = 0 and empty lists
         const ImpLayout il = imp_layout(n);
@@ -496,7 +551,15 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.imp + il.cnt), 4 * n, 0, s), "implicit state");
         const ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, true, ctx->implicit_k);
         HIP_TRY(launch_row_imp(ipl, warm == APX_COLD ? IMP_PRO_COLD : IMP_PRO_WARM, ia, s), "prologue");
-        if (warm == APX_COLD) HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+        if (imp_a) {
+            // A_0 = 0: both column vectors zero, every exception list empty
+            HIP_TRY(launch_fill_f32_rows(w.acol[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
+            HIP_TRY(launch_fill_f32_rows(w.adiag[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
+            HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.xst + x_layout(n).cnt), 4 * n, 0, s),
+                    "implicit A");
+        } else if (warm == APX_COLD) {
+            HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+        }
     } else {
         PassArgs pr = pass_args(S, R, buf[1], A, n, ld, lam, w, nullptr, nullptr, nullptr);
         if (warm == APX_COLD) {
@@ -508,7 +571,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
         }
     }
-    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
+    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0, imp_a ? 0 : -1, lam), s), "column reduce");
 
     // Host polls every `chunk` iterations (even, so every replay of the
     // captured chunk starts on the same responsibility buffer).  Passes after
@@ -534,7 +597,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         const int32_t t_first = t;
         bool done = false;
         if (use_graph && stop_at - t == chunk) {
-            const apx_status gs = graph_chunk(ctx, implicit ? ipl : pl, implicit, S, buf, A, n, ld, lam, w,
+            const int mode = imp_a ? SOLVE_IMPLICIT_A : implicit ? SOLVE_IMPLICIT_R : SOLVE_EXPLICIT;
+            const apx_status gs = graph_chunk(ctx, imp_a ? apl : implicit ? ipl : pl, mode, S, buf, A, n, ld, lam, w,
                                               chunk, t, hst);
             if (gs == APX_OK) {
                 t = stop_at;
@@ -551,14 +615,18 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                                         w.eflag, w.st);
                 const int slot = t - t_first;
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
-                if (implicit)
+                if (imp_a)
+                    HIP_TRY(launch_row_ia(apl, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k,
+                                                        ctx->implicit_a), s),
+                            "row pass");
+                else if (implicit)
                     HIP_TRY(launch_row_imp(ipl, IMP_FULL,
                                            imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k), s),
                             "row pass");
                 else
                     HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
-                HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1), s), "column reduce");
+                HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1, imp_a ? t : -1, lam), s), "column reduce");
             }
             HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, s), "state");
             HIP_TRY(hipStreamSynchronize(s), "sync");
@@ -574,18 +642,27 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             }
         }
         if (hst->frozen == 2) {
-            // A row's implicit list overflowed in pass t_a: R_{t_a+1} is made
-            // explicit (overflowed rows were written by the pass itself), its
-            // column vectors are rebuilt, and the run continues with explicit R.
+            // A row list overflowed in pass t_a (overflowed rows were written
+            // explicitly by the pass itself).  A_{t_a} is made explicit when A
+            // was implicit, R_{t_a+1} when its list overflowed; the column
+            // vectors are rebuilt and the run continues with explicit messages.
             const int32_t ta = hst->iter;
             const int po = (ta + 1) & 1;
-            // alpha_{t_a+1} is the run state's current alpha after the reduce of pass t_a
-            HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, &w.st->imp_al,
-                                           w.imp + po * w.imp_stride, s), "materialize R");
+            if (imp_a) {
+                HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[ta & 1], w.adiag[ta & 1],
+                                              w.xst + (ta & 1) * w.xstride, s), "materialize A");
+                imp_a = false;
+                ia_until = ta;
+            }
+            if (hst->imp_abort & 1) {
+                // alpha_{t_a+1} is the run state's current alpha after the reduce of pass t_a
+                HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, &w.st->imp_al,
+                                               w.imp + po * w.imp_stride, s), "materialize R");
+                implicit = false;
+                imp_until = ta;
+            }
             HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
             HIP_TRY(launch_state_resume(w.st, s), "resume");
-            implicit = false;
-            imp_until = ta;
             t = ta + 1;
             continue;
         }
@@ -596,6 +673,11 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     res->converged = hst->converged;
     ctx->last_imp_iters = imp_until < T ? imp_until : T;
     ctx->last_exp_iters = T - ctx->last_imp_iters;
+    ctx->last_ia_iters = ia_until < T ? ia_until : T;
+    if (imp_a) {
+        HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[T & 1], w.adiag[T & 1],
+                                      w.xst + (T & 1) * w.xstride, s), "materialize A");
+    }
     if (implicit) {
         // alpha_T is the previous alpha after the reduce of pass T
         HIP_TRY(launch_imp_materialize(S, R, ld, (int32_t)n, &w.st->imp_al_prev,

@@ -25,7 +25,7 @@ struct ApState {
     int32_t max_iter;
     int32_t conv_iter;
     int32_t last_nex;   // |E| of the last completed iteration
-    int32_t imp_abort;  // an implicit-R row overflowed its list (see ImpArgs)
+    int32_t imp_abort;  // bit 0: an implicit-R row list overflowed; bit 1: an implicit-A list did
     float imp_lam;      // damping of the run
     float imp_al;       // alpha_t for the next full pass t (1 - lambda^t)
     float imp_al1;      // alpha_{t+1}
@@ -72,6 +72,12 @@ struct ColArgs {
     int32_t n;
     ApState *st;        // nullable
     int32_t bookkeep;   // 1: apply the stop rule for the pass just finished
+    // Implicit availabilities (nullable): with the column vectors of R_{t+1}
+    // just summed, acol_{t+1} = lam acol_t + (1-lam) min(0, t_k) and
+    // adiag_{t+1} = lam adiag_t + (1-lam) c_k (Eqs. (3), (4), damping).
+    const float *acol_in, *adiag_in;
+    float *acol_out, *adiag_out;
+    float lam;
 };
 
 // Launch helpers (ap_iter.hip).
@@ -123,7 +129,34 @@ struct ImpArgs {
     int32_t kmax;               // list capacity in use (<= IMP_K)
     int32_t prologue;           // 1: the t = 0 pass (alpha_0 = 0, alpha_1 from st)
     int64_t row_begin, row_end;
+    // Implicit availabilities (k_row_ia only), see XLayout.
+    const float *acol[2];       // acol_t by parity of t
+    const float *adiag[2];      // adiag_t by parity of t
+    char *xstate;               // exception lists, two parities of `xstride` bytes
+    int64_t xstride;
+    int32_t xcap;               // list capacity in use (<= IMP_KA)
 };
+// Implicit availabilities.  With A_0 = 0, Eq. (3) with damping gives every
+// off-diagonal element (i,k) whose responsibility r_s(i,k) was never positive
+// (s <= t) the same value acol_t(k) = lam acol_{t-1}(k) + (1-lam) min(0, t_k),
+// and Eq. (4) gives the diagonal adiag_t(k) = lam adiag_{t-1}(k) + (1-lam) c_k:
+// both are column vectors.  The other elements (the columns where row i ever
+// had a positive responsibility) are kept per row as a list of (column,
+// value): the exceptions.  The list of A_t lives in parity t & 1.
+constexpr int IMP_KA = 1024;         // exception list capacity per row
+struct XLayout {
+    int64_t cnt, col, val, stride;
+};
+// cnt (n ints, -1 after an overflow), columns (n x IMP_KA), values (n x IMP_KA).
+__host__ __device__ inline XLayout x_layout(int64_t n) {
+    const int64_t a = (4 * n + 255) & ~int64_t(255), b = (4 * n * IMP_KA + 255) & ~int64_t(255);
+    XLayout L{};
+    L.cnt = 0;
+    L.col = a;
+    L.val = a + b;
+    L.stride = a + 2 * b;
+    return L;
+}
 // Byte layout of one parity of the implicit-R state for n rows: beta (n
 // floats), list length (n ints, -1 after an overflow), columns (n x IMP_K
 // ints), gammas (n x IMP_K floats).
@@ -149,6 +182,14 @@ hipError_t launch_row_imp(const PassPlan &pl, int kind, const ImpArgs &a, hipStr
 // state is -1 (overflowed) are left alone.
 hipError_t launch_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
                                   const char *state_parity, hipStream_t s);
+// Plan of the pass with implicit R and A (cold start); false when n has no
+// instantiated variant or its LDS does not fit.
+bool ia_plan(int64_t n, int num_cus, PassPlan *pl);
+hipError_t launch_row_ia(const PassPlan &pl, const ImpArgs &a, hipStream_t s);
+// A = acol off the diagonal, adiag on it, then the row's exceptions; rows
+// whose list is -1 (overflowed: written by the pass) are left alone.
+hipError_t launch_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
+                                 const char *x_parity, hipStream_t s);
 // Clears the frozen and overflow flags after an overflow hand-over.
 hipError_t launch_state_resume(ApState *st, hipStream_t s);
 
@@ -201,6 +242,8 @@ struct apx_ctx {
     int64_t implicit_min_n = 8192;    // smaller problems run explicit R (faster there)
     int32_t last_imp_iters = 0;       // iterations of the last ap_solve run with implicit R
     int32_t last_exp_iters = 0;       // ... and with explicit R
+    int implicit_a = apx::IMP_KA;     // implicit-A exception list capacity (0 = explicit A)
+    int32_t last_ia_iters = 0;        // iterations of the last ap_solve run with implicit A
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
     std::vector<apx::TuneEntry> tune;

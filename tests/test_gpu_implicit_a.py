@@ -1,0 +1,166 @@
+"""ap_solve with implicit availabilities (cold start) against explicit
+messages and the FP64 oracle.
+
+With A_0 = 0, Eq. (3) with damping keeps every off-diagonal a(i,k) whose
+responsibility was never positive equal to one value per column, and Eq. (4)
+makes the diagonal a column vector; each row keeps the other elements in a
+list.  A is the explicit update element for element, R is implicit as in
+test_gpu_implicit.py: messages agree with explicit messages and with the
+oracle within the message tolerance, exemplar sets and labels are identical.
+Tiny list capacities force the hand-over to explicit A mid-run.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0910_1650_amd as apx  # noqa: E402
+
+TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def host(M):
+    return M.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(autouse=True)
+def restore():
+    yield
+    apx.apx_set_implicit(16, 8192)
+    apx.apx_set_implicit_a(1024)
+    apx.apx_set_graphs(True)
+    os.environ.pop("APX_IMPLICIT_A_GP", None)
+
+
+def mixture(n, seed, d=8, k=12):
+    pts = synth.gaussian_mixture(n=n, d=d, k=k, seed=seed)
+    S = oracle.prepare(oracle.similarity(pts.X), "median", seed=seed).S
+    return S.astype(np.float32).astype(np.float64)
+
+
+def solve(Sd, cap_r, cap_a, lam=0.9, max_iter=2000, conv_iter=15):
+    apx.apx_set_implicit(cap_r, 0)     # every size: these tests use small problems
+    apx.apx_set_implicit_a(cap_a)
+    n = Sd.shape[0]
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    idx, res = apx.ap_solve(Sd, R, A, lam, max_iter, conv_iter)
+    torch.cuda.synchronize()
+    return R, A, idx, res, apx.apx_last_solve_info()
+
+
+@pytest.mark.parametrize("n", [300, 1000, 4097, 6000])
+def test_implicit_a_matches_explicit_and_oracle(n):
+    say(f"implicit A vs explicit n={n}")
+    S = mixture(n, 2300 + n)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    Ri, Ai, ii, ri, info = solve(Sd, 16, 1024)
+    Rr, Ar, ir, rr, _ = solve(Sd, 16, 0)       # implicit R, explicit A
+    Re, Ae, ie, re, _ = solve(Sd, 0, 0)        # explicit R and A
+    ref = oracle.ap(S, 0.9, 2000, 15)
+    rng = S.max() - S.min()
+    assert info[2] == ri.iterations, info        # A implicit for the whole run
+    assert ri.converged and re.converged and ref.converged
+    assert ri.iterations == rr.iterations == re.iterations == ref.iterations
+    assert torch.equal(ii, ie) and torch.equal(ii, ir)
+    assert np.array_equal(ii.cpu().numpy(), ref.idx)
+    # same R arithmetic as implicit R with explicit A: A differs at most in zero signs
+    assert torch.equal(Ri, Rr) and torch.equal(Ai, Ar)
+    assert np.max(np.abs(host(Ai) - host(Ae))) <= TOL * rng
+    assert np.max(np.abs(host(Ri) - host(Re))) <= TOL * rng
+    assert np.max(np.abs(host(Ai) - ref.A)) <= TOL * rng
+    assert abs(ri.netsim - ref.netsim) <= n * 1e-6 * rng
+
+
+def test_fixed_count_messages_against_oracle():
+    n = 2000
+    say(f"implicit A fixed count n={n}")
+    S = mixture(n, 177)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    R, A, _, res, info = solve(Sd, 16, 1024, max_iter=37, conv_iter=0)
+    assert res.iterations == 37 and info[2] == 37
+    ref = oracle.ap(S, 0.9, 37, 0)
+    rng = S.max() - S.min()
+    assert np.max(np.abs(host(R) - ref.R)) <= TOL * rng
+    assert np.max(np.abs(host(A) - ref.A)) <= TOL * rng
+
+
+@pytest.mark.parametrize("cap_r,cap_a", [(16, 1), (16, 3), (1, 2)])
+def test_list_overflow_hands_over_to_explicit(cap_r, cap_a):
+    n = 1500
+    say(f"implicit A overflow with capacities R {cap_r}, A {cap_a}")
+    S = mixture(n, 191)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    R, A, idx, res, info = solve(Sd, cap_r, cap_a)
+    Re, Ae, ie, re, _ = solve(Sd, 0, 0)
+    rng = S.max() - S.min()
+    say(f"  iterations {res.iterations}, implicit A for {info[2]}, implicit R for {info[0]}")
+    assert info[2] < res.iterations              # the hand-over happened
+    assert res.converged and res.iterations == re.iterations
+    assert torch.equal(idx, ie)
+    assert np.max(np.abs(host(R) - host(Re))) <= TOL * rng
+    assert np.max(np.abs(host(A) - host(Ae))) <= TOL * rng
+
+
+def test_warm_start_keeps_explicit_a():
+    n = 2400
+    say(f"implicit A off for a warm start n={n}")
+    S = mixture(n, 155)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    apx.apx_set_implicit(16, 0)
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    apx.pap_solve(Sd, R, A, 4, damping=0.9, max_iter=2000, conv_iter=15)
+    torch.cuda.synchronize()
+    assert apx.apx_last_solve_info()[2] == 0
+
+
+def test_graph_and_repeat_bit_identical():
+    n = 3000
+    say(f"implicit A graph vs host launches n={n}")
+    S = mixture(n, 166)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    apx.apx_set_graphs(False)
+    ref = solve(Sd, 16, 1024)
+    apx.apx_set_graphs(True)
+    for _ in range(2):
+        got = solve(Sd, 16, 1024)
+        for a, b in zip(got[:3], ref[:3]):
+            assert torch.equal(a, b)
+        assert got[3].netsim == ref[3].netsim
+
+
+def test_long_rows_global_partials():
+    # rows of 7 float4 chunks per thread (n in (24576, 25312] still fits
+    # the LDS variant): the LDS and the global-partials variants give
+    # identical messages; both agree with explicit messages
+    n = 25000
+    say(f"implicit A long rows n={n}")
+    pts = synth.gaussian_mixture(n=n, d=16, k=30, seed=2601)
+    X = torch.from_numpy(pts.X).cuda()
+    Sd, _ = apx.ap_similarity(X, pref="median", noise_seed=2601, noise_rel=1e-12)
+    out = {}
+    for gp in ("0", "1"):
+        os.environ["APX_IMPLICIT_A_GP"] = gp
+        R, A, idx, res, info = solve(Sd, 16, 1024, max_iter=25, conv_iter=0)
+        assert info[2] == 25
+        out[gp] = (R.clone(), A.clone(), idx.clone())
+        del R, A
+    os.environ.pop("APX_IMPLICIT_A_GP", None)
+    for a, b in zip(out["0"], out["1"]):
+        assert torch.equal(a, b)
+    Re, Ae, ie, re, _ = solve(Sd, 0, 0, max_iter=25, conv_iter=0)
+    rng = float(Sd.max() - Sd.min())
+    assert float((out["0"][0] - Re).abs().max()) <= TOL * rng
+    assert float((out["0"][1] - Ae).abs().max()) <= TOL * rng
