@@ -1104,49 +1104,125 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
 
 // ---- implicit availabilities -----------------------------------------------
 // Pass t with R_t implicit (as in k_row_imp) and A_{t-1} implicit (see
-// XLayout): it reads S and short per-row lists and writes no matrix.  An
-// off-diagonal element outside the row's exception list takes acol_t(k), the
-// diagonal takes adiag_t(i); listed elements are excluded from the row scan
-// and updated from their stored value by the thread that holds the list
-// entry; an element whose responsibility turns positive for the first time
-// is updated from acol_{t-1}(k) (exactly what the explicit update gives it)
-// and appended to the list.  The column partials of max(0, R_{t+1}) are only
-// touched where a value is positive (adding zeros changes nothing).
-// Exception lists and their column masks (one byte per float4 chunk) use
-// NXS LDS slots: row i+1's slot is filled during row i before the reduction
-// barrier; row i's mask bits are cleared during row i+1 after it, which is
-// two barriers before the slot is filled again.
+// XLayout): it reads S and short per-row lists and writes no matrix.
+// The row scan covers the ordinary elements: off-diagonal, not in the row's
+// exception list, not in its R list, responsibility not positive.  Their
+// availability is acol_t(k) and R_t has no gamma term there, so the scan is
+// a few instructions per element.  Every other element is merged after the
+// scan, with its column index, by the thread holding it:
+//   - exception-list entries by their list holder (update from the stored
+//     value, Eq. (3) with damping),
+//   - R-list entries by their holder, lane q of wavefront 0 for entry q,
+//   - the diagonal (adiag_t(i)) by thread 0,
+//   - first positive responsibilities by the column owner (update from
+//     acol_{t-1}(k), exactly what the explicit update gives a never-positive
+//     element; appended to the list).
+// Holders gather their S values at the start of the row, so the row
+// registers are free after the scan and the next row's S is loaded before
+// the reduction.  The column partials of max(0, R_{t+1}) take one addition
+// per row and column, in row order, by the same holders; ordinary elements
+// are reread (from L2) only by threads whose largest ordinary s can give a
+// positive value (al1 s - beta1 is monotone in s).
+// Each row has an LDS byte mask (one byte per float4 chunk): bit e marks an
+// exception-list column, bit 4+e an R-listed column or the diagonal.  NXS
+// slots: row i+1's bits are set during row i before the reduction barrier,
+// and each thread zeroes its own bytes of row i-1's slot after it, two
+// barriers before the slot is set again.
 // GP: the partials accumulate in the workgroup's global partial row (rows too
-// long for LDS).  PREF: the next row's S is loaded into a second register
-// set during the current row.
+// long for LDS); the reduction barrier orders LDS only, so there every
+// column's partial is formed by the column owner.
 constexpr int NXS = 4;
-constexpr int kMaxDynLdsIa = 160 * 1024 - 36 * 1024;
+constexpr int kMaxDynLdsIa = 160 * 1024 - 4 * 1024;
 
 __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) << 3) + (k & 3)); }
 
-template <int T, int J, bool PREF, bool GP>
+// Top-2 of a+s that also carries s at the top-1 column.
+struct Top2S {
+    float v1;
+    int k1;
+    float v2;
+    float s1;
+};
+__device__ __forceinline__ void top2s_merge(Top2S &t, float ov1, int ok1, float ov2, float os1) {
+    const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
+    const float nv2 = take ? fmaxf(ov2, t.v1) : fmaxf(t.v2, ov1);
+    t.v1 = take ? ov1 : t.v1;
+    t.k1 = take ? ok1 : t.k1;
+    t.s1 = take ? os1 : t.s1;
+    t.v2 = nv2;
+}
+// wg_reduce for Top2S (same order of merges).
+template <int NW>
+__device__ __forceinline__ void wg_reduce_s(Top2S &t2, ArgMax &dm, float (*sh_f)[4], int (*sh_i)[2], int lane,
+                                            int wave) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ov1 = __shfl_xor(t2.v1, off, 64);
+        const int ok1 = __shfl_xor(t2.k1, off, 64);
+        const float ov2 = __shfl_xor(t2.v2, off, 64);
+        const float os1 = __shfl_xor(t2.s1, off, 64);
+        top2s_merge(t2, ov1, ok1, ov2, os1);
+        const float odv = __shfl_xor(dm.v, off, 64);
+        const int odk = __shfl_xor(dm.k, off, 64);
+        argmax_merge(dm, odv, odk);
+    }
+    if (lane == 0) {
+        sh_f[wave][0] = t2.v1;
+        sh_f[wave][1] = t2.v2;
+        sh_f[wave][2] = dm.v;
+        sh_f[wave][3] = t2.s1;
+        sh_i[wave][0] = t2.k1;
+        sh_i[wave][1] = dm.k;
+    }
+    lds_barrier();
+    if constexpr (NW > 1) {
+        const bool has = lane < NW;
+        const int w = has ? lane : 0;
+        t2 = has ? Top2S{sh_f[w][0], sh_i[w][0], sh_f[w][1], sh_f[w][3]} : Top2S{kNegInf, INT32_MAX, kNegInf, 0.0f};
+        dm = has ? ArgMax{sh_f[w][2], sh_i[w][1]} : ArgMax{kNegInf, INT32_MAX};
+#pragma unroll
+        for (int off = NW / 2; off >= 1; off >>= 1) {
+            const float ov1 = __shfl_xor(t2.v1, off, 64);
+            const int ok1 = __shfl_xor(t2.k1, off, 64);
+            const float ov2 = __shfl_xor(t2.v2, off, 64);
+            const float os1 = __shfl_xor(t2.s1, off, 64);
+            top2s_merge(t2, ov1, ok1, ov2, os1);
+            const float odv = __shfl_xor(dm.v, off, 64);
+            const int odk = __shfl_xor(dm.k, off, 64);
+            argmax_merge(dm, odv, odk);
+        }
+        t2 = Top2S{__shfl(t2.v1, 0, 64), __shfl(t2.k1, 0, 64), __shfl(t2.v2, 0, 64), __shfl(t2.s1, 0, 64)};
+        dm = ArgMax{__shfl(dm.v, 0, 64), __shfl(dm.k, 0, 64)};
+    } else {
+        t2 = Top2S{sh_f[0][0], sh_i[0][0], sh_f[0][1], sh_f[0][3]};
+        dm = ArgMax{sh_f[0][2], sh_i[0][1]};
+    }
+}
+
+template <int T, int J, bool GP>
 __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
 #pragma clang fp contract(off)
     constexpr int NW = T / 64;
-    constexpr int NOWN = 2;
-    constexpr int EPT = (IMP_KA + T - 1) / T;    // list entries per thread
+    constexpr int NOWN = 2;                      // overflow rule shared with k_row_imp
+    constexpr int EPT = (IMP_KA + T - 1) / T;    // exception-list entries per thread
+    static_assert(IMP_K <= 64, "R-list holders are lanes of wavefront 0");
 
     if (p.st->frozen) return;
-    __shared__ float sh_f[2][NW][3];
+    __shared__ float sh_f[2][NW][4];
     __shared__ int sh_i[2][NW][2];
     __shared__ int st_col[3][IMP_K];
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
     __shared__ int st_cnt[3];
     __shared__ float st_ad[3];
-    __shared__ int xa_col[NXS][IMP_KA];
-    __shared__ float xa_val[NXS][IMP_KA];
     __shared__ int xa_new[NXS];
     extern __shared__ float4 dyn[];
     const int q = (p.n + 3) >> 2;
     const int mw = (q + 3) >> 2;                 // mask words per slot
     float4 *lpart = dyn;                         // column partials (LDS variant), q entries
+    float *lp = reinterpret_cast<float *>(dyn);  // the same, indexed by column
     uint32_t *mask = reinterpret_cast<uint32_t *>(dyn + (GP ? 0 : q));
+    uint8_t *mask8 = reinterpret_cast<uint8_t *>(mask);
     int *rcnt = reinterpret_cast<int *>(mask + NXS * mw);   // list lengths of this workgroup's rows
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1216,53 +1292,70 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         if (tid == 2 * IMP_K + 2) return __float_as_uint(adiag_t[i]);
         return 0u;
     };
-    auto put_state = [&](int64_t i, uint32_t v) {
+    // R state of row i into its LDS slot; the R-listed columns and the
+    // diagonal are marked in the high nibble of the row's mask bytes
+    auto put_state = [&](int64_t i, uint32_t v, int rc) {
         const int sl = (int)(i % 3);
-        if (tid < IMP_K) st_col[sl][tid] = (int)v;
-        else if (tid < 2 * IMP_K) st_gam[sl][tid - IMP_K] = __uint_as_float(v);
-        else if (tid == 2 * IMP_K) st_beta[sl] = __uint_as_float(v);
-        else if (tid == 2 * IMP_K + 1) st_cnt[sl] = (int)v;
-        else if (tid == 2 * IMP_K + 2) st_ad[sl] = __uint_as_float(v);
+        uint32_t *m = mask + (i % NXS) * mw;
+        if (tid < IMP_K) {
+            st_col[sl][tid] = (int)v;
+            const int c = (int)v;
+            if (tid < rc && (unsigned)c < (unsigned)n) atomicOr(&m[c >> 4], xbit(c) << 4);
+        } else if (tid < 2 * IMP_K) {
+            st_gam[sl][tid - IMP_K] = __uint_as_float(v);
+        } else if (tid == 2 * IMP_K) {
+            st_beta[sl] = __uint_as_float(v);
+        } else if (tid == 2 * IMP_K + 1) {
+            st_cnt[sl] = (int)v;
+        } else if (tid == 2 * IMP_K + 2) {
+            st_ad[sl] = __uint_as_float(v);
+        }
+        if (tid == 0) atomicOr(&m[i >> 4], xbit((int)i) << 4);
     };
-    // exception list of a row: thread tid holds entries tid + u*T
+    // Exception list of a row: thread tid holds entries tid + u*T in
+    // registers (column -1 when absent).
     auto fetch_x = [&](int64_t i, int *xc, float *xv) {
         const int len = rcnt[i - r0];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int qx = tid + u * T;
+            xc[u] = -1;
+            xv[u] = 0.0f;
             if (qx < len) {
                 xc[u] = xcol_in[i * IMP_KA + qx];
                 xv[u] = xval_in[i * IMP_KA + qx];
             }
         }
     };
-    auto put_x = [&](int64_t i, const int *xc, const float *xv) {
+    auto mark_x = [&](int64_t i, const int *xc) {
         const int xs = (int)(i % NXS);
-        const int len = rcnt[i - r0];
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int qx = tid + u * T;
-            if (qx < len) {
-                xa_col[xs][qx] = xc[u];
-                xa_val[xs][qx] = xv[u];
-                if ((unsigned)xc[u] < (unsigned)n) atomicOr(&mask[xs * mw + (xc[u] >> 4)], xbit(xc[u]));
-            }
-        }
+        for (int u = 0; u < EPT; ++u)
+            if ((unsigned)xc[u] < (unsigned)n) atomicOr(&mask[xs * mw + (xc[u] >> 4)], xbit(xc[u]));
         if (tid == 0) xa_new[xs] = 0;
     };
-    float4 s4[J], s4n[PREF ? J : 1];
+    // acol_t of this thread's columns is the same for every row of the pass:
+    // short rows keep it in registers, long rows read it per chunk
+    constexpr bool ACV = J <= 5;
+    float4 acv[ACV ? J : 1];
+    if constexpr (ACV) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) acv[j] = (j < J - 1 || last_in) ? ld4(acol_t + c0 + j * T * 4) : z4;
+    }
+    float4 s4[J];
     auto load_row = [&](int64_t i, float4 *dst) {
         const rsrc_t srs = row_rsrc(p.S + i * ld, ld);
 #pragma unroll
         for (int j = 0; j < J; ++j)
             if (j < J - 1 || last_in) dst[j] = bld4(srs, tid * 16, j * T * 16);
     };
+    int cur_c[EPT], nxt_c[EPT];
+    float cur_v[EPT], nxt_v[EPT];
     if (r0 < r1) {
-        put_state(r0, fetch_state(r0));
-        int xc[EPT];
-        float xv[EPT];
-        fetch_x(r0, xc, xv);
-        put_x(r0, xc, xv);
+        const int rc = tid < IMP_K ? cnt_in[r0] : 0;
+        put_state(r0, fetch_state(r0), rc);
+        fetch_x(r0, cur_c, cur_v);
+        mark_x(r0, cur_c);
         load_row(r0, s4);
     }
     __syncthreads();
@@ -1271,174 +1364,176 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const int ii = (int)i;
         const int sl = (int)(i % 3);
         const int xs = (int)(i % NXS);
-        const ColOwner dg = owner_of<T>(ii, tid);
-        const int dle = dg.mine ? 4 * dg.j + dg.e : -1;
-        const bool wave_diag = __any(dg.mine);
         const float beta = st_beta[sl];
         const int cnt = st_cnt[sl];
         const float adg = st_ad[sl];
         const int xcnt = rcnt[i - r0];
-        // next row's state and list, in flight during this row
+        const uint8_t *mb8 = mask8 + (size_t)xs * mw * 4;
+        // previous exemplar flag of the row, read before the next row's S is
+        // in flight (a later global load would wait for it)
+        const uint8_t ef_prev = tid == 0 ? p.eflag[ii] : 0;
+        // next row's R state and list, in flight during this row
         uint32_t nstate = 0u;
-        int xn_c[EPT];
-        float xn_v[EPT];
+        int ncnt = 0;
         if (i + 1 < r1) {
             nstate = fetch_state(i + 1);
-            fetch_x(i + 1, xn_c, xn_v);
+            ncnt = tid < IMP_K ? cnt_in[i + 1] : 0;
+            fetch_x(i + 1, nxt_c, nxt_v);
         }
-        // this row's exceptions: s(i,k) and t_k of the entries this thread holds
-        int xk[EPT];
-        bool xok[EPT];
-        float xa[EPT], xsv[EPT], xtv[EPT];
+        // R-list entry tid (lanes of wavefront 0): column, gamma, s, acol_t
+        int rk = -1;
+        float rg = 0.0f, rs = 0.0f, rav = 0.0f;
+        if (tid < cnt) {
+            rk = st_col[sl][tid];
+            rg = st_gam[sl][tid];
+            if ((unsigned)rk < (unsigned)n) {
+                rs = p.S[i * ld + rk];
+                rav = acol_t[rk];
+            } else {
+                rk = -1;
+            }
+        }
+        const float sdg = tid == 0 ? p.S[i * ld + ii] : 0.0f;
+        // exception-list entries: s(i,k) and t_k
+        float xsv[EPT], xtv[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
-            const int qx = tid + u * T;
-            xk[u] = qx < xcnt ? xa_col[xs][qx] : -1;
-            xok[u] = (unsigned)xk[u] < (unsigned)n;
-            xa[u] = xsv[u] = xtv[u] = 0.0f;
-            if (xok[u]) {
-                xa[u] = xa_val[xs][qx];
-                xsv[u] = p.S[i * ld + xk[u]];
-                xtv[u] = p.tcol[xk[u]];
+            xsv[u] = 0.0f;
+            xtv[u] = 0.0f;
+            if ((unsigned)cur_c[u] < (unsigned)n) {
+                xsv[u] = p.S[i * ld + cur_c[u]];
+                xtv[u] = p.tcol[cur_c[u]];
             }
         }
-        int own_le[NOWN], own_q[NOWN];
-        float own_g[NOWN];
-#pragma unroll
-        for (int o = 0; o < NOWN; ++o) {
-            own_le[o] = -1;
-            own_q[o] = -1;
-            own_g[o] = 0.0f;
-        }
-        int nown = 0;
-        for (int qq = 0; qq < cnt; ++qq) {
-            const int c = st_col[sl][qq];
-            if (((c >> 2) % T) == tid) {
-                const int le = ((c >> 2) / T) * 4 + (c & 3);
-#pragma unroll
-                for (int o = 0; o < NOWN; ++o) {
-                    const bool put = nown == o;
-                    own_le[o] = put ? le : own_le[o];
-                    own_q[o] = put ? qq : own_q[o];
-                    own_g[o] = put ? st_gam[sl][qq] : own_g[o];
-                }
-                ++nown;
-            }
-        }
-        const bool wave_own = __any(nown > 0);
-        const uint8_t *mb8 = reinterpret_cast<const uint8_t *>(mask + xs * mw);
-        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+
+        // ---- scan of the ordinary elements
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf, s1 = 0.0f;
+        float smax = kNegInf;   // largest s of the thread's columns that phase 2 leaves to it
         int l1 = -1, dl = -1;
-        uint64_t npm = 0;    // elements whose responsibility is positive for the first time
+        uint32_t fch = 0;       // chunks holding a first positive responsibility
+        bool has_sp = false;    // the thread owns a special column (GP phase 2)
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (!(j < J - 1 || last_in)) continue;
             const bool full = (j < J - 1) || last_full;
             const int c = c0 + j * T * 4;
             const float4 sv = s4[j];
-            const float4 av = ld4(acol_t + c);
+            float4 av;
+            if constexpr (ACV) av = acv[j];
+            else av = ld4(acol_t + c);
             const uint32_t mb = mb8[j * T + tid];
-            float4 r;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) f4set(r, e, al * f4get(sv, e) - beta);
-            if (wave_own) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) f4set(r, e, f4get(r, e) + own_g[o]);
-            }
-            float4 a;
-            uint32_t np = 0u;
+            const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+            has_sp = has_sp || (mb >> 4) != 0u;
+            bool fr = false;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
+                const float s = f4get(sv, e);
+                const float r = al * s - beta;
                 const bool inb = full || c + e < n;
-                const bool listed = (mb >> e) & 1u;
-                const bool fresh = inb && !listed && f4get(r, e) > 0.0f;
-                // listed and fresh elements are merged after the scan
-                f4set(a, e, (listed || fresh || !inb) ? kNegInf : f4get(av, e));
-                np |= fresh ? (1u << e) : 0u;
+                const bool x = (ex >> e) & 1u;
+                const bool pos = r > 0.0f;
+                fr = fr || (inb && !x && pos);
+                const float a = (x || pos || !inb) ? kNegInf : f4get(av, e);
+                const float v = a + r;
+                const bool gd = v > dv;
+                dl = gd ? 4 * j + e : dl;
+                dv = gd ? v : dv;
+                const float w = a + s;
+                const bool g1 = w > v1;
+                l1 = g1 ? 4 * j + e : l1;
+                s1 = g1 ? s : s1;
+                v2 = __builtin_amdgcn_fmed3f(v1, v2, w);
+                v1 = g1 ? w : v1;
+                smax = (inb && (GP || !x)) ? fmaxf(smax, s) : smax;
             }
-            if (wave_diag) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (dle == 4 * j + e) {
-                        f4set(a, e, adg);
-                        np &= ~(1u << e);
-                    }
-            }
-            npm |= (uint64_t)np << (4 * j);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = f4get(a, e) + f4get(r, e);
-                const bool gt = v > dv;
-                dl = gt ? 4 * j + e : dl;
-                dv = gt ? v : dv;
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = f4get(a, e) + f4get(sv, e);
-                const bool gt = v > v1;
-                v2 = gt ? v1 : fmaxf(v2, v);
-                l1 = gt ? 4 * j + e : l1;
-                v1 = gt ? v : v1;
-            }
+            fch |= fr ? (1u << j) : 0u;
         }
-        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        Top2S t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2, s1};
         ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
-        if (__any(npm != 0)) {
-            // first positive responsibility: A from acol_{t-1} (the explicit
-            // update of a never-positive element), and a new list entry
-            uint64_t m = npm;
+        auto merge = [&](float v, float w, int k, float s) {
+            argmax_merge(dm, v, k);
+            top2s_merge(t2, w, k, kNegInf, s);
+        };
+        // first positive responsibility: A from acol_{t-1}, a new list entry
+        auto fresh = [&](int k, float s, float r) {
+            const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
+            merge(an + r, an + s, k, s);
+            const int pos = xcnt + atomicAdd(&xa_new[xs], 1);
+            if (pos < xcap) {
+                xcol_out[i * IMP_KA + pos] = k;
+                xval_out[i * IMP_KA + pos] = an;
+            }
+        };
+        if (__any(fch != 0)) {
+            uint32_t m = fch;
             while (m) {
-                const int le = __builtin_ctzll(m);
+                const int j = __builtin_ctz(m);
                 m &= m - 1;
-                const int k = local_to_col<T>(le, tid);
-                const float sv = p.S[i * ld + k];
-                float r = al * sv - beta;
+                float4 sv = s4[0];
 #pragma unroll
-                for (int o = 0; o < NOWN; ++o)
-                    if (own_le[o] == le) r = r + own_g[o];
-                const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
-                argmax_merge(dm, an + r, k);
-                top2_merge(t2, an + sv, k, kNegInf);
-                const int pos = xcnt + atomicAdd(&xa_new[xs], 1);
-                if (pos < xcap) {
-                    xcol_out[i * IMP_KA + pos] = k;
-                    xval_out[i * IMP_KA + pos] = an;
+                for (int jj = 1; jj < J; ++jj)
+                    if (jj == j) sv = s4[jj];
+                const uint32_t mb = mb8[j * T + tid];
+                const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+                for (int e = 0; e < 4; ++e) {
+                    const int k = c0 + j * T * 4 + e;
+                    if (k >= n) break;
+                    const float s = f4get(sv, e);
+                    const float r = al * s - beta;
+                    if (!((ex >> e) & 1u) && r > 0.0f) fresh(k, s, r);
                 }
             }
         }
+        // R-listed columns, by the holder of the entry (those also in the
+        // exception list are merged by the list holder)
+        const bool rl_diag = __ballot(rk == ii) != 0;     // meaningful in wavefront 0
+        if (rk >= 0) {
+            const float r = (al * rs - beta) + rg;
+            if (rk == ii) {
+                merge(adg + r, adg + rs, ii, rs);
+            } else if (!((mask8[(size_t)xs * mw * 4 + (rk >> 2)] >> (rk & 3)) & 1u)) {
+                if (r > 0.0f) fresh(rk, rs, r);
+                else merge(rav + r, rav + rs, rk, rs);
+            }
+        }
+        // the diagonal (thread 0) unless it is R-listed
+        if (tid == 0 && !rl_diag) {
+            const float r = al * sdg - beta;
+            merge(adg + r, adg + sdg, ii, sdg);
+        }
+        // exception-list entries: A from the stored value
+        bool xrl[EPT];   // the column is R-listed (its R-list holder forms the partial)
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
-            if (xok[u]) {
-                // listed element: r as the row scan forms it, A from its stored value
-                const int qx = tid + u * T;
+            xrl[u] = false;
+            const int k = cur_c[u];
+            if ((unsigned)k < (unsigned)n) {
                 float r = al * xsv[u] - beta;
-                for (int qq = 0; qq < cnt; ++qq)
-                    if (st_col[sl][qq] == xk[u]) r = r + st_gam[sl][qq];
-                const float an = lam * xa[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
-                argmax_merge(dm, an + r, xk[u]);
-                top2_merge(t2, an + xsv[u], xk[u], kNegInf);
-                xa_val[xs][qx] = an;
-                xcol_out[i * IMP_KA + qx] = xk[u];
-                xval_out[i * IMP_KA + qx] = an;
+                if ((mb8[k >> 2] >> (4 + (k & 3))) & 1u) {
+                    xrl[u] = true;
+                    for (int qq = 0; qq < cnt; ++qq)
+                        if (st_col[sl][qq] == k) r = r + st_gam[sl][qq];
+                }
+                const float an = lam * cur_v[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
+                merge(an + r, an + xsv[u], k, xsv[u]);
+                xcol_out[i * IMP_KA + tid + u * T] = k;
+                xval_out[i * IMP_KA + tid + u * T] = an;
             }
         }
         __builtin_amdgcn_sched_barrier(0);
         if (i + 1 < r1) {
-            put_state(i + 1, nstate);
-            put_x(i + 1, xn_c, xn_v);
-            if constexpr (PREF) load_row(i + 1, s4n);
+            put_state(i + 1, nstate, ncnt);
+            mark_x(i + 1, nxt_c);
+            load_row(i + 1, s4);
         }
         __builtin_amdgcn_sched_barrier(0);
 
-        wg_reduce<NW, true, true>(t2, dm, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        wg_reduce_s<NW>(t2, dm, sh_f[i & 1], sh_i[i & 1], lane, wave);
         if (tid == 0) {
             const int k = dm.k;
             if (p.dec) p.dec[ii] = k;
             const uint8_t ef = (uint8_t)(k == ii);
-            if (p.eflag[ii] != ef) my_changed = 1;
+            if (ef_prev != ef) my_changed = 1;
             p.eflag[ii] = ef;
             my_nex += ef;
         }
@@ -1449,143 +1544,169 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             if (xovf) atomicOr(&p.st->imp_abort, 2);
         }
 
-        // State of R_{t+1} (as in k_row_imp).
+        // State of R_{t+1}: beta' = lam beta + (1-lam) v1; every gamma decays
+        // by lam and column k1 gains d = (1-lam)(v1 - v2).  The list is held
+        // by wavefront 0, so its searches are ballots there.
         const int k1 = t2.k1;
         const float d = oml * (t2.v1 - t2.v2);
         const float beta1 = lam * beta + oml * t2.v1;
-        int pos1 = -1, k1_owner_has = 0;
+        const uint64_t bk1 = __ballot(rk >= 0 && rk == k1);
+        const int pos1 = bk1 ? __builtin_ctzll(bk1) : -1;                  // wavefront 0
         const int k1_owner = (k1 >> 2) % T;
-        for (int qq = 0; qq < cnt; ++qq) {
-            const int c = st_col[sl][qq];
-            pos1 = (c == k1) ? qq : pos1;
-            k1_owner_has += (((c >> 2) % T) == k1_owner) ? 1 : 0;
-        }
-        const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);
-        if (tid == 0) {
-            beta_out[ii] = beta1;
-            if (ovf) {
-                cnt_out[ii] = -1;
-                atomicOr(&p.st->imp_abort, 1);
-            } else {
-                for (int qq = 0; qq < cnt; ++qq) {
-                    col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
-                    gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
+        const int k1_owner_has = __popcll(__ballot(rk >= 0 && ((rk >> 2) % T) == k1_owner));
+        const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);   // wavefront 0
+        if (wave == 0) {
+            if (rk >= 0 && !ovf) {
+                col_out[(int64_t)ii * IMP_K + tid] = rk;
+                gam_out[(int64_t)ii * IMP_K + tid] = lam * rg + (tid == pos1 ? d : 0.0f);
+            }
+            if (tid == 0) {
+                beta_out[ii] = beta1;
+                if (ovf) {
+                    cnt_out[ii] = -1;
+                    atomicOr(&p.st->imp_abort, 1);
+                } else {
+                    if (pos1 < 0) {
+                        col_out[(int64_t)ii * IMP_K + cnt] = k1;
+                        gam_out[(int64_t)ii * IMP_K + cnt] = d;
+                    }
+                    cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
                 }
-                if (pos1 < 0) {
-                    col_out[(int64_t)ii * IMP_K + cnt] = k1;
-                    gam_out[(int64_t)ii * IMP_K + cnt] = d;
-                }
-                cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
             }
         }
-        float own_g1[NOWN];
-#pragma unroll
-        for (int o = 0; o < NOWN; ++o) own_g1[o] = lam * own_g[o] + (own_q[o] == pos1 ? d : 0.0f);
-        const bool k1_mine = pos1 < 0 && k1_owner == tid;
-        const int k1_le = ((k1 >> 2) / T) * 4 + (k1 & 3);
-        const bool wave_k1 = __any(k1_mine);
 
-        // previous row's mask bits (its slot is refilled two barriers later)
+        // this thread's bytes of the previous row's mask slot
         if (i > r0) {
-            const int ps = (int)((i - 1) % NXS);
-            const int len = rcnt[i - 1 - r0];
+            uint8_t *pm = mask8 + (size_t)((i - 1) % NXS) * mw * 4;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (j < J - 1 || last_in) pm[j * T + tid] = 0;
+        }
+
+        // ---- column partials of max(0, R_{t+1}), one addition per row and
+        // column, in row order.
+        if constexpr (!GP) {
+            // LDS partials: special columns and listed ones by their holders
+            // (the reduction barrier orders the adds of consecutive rows)
+            if (rk >= 0) {
+                const float r = (al1 * rs - beta1) + (lam * rg + (rk == k1 ? d : 0.0f));
+                if (rk == ii) p.rdiag[ii] = r;
+                else if (r > 0.0f) lp[rk] = lp[rk] + r;
+            }
+            if (tid == 0) {
+                if (pos1 < 0) {
+                    const float r = (al1 * t2.s1 - beta1) + d;
+                    if (k1 == ii) p.rdiag[ii] = r;
+                    else if (r > 0.0f) lp[k1] = lp[k1] + r;
+                }
+                if (!rl_diag && !(pos1 < 0 && k1 == ii)) p.rdiag[ii] = al1 * sdg - beta1;
+            }
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
-                const int qx = tid + u * T;
-                if (qx < len) {
-                    const int xc = xa_col[ps][qx];
-                    if ((unsigned)xc < (unsigned)n) atomicAnd(&mask[ps * mw + (xc >> 4)], ~xbit(xc));
+                const int k = cur_c[u];
+                if ((unsigned)k < (unsigned)n && !xrl[u] && k != k1) {
+                    const float r = al1 * xsv[u] - beta1;
+                    if (r > 0.0f) lp[k] = lp[k] + r;
+                }
+            }
+            // ordinary elements: a positive value needs al1 s - beta1 > 0,
+            // which is monotone in s, so only threads whose largest ordinary
+            // s passes reread their chunks (from L2)
+            const bool hot = al1 * smax - beta1 > 0.0f;
+            if (__any(hot)) {
+                if (hot) {
+                    const float *srow = p.S + i * ld;
+#pragma unroll 1
+                    for (int j = 0; j < J; ++j) {
+                        if (!(j < J - 1 || last_in)) continue;
+                        const int c = c0 + j * T * 4;
+                        const float4 sv = ld4(srow + c);
+                        const uint32_t mb = mb8[j * T + tid];
+                        const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+                        for (int e = 0; e < 4; ++e) {
+                            const int k = c + e;
+                            const float r = al1 * f4get(sv, e) - beta1;
+                            if (k < n && !((ex >> e) & 1u) && k != k1 && r > 0.0f) lp[k] = lp[k] + r;
+                        }
+                    }
+                }
+            }
+        } else {
+            // global partials: every column by its owner (no ordering between
+            // threads is needed), rereading S
+            const bool hot = al1 * smax - beta1 > 0.0f || has_sp || k1_owner == tid;
+            if (__any(hot)) {
+                if (hot) {
+                    const float *srow = p.S + i * ld;
+#pragma unroll 1
+                    for (int j = 0; j < J; ++j) {
+                        if (!(j < J - 1 || last_in)) continue;
+                        const int c = c0 + j * T * 4;
+                        const float4 sv = ld4(srow + c);
+                        const uint32_t sp = mb8[j * T + tid] >> 4;
+                        for (int e = 0; e < 4; ++e) {
+                            const int k = c + e;
+                            if (k >= n) break;
+                            float r = al1 * f4get(sv, e) - beta1;
+                            bool listed = false;
+                            if ((sp >> e) & 1u) {
+                                for (int qq = 0; qq < cnt; ++qq) {
+                                    if (st_col[sl][qq] == k) {
+                                        r = r + (lam * st_gam[sl][qq] + (k == k1 ? d : 0.0f));
+                                        listed = true;
+                                    }
+                                }
+                            }
+                            if (!listed && k == k1) r = r + d;
+                            if (k == ii) p.rdiag[ii] = r;
+                            else if (r > 0.0f) P[k] = P[k] + r;
+                        }
+                    }
                 }
             }
         }
 
-        // Column partials of max(0, R_{t+1}), touched only where positive.
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (!(j < J - 1 || last_in)) continue;
-            const bool full = (j < J - 1) || last_full;
-            const int c = c0 + j * T * 4;
-            const float4 sv = s4[j];
-            float4 rv4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) f4set(rv4, e, al1 * f4get(sv, e) - beta1);
-            if (wave_k1) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k1_mine && k1_le == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + d);
-            }
-            if (wave_own) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + own_g1[o]);
-            }
-            float4 pos;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                f4set(pos, e, ((full || c + e < n) && f4get(rv4, e) > 0.0f) ? f4get(rv4, e) : 0.0f);
-            if (wave_diag) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (dle == 4 * j + e) {
-                        f4set(pos, e, 0.0f);
-                        p.rdiag[ii] = f4get(rv4, e);
-                    }
-            }
-            const bool anyp = (pos.x > 0.0f) | (pos.y > 0.0f) | (pos.z > 0.0f) | (pos.w > 0.0f);
-            if constexpr (GP) {
-                if (anyp) {
-                    float4 acc = ld4(P + c);
-                    add4(acc, pos);
-                    st4(P + c, acc);
-                }
-            } else {
-                if (__any(anyp)) {
-                    float4 acc = lpart[j * T + tid];
-                    add4(acc, pos);
-                    lpart[j * T + tid] = acc;
-                }
-            }
-        }
-        // Overflowing rows (at most once per run): R_{t+1} and A_t written
-        // explicitly, same values; S is read again so that nothing of the row
-        // scan stays live for this path.
-        if (ovf) {
+        // Overflowing rows (at most once per run), written explicitly with
+        // the same values.  R_{t+1}: by wavefront 0, which holds the list.
+        if (wave == 0 && ovf) {
             float *Rx = Rx_base + i * ld;
-#pragma unroll 1
-            for (int j = 0; j < J; ++j) {
-                const int c = c0 + j * T * 4;
-                for (int e = 0; e < 4; ++e) {
-                    const int k = c + e;
-                    if (k >= n) break;
-                    float rv = al1 * p.S[i * ld + k] - beta1;
-                    if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
-                    for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
-                    Rx[k] = rv;
+            for (int k = lane; k < n; k += 64) {
+                float r = al1 * p.S[i * ld + k] - beta1;
+                bool listed = false;
+                for (int qq = 0; qq < cnt; ++qq) {
+                    if (st_col[sl][qq] == k) {
+                        r = r + (lam * st_gam[sl][qq] + (k == k1 ? d : 0.0f));
+                        listed = true;
+                    }
                 }
+                if (!listed && k == k1) r = r + d;
+                Rx[k] = r;
             }
         }
         if (xovf) {
+            // A_t: listed values from this row's output list (written before
+            // the reduction barrier by their holders)
+            __syncthreads();
             float *Arow = p.A + i * ld;
 #pragma unroll 1
             for (int j = 0; j < J; ++j) {
                 const int c = c0 + j * T * 4;
-                const uint32_t mb = mb8[j * T + tid];
+                const uint32_t mb = (j < J - 1 || last_in) ? mb8[j * T + tid] : 0u;
                 for (int e = 0; e < 4; ++e) {
                     const int k = c + e;
                     if (k >= n) break;
-                    const float sv = p.S[i * ld + k];
-                    float r = al * sv - beta;
-                    for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) r = r + own_g[o];
+                    const float s = p.S[i * ld + k];
+                    float r = al * s - beta;
+                    if ((mb >> (4 + e)) & 1u) {
+                        for (int qq = 0; qq < cnt; ++qq)
+                            if (st_col[sl][qq] == k) r = r + st_gam[sl][qq];
+                    }
                     float a = acol_t[k];
                     if (k == ii) {
                         a = adg;
                     } else if ((mb >> e) & 1u) {
                         for (int qq = 0; qq < xcnt; ++qq)
-                            if (xa_col[xs][qq] == k) a = xa_val[xs][qq];
+                            if (xcol_out[i * IMP_KA + qq] == k) a = xval_out[i * IMP_KA + qq];
                     } else if (r > 0.0f) {
                         a = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
                     }
@@ -1593,15 +1714,15 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 }
             }
         }
-        if constexpr (PREF) {
 #pragma unroll
-            for (int j = 0; j < J; ++j) s4[j] = s4n[j];
-        } else {
-            if (i + 1 < r1) load_row(i + 1, s4);
+        for (int u = 0; u < EPT; ++u) {
+            cur_c[u] = nxt_c[u];
+            cur_v[u] = nxt_v[u];
         }
     }
 
     if constexpr (!GP) {
+        __syncthreads();   // holders add to other threads' columns
 #pragma unroll
         for (int j = 0; j < J; ++j)
             if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, lpart[j * T + tid]);
@@ -1698,16 +1819,16 @@ hipError_t launch_imp_t(int kind, const ImpArgs &a, const PassPlan &pl, hipStrea
     return launch_imp_tj<T, J, false>(kind, a, pl, s);
 }
 
-template <int T, int J, bool PREF, bool GP>
+template <int T, int J, bool GP>
 hipError_t launch_ia_k(const ImpArgs &a, int grid, size_t lds, hipStream_t s) {
     static bool attr_set = false;   // per process; the attribute is per function
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_row_ia<T, J, PREF, GP>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_row_ia<T, J, GP>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsIa);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    k_row_ia<T, J, PREF, GP><<<grid, T, lds, s>>>(a);
+    k_row_ia<T, J, GP><<<grid, T, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1722,19 +1843,12 @@ size_t ia_lds(int64_t n, int grid, bool gp) {
 template <int T, int J>
 hipError_t launch_ia_t(const ImpArgs &a, const PassPlan &pl, hipStream_t s) {
     const bool gp = pl.lds_bytes < ia_lds(a.n, pl.grid, false);
-    // APX_IA_PREFETCH=0 selects the variant without the second S register set
-    static const bool pref = [] {
-        const char *v = getenv("APX_IA_PREFETCH");
-        return !(v && v[0] == '0');
-    }();
     if constexpr (J >= 7) {
-        if (gp) return pref ? launch_ia_k<T, J, true, true>(a, pl.grid, pl.lds_bytes, s)
-                            : launch_ia_k<T, J, false, true>(a, pl.grid, pl.lds_bytes, s);
+        if (gp) return launch_ia_k<T, J, true>(a, pl.grid, pl.lds_bytes, s);
     } else {
         if (gp) return hipErrorInvalidValue;
     }
-    return pref ? launch_ia_k<T, J, true, false>(a, pl.grid, pl.lds_bytes, s)
-                : launch_ia_k<T, J, false, false>(a, pl.grid, pl.lds_bytes, s);
+    return launch_ia_k<T, J, false>(a, pl.grid, pl.lds_bytes, s);
 }
 
 }  // namespace
