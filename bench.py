@@ -12,14 +12,16 @@ solved once each from a cold start, by PAP (Algorithm 2, 8 random uneven
 parts) and from the learned warm start, reporting wall time to the stop rule
 and whether the exemplar set is the FP64 oracle's ("time_to_exemplars").
 
-Prints one JSON line (see the fields below).  `value` is the algorithmic
-message traffic of the AP iterations divided by the whole step time, so
-similarity, preference and finalize time count against it.  An iteration
-with implicit responsibilities (the library's path at this size: R rebuilt
-from S and a short per-row state) moves 12 bytes per matrix element (read S,
-A; write A); one with explicit R moves 20 (read S, R, A; write A, R).
-`iteration_path` reports which ran and the rate the explicit form would need
-for the same iterations per second.
+Prints one JSON line (see the fields below).  `value` is the dense-form
+message traffic of the AP iterations, 20 bytes per matrix element and
+iteration (read S, R, A; write A, R), divided by the whole step time, so
+similarity, preference and finalize time count against it.  The library's
+path at this size keeps the messages implicitly and moves fewer bytes: with
+implicit R and A (cold start) an iteration reads S, 4 bytes per element;
+with implicit R only it reads S and A and writes A, 12 bytes.  The value is
+therefore an effective rate and can exceed the HBM peak; `iteration_path`
+reports which form ran and the bytes it actually needs, and `roofline`
+measures the dominant kernel against the peak on its own bytes.
 """
 from __future__ import annotations
 
@@ -35,8 +37,9 @@ if ROOT not in sys.path:
 
 N, D, K_MIX, SEED = 20000, 64, 50, 2001
 LAMBDA, MAX_ITER, CONV_ITER = 0.9, 2000, 15
-BYTES_EXPLICIT = 20               # explicit R: read S, R, A; write A, R (FP32)
+BYTES_EXPLICIT = 20               # explicit R and A: read S, R, A; write A, R (FP32)
 BYTES_IMPLICIT = 12               # implicit R: read S, A; write A (FP32)
+BYTES_IMPLICIT_A = 4              # implicit R and A: read S (FP32)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -50,9 +53,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-warm-compare", action="store_true")
     ap.add_argument("--counter-run", action="store_true",
-                    help="short fixed sequence for rocprofv3 --pmc runs: 4 AP iterations at N "
-                         "(ap_solve, fixed count), "
-                         "then a plain 1.6 GB device copy (the calibration kernel); prints no JSON")
+                    help="sequence for rocprofv3 --pmc runs: one ap_solve at N as a step runs it "
+                         "(to the stop rule), then a plain 1.6 GB device copy (the calibration "
+                         "kernel); prints no JSON")
     return ap.parse_args()
 
 
@@ -78,14 +81,16 @@ def cpu_baseline(pts, n_iter: int) -> dict:
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_n20000_d64_k50_seed2001.json")
 CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kernel
 
-# HBM bytes moved by one working full row pass at N=20000, from rocprofv3
+# HBM bytes moved per launch by the full row pass of the form that runs at
+# N=20000 (averaged over the launches of one solve), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs of `bench.py --counter-run`, each scaled by
 # what the same counter reads for the 1.6 GB copy (profiles/
-# row_pass_n20000_hbm_counters.md).  Valid only for the row-pass source with
-# this SHA-256; otherwise the benchmark reports traffic as null.
+# row_pass_n20000_hbm_counters.md).  Valid only for that form and the
+# row-pass source with this SHA-256; otherwise the benchmark reports traffic
+# as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 3204067369, "write": 1625317168, "implicit": True,
-                    "sha256": "c9da37445f4202dafb030c3ad878cf52cc35c6545adbd3ff591a95c6937b6762"}
+ROW_PASS_TRAFFIC = {"read": 1937108202, "write": 46140205, "path": "implicit_RA",
+                    "sha256": "b1ae2e6474e6c74f8bfc32d1a828c9340d0fe5a26e34b4d0afd6526a3c3f14b5"}
 PAP_K = 8
 
 
@@ -145,7 +150,7 @@ def counter_run(n: int) -> None:
     X = torch.from_numpy(pts.X).cuda()
     S, _ = apx.ap_similarity(X, pref="median", noise_seed=SEED, noise_rel=1e-12)
     R, A = apx.empty_matrix(n), apx.empty_matrix(n)
-    apx.ap_solve(S, R, A, LAMBDA, 4, 0)     # prologue and 4 full passes, as the benchmark runs them
+    apx.ap_solve(S, R, A, LAMBDA, MAX_ITER, CONV_ITER)    # the solve of one benchmark step
     torch.cuda.synchronize()
     src = torch.ones(CALIB_ELEMS, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -199,16 +204,17 @@ def main():
     apx.apx_profile_read()
     iters = 0
     alg_bytes = 0
-    imp_iters = exp_iters = 0
+    imp_iters = exp_iters = ia_iters = 0
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         _, res = step()
         iters += res.iterations
-        ni, ne, _ = apx.apx_last_solve_info()
+        ni, ne, na = apx.apx_last_solve_info()
         imp_iters += ni
         exp_iters += ne
+        ia_iters += na
         results.append(res)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -226,16 +232,28 @@ def main():
 
     elems = n * n
     ms_step = dt * 1e3 / args.steps
-    alg_bytes = (imp_iters * BYTES_IMPLICIT + exp_iters * BYTES_EXPLICIT) * elems
-    gbs = alg_bytes / dt / 1e9
+    ir_iters = imp_iters - ia_iters              # implicit R with explicit A
+    exec_bytes = (ia_iters * BYTES_IMPLICIT_A + ir_iters * BYTES_IMPLICIT + exp_iters * BYTES_EXPLICIT) * elems
+    gbs = iters * BYTES_EXPLICIT * elems / dt / 1e9
     avg_pass_ms = pass_ms / max(launches, 1)
-    implicit = imp_iters > 0 and exp_iters == 0
-    per_launch = (BYTES_IMPLICIT if implicit else BYTES_EXPLICIT) * elems
+    # the dominant row-pass kernel (profiled launches average over the form that ran)
+    if ia_iters == iters:
+        path, per_elem = "implicit_RA", BYTES_IMPLICIT_A
+        kernel = "k_row_ia (full iteration pass, implicit R and A)"
+    elif imp_iters == iters and ia_iters == 0:
+        path, per_elem = "implicit_R", BYTES_IMPLICIT
+        kernel = "k_row_imp (full iteration pass, implicit R)"
+    elif exp_iters == iters:
+        path, per_elem = "explicit", BYTES_EXPLICIT
+        kernel = "k_row_pass (full iteration pass)"
+    else:
+        path, per_elem = "mixed", exec_bytes / max(iters, 1) / elems
+        kernel = "row passes of mixed forms (hand-over during the run)"
+    per_launch = int(per_elem * elems)
     achieved = per_launch / (avg_pass_ms * 1e-3) / 1e9
     r0 = results[-1]
     traffic = None
-    kernel = "k_row_imp (full iteration pass, implicit R)" if implicit else "k_row_pass (full iteration pass)"
-    if (ROW_PASS_TRAFFIC is not None and n == N and implicit == ROW_PASS_TRAFFIC["implicit"]
+    if (ROW_PASS_TRAFFIC is not None and n == N and path == ROW_PASS_TRAFFIC["path"]
             and source_sha256(ROW_PASS_SRC) == ROW_PASS_TRAFFIC["sha256"]):
         traffic = round((ROW_PASS_TRAFFIC["read"] + ROW_PASS_TRAFFIC["write"]) / 1e9, 3)
     out = {
@@ -261,9 +279,14 @@ def main():
         "n_exemplars": r0.n_exemplars,
         "netsim": r0.netsim,
         "similarity_ms": round(sim_ms, 3),
-        "iteration_path": {"implicit_R_iterations": imp_iters, "explicit_R_iterations": exp_iters,
-                           "bytes_per_element": {"implicit": BYTES_IMPLICIT, "explicit": BYTES_EXPLICIT},
-                           "explicit_R_equivalent_GBps": round(iters * BYTES_EXPLICIT * elems / dt / 1e9, 2)},
+        "value_basis": f"dense-form traffic, {BYTES_EXPLICIT} B per matrix element and iteration "
+                       f"(effective rate; the form that ran moves fewer bytes, see iteration_path)",
+        "iteration_path": {"form": path,
+                           "implicit_RA_iterations": ia_iters, "implicit_R_iterations": ir_iters,
+                           "explicit_iterations": exp_iters,
+                           "bytes_per_element": {"implicit_RA": BYTES_IMPLICIT_A, "implicit_R": BYTES_IMPLICIT,
+                                                 "explicit": BYTES_EXPLICIT},
+                           "executed_GBps": round(exec_bytes / dt / 1e9, 2)},
         "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
