@@ -1151,21 +1151,63 @@ __device__ __forceinline__ void top2s_merge(Top2S &t, float ov1, int ok1, float 
     t.s1 = take ? os1 : t.s1;
     t.v2 = nv2;
 }
-// wg_reduce for Top2S (same order of merges).
+// max(a, b) as one med3 (no canonicalisation of the operands; no NaNs here).
+__device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+
+// Workgroup reduction of Top2S and ArgMax: DPP steps inside each 16-lane row
+// (quad swaps, half-row and row mirrors: every lane ends with its row's
+// merge), lane reads across the four rows, one LDS slot per wavefront, and
+// the same row reduction over the NW slots.  The merges only compare and
+// select, with ties broken by column, so any merge order gives the same
+// result.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ void red_merge(Top2S &t, ArgMax &m, float ov1, int ok1, float ov2, float os1, float odv,
+                                          int odk) {
+    const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
+    const float nv2 = max3f(fminf(t.v1, ov1), max3f(t.v2, ov2));   // second largest of both
+    t.v1 = take ? ov1 : t.v1;
+    t.k1 = take ? ok1 : t.k1;
+    t.s1 = take ? os1 : t.s1;
+    t.v2 = nv2;
+    argmax_merge(m, odv, odk);
+}
+template <int CTRL>
+__device__ __forceinline__ void red_step(Top2S &t, ArgMax &m) {
+    red_merge(t, m, dpp_f<CTRL>(t.v1), dpp_i<CTRL>(t.k1), dpp_f<CTRL>(t.v2), dpp_f<CTRL>(t.s1),
+              dpp_f<CTRL>(m.v), dpp_i<CTRL>(m.k));
+}
+__device__ __forceinline__ void red_row(Top2S &t, ArgMax &m) {
+    red_step<0xB1>(t, m);    // quad_perm [1,0,3,2]
+    red_step<0x4E>(t, m);    // quad_perm [2,3,0,1]
+    red_step<0x141>(t, m);   // row_half_mirror
+    red_step<0x140>(t, m);   // row_mirror
+}
+__device__ __forceinline__ float rdl_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+// the merge of rows 0..R-1 (lanes 0, 16, ...) as uniform values
+template <int R>
+__device__ __forceinline__ void red_rows(Top2S &t, ArgMax &m) {
+    Top2S u{rdl_f(t.v1, 0), __builtin_amdgcn_readlane(t.k1, 0), rdl_f(t.v2, 0), rdl_f(t.s1, 0)};
+    ArgMax w{rdl_f(m.v, 0), __builtin_amdgcn_readlane(m.k, 0)};
+#pragma unroll
+    for (int r = 1; r < R; ++r)
+        red_merge(u, w, rdl_f(t.v1, 16 * r), __builtin_amdgcn_readlane(t.k1, 16 * r), rdl_f(t.v2, 16 * r),
+                  rdl_f(t.s1, 16 * r), rdl_f(m.v, 16 * r), __builtin_amdgcn_readlane(m.k, 16 * r));
+    t = u;
+    m = w;
+}
 template <int NW>
 __device__ __forceinline__ void wg_reduce_s(Top2S &t2, ArgMax &dm, float (*sh_f)[4], int (*sh_i)[2], int lane,
                                             int wave) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const float ov1 = __shfl_xor(t2.v1, off, 64);
-        const int ok1 = __shfl_xor(t2.k1, off, 64);
-        const float ov2 = __shfl_xor(t2.v2, off, 64);
-        const float os1 = __shfl_xor(t2.s1, off, 64);
-        top2s_merge(t2, ov1, ok1, ov2, os1);
-        const float odv = __shfl_xor(dm.v, off, 64);
-        const int odk = __shfl_xor(dm.k, off, 64);
-        argmax_merge(dm, odv, odk);
-    }
+    static_assert(NW <= 16, "one slot per lane of the first row");
+    red_row(t2, dm);
+    red_rows<4>(t2, dm);
     if (lane == 0) {
         sh_f[wave][0] = t2.v1;
         sh_f[wave][1] = t2.v2;
@@ -1175,28 +1217,12 @@ __device__ __forceinline__ void wg_reduce_s(Top2S &t2, ArgMax &dm, float (*sh_f)
         sh_i[wave][1] = dm.k;
     }
     lds_barrier();
-    if constexpr (NW > 1) {
-        const bool has = lane < NW;
-        const int w = has ? lane : 0;
-        t2 = has ? Top2S{sh_f[w][0], sh_i[w][0], sh_f[w][1], sh_f[w][3]} : Top2S{kNegInf, INT32_MAX, kNegInf, 0.0f};
-        dm = has ? ArgMax{sh_f[w][2], sh_i[w][1]} : ArgMax{kNegInf, INT32_MAX};
-#pragma unroll
-        for (int off = NW / 2; off >= 1; off >>= 1) {
-            const float ov1 = __shfl_xor(t2.v1, off, 64);
-            const int ok1 = __shfl_xor(t2.k1, off, 64);
-            const float ov2 = __shfl_xor(t2.v2, off, 64);
-            const float os1 = __shfl_xor(t2.s1, off, 64);
-            top2s_merge(t2, ov1, ok1, ov2, os1);
-            const float odv = __shfl_xor(dm.v, off, 64);
-            const int odk = __shfl_xor(dm.k, off, 64);
-            argmax_merge(dm, odv, odk);
-        }
-        t2 = Top2S{__shfl(t2.v1, 0, 64), __shfl(t2.k1, 0, 64), __shfl(t2.v2, 0, 64), __shfl(t2.s1, 0, 64)};
-        dm = ArgMax{__shfl(dm.v, 0, 64), __shfl(dm.k, 0, 64)};
-    } else {
-        t2 = Top2S{sh_f[0][0], sh_i[0][0], sh_f[0][1], sh_f[0][3]};
-        dm = ArgMax{sh_f[0][2], sh_i[0][1]};
-    }
+    const bool has = lane < NW;
+    const int w = has ? lane : 0;
+    t2 = has ? Top2S{sh_f[w][0], sh_i[w][0], sh_f[w][1], sh_f[w][3]} : Top2S{kNegInf, INT32_MAX, kNegInf, 0.0f};
+    dm = has ? ArgMax{sh_f[w][2], sh_i[w][1]} : ArgMax{kNegInf, INT32_MAX};
+    red_row(t2, dm);
+    red_rows<1>(t2, dm);
 }
 
 template <int T, int J, bool GP>
@@ -1444,7 +1470,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 s1 = g1 ? s : s1;
                 v2 = __builtin_amdgcn_fmed3f(v1, v2, w);
                 v1 = g1 ? w : v1;
-                smax = (inb && (GP || !x)) ? fmaxf(smax, s) : smax;
+                smax = max3f(smax, (inb && (GP || !x)) ? s : kNegInf);
             }
             fch |= fr ? (1u << j) : 0u;
         }
