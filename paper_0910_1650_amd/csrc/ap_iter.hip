@@ -1154,12 +1154,6 @@ __device__ __forceinline__ void top2s_merge(Top2S &t, float ov1, int ok1, float 
 // max(a, b) as one med3 (no canonicalisation of the operands; no NaNs here).
 __device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
 
-// Workgroup reduction of Top2S and ArgMax: DPP steps inside each 16-lane row
-// (quad swaps, half-row and row mirrors: every lane ends with its row's
-// merge), lane reads across the four rows, one LDS slot per wavefront, and
-// the same row reduction over the NW slots.  The merges only compare and
-// select, with ties broken by column, so any merge order gives the same
-// result.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
@@ -1168,61 +1162,57 @@ template <int CTRL>
 __device__ __forceinline__ int dpp_i(int x) {
     return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ void red_merge(Top2S &t, ArgMax &m, float ov1, int ok1, float ov2, float os1, float odv,
-                                          int odk) {
+__device__ __forceinline__ float rdl_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+
+__device__ __forceinline__ void t2_merge(Top2S &t, float ov1, int ok1, float ov2, float os1) {
     const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
     const float nv2 = max3f(fminf(t.v1, ov1), max3f(t.v2, ov2));   // second largest of both
     t.v1 = take ? ov1 : t.v1;
     t.k1 = take ? ok1 : t.k1;
     t.s1 = take ? os1 : t.s1;
     t.v2 = nv2;
-    argmax_merge(m, odv, odk);
 }
 template <int CTRL>
-__device__ __forceinline__ void red_step(Top2S &t, ArgMax &m) {
-    red_merge(t, m, dpp_f<CTRL>(t.v1), dpp_i<CTRL>(t.k1), dpp_f<CTRL>(t.v2), dpp_f<CTRL>(t.s1),
-              dpp_f<CTRL>(m.v), dpp_i<CTRL>(m.k));
+__device__ __forceinline__ void t2_step(Top2S &t) {
+    t2_merge(t, dpp_f<CTRL>(t.v1), dpp_i<CTRL>(t.k1), dpp_f<CTRL>(t.v2), dpp_f<CTRL>(t.s1));
 }
-__device__ __forceinline__ void red_row(Top2S &t, ArgMax &m) {
-    red_step<0xB1>(t, m);    // quad_perm [1,0,3,2]
-    red_step<0x4E>(t, m);    // quad_perm [2,3,0,1]
-    red_step<0x141>(t, m);   // row_half_mirror
-    red_step<0x140>(t, m);   // row_mirror
+__device__ __forceinline__ void t2_row(Top2S &t) {
+    t2_step<0xB1>(t);    // quad_perm [1,0,3,2]
+    t2_step<0x4E>(t);    // quad_perm [2,3,0,1]
+    t2_step<0x141>(t);   // row_half_mirror
+    t2_step<0x140>(t);   // row_mirror
 }
-__device__ __forceinline__ float rdl_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
-// the merge of rows 0..R-1 (lanes 0, 16, ...) as uniform values
 template <int R>
-__device__ __forceinline__ void red_rows(Top2S &t, ArgMax &m) {
+__device__ __forceinline__ void t2_rows(Top2S &t) {
     Top2S u{rdl_f(t.v1, 0), __builtin_amdgcn_readlane(t.k1, 0), rdl_f(t.v2, 0), rdl_f(t.s1, 0)};
-    ArgMax w{rdl_f(m.v, 0), __builtin_amdgcn_readlane(m.k, 0)};
 #pragma unroll
     for (int r = 1; r < R; ++r)
-        red_merge(u, w, rdl_f(t.v1, 16 * r), __builtin_amdgcn_readlane(t.k1, 16 * r), rdl_f(t.v2, 16 * r),
-                  rdl_f(t.s1, 16 * r), rdl_f(m.v, 16 * r), __builtin_amdgcn_readlane(m.k, 16 * r));
+        t2_merge(u, rdl_f(t.v1, 16 * r), __builtin_amdgcn_readlane(t.k1, 16 * r), rdl_f(t.v2, 16 * r),
+                 rdl_f(t.s1, 16 * r));
     t = u;
-    m = w;
 }
+// Workgroup reduction of Top2S: DPP steps inside each 16-lane row (quad
+// swaps, half-row and row mirrors: every lane ends with its row's merge),
+// lane reads across the four rows, one LDS slot per wavefront, and the same
+// row reduction over the NW slots.  The merge only compares and selects,
+// with ties broken by column, so any merge order gives the same result.
 template <int NW>
-__device__ __forceinline__ void wg_reduce_s(Top2S &t2, ArgMax &dm, float (*sh_f)[4], int (*sh_i)[2], int lane,
-                                            int wave) {
+__device__ __forceinline__ void wg_reduce_t(Top2S &t2, float (*sh_f)[4], int (*sh_i)[2], int lane, int wave) {
     static_assert(NW <= 16, "one slot per lane of the first row");
-    red_row(t2, dm);
-    red_rows<4>(t2, dm);
+    t2_row(t2);
+    t2_rows<4>(t2);
     if (lane == 0) {
         sh_f[wave][0] = t2.v1;
         sh_f[wave][1] = t2.v2;
-        sh_f[wave][2] = dm.v;
         sh_f[wave][3] = t2.s1;
         sh_i[wave][0] = t2.k1;
-        sh_i[wave][1] = dm.k;
     }
     lds_barrier();
     const bool has = lane < NW;
     const int w = has ? lane : 0;
     t2 = has ? Top2S{sh_f[w][0], sh_i[w][0], sh_f[w][1], sh_f[w][3]} : Top2S{kNegInf, INT32_MAX, kNegInf, 0.0f};
-    dm = has ? ArgMax{sh_f[w][2], sh_i[w][1]} : ArgMax{kNegInf, INT32_MAX};
-    red_row(t2, dm);
-    red_rows<1>(t2, dm);
+    t2_row(t2);
+    t2_rows<1>(t2);
 }
 
 template <int T, int J, bool GP>
@@ -1241,7 +1231,11 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     __shared__ float st_beta[3];
     __shared__ int st_cnt[3];
     __shared__ float st_ad[3];
+    __shared__ float st_sd[3];                   // s(i,i)
+    __shared__ float st_gd[3];                   // gamma(i,i) when R-listed ...
+    __shared__ int st_gdr[3];                    // ... for the row stored here
     __shared__ int xa_new[NXS];
+    __shared__ int dec_fail[NXS];                // a column beats the diagonal
     extern __shared__ float4 dyn[];
     const int q = (p.n + 3) >> 2;
     const int mw = (q + 3) >> 2;                 // mask words per slot
@@ -1307,6 +1301,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const int c = xcnt_in[r];
         rcnt[r - r0] = c < 0 ? 0 : (c > IMP_KA ? IMP_KA : c);
     }
+    if (tid < 3) st_gdr[tid] = -1;
     int my_nex = 0, my_changed = 0;
     __syncthreads();
 
@@ -1316,17 +1311,22 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         if (tid == 2 * IMP_K) return __float_as_uint(beta_in[i]);
         if (tid == 2 * IMP_K + 1) return (uint32_t)cnt_in[i];
         if (tid == 2 * IMP_K + 2) return __float_as_uint(adiag_t[i]);
+        if (tid == 2 * IMP_K + 3) return __float_as_uint(p.S[i * ld + i]);
         return 0u;
     };
     // R state of row i into its LDS slot; the R-listed columns and the
     // diagonal are marked in the high nibble of the row's mask bytes
-    auto put_state = [&](int64_t i, uint32_t v, int rc) {
+    auto put_state = [&](int64_t i, uint32_t v, int rc, float rgam) {
         const int sl = (int)(i % 3);
         uint32_t *m = mask + (i % NXS) * mw;
         if (tid < IMP_K) {
             st_col[sl][tid] = (int)v;
             const int c = (int)v;
             if (tid < rc && (unsigned)c < (unsigned)n) atomicOr(&m[c >> 4], xbit(c) << 4);
+            if (tid < rc && c == (int)i) {
+                st_gd[sl] = rgam;
+                st_gdr[sl] = (int)i;
+            }
         } else if (tid < 2 * IMP_K) {
             st_gam[sl][tid - IMP_K] = __uint_as_float(v);
         } else if (tid == 2 * IMP_K) {
@@ -1335,6 +1335,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             st_cnt[sl] = (int)v;
         } else if (tid == 2 * IMP_K + 2) {
             st_ad[sl] = __uint_as_float(v);
+        } else if (tid == 2 * IMP_K + 3) {
+            st_sd[sl] = __uint_as_float(v);
         }
         if (tid == 0) atomicOr(&m[i >> 4], xbit((int)i) << 4);
     };
@@ -1358,7 +1360,10 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
 #pragma unroll
         for (int u = 0; u < EPT; ++u)
             if ((unsigned)xc[u] < (unsigned)n) atomicOr(&mask[xs * mw + (xc[u] >> 4)], xbit(xc[u]));
-        if (tid == 0) xa_new[xs] = 0;
+        if (tid == 0) {
+            xa_new[xs] = 0;
+            dec_fail[xs] = 0;
+        }
     };
     // acol_t of this thread's columns is the same for every row of the pass:
     // short rows keep it in registers, long rows read it per chunk
@@ -1379,7 +1384,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     float cur_v[EPT], nxt_v[EPT];
     if (r0 < r1) {
         const int rc = tid < IMP_K ? cnt_in[r0] : 0;
-        put_state(r0, fetch_state(r0), rc);
+        const float rgam = tid < IMP_K ? gam_in[r0 * IMP_K + tid] : 0.0f;
+        put_state(r0, fetch_state(r0), rc, rgam);
         fetch_x(r0, cur_c, cur_v);
         mark_x(r0, cur_c);
         load_row(r0, s4);
@@ -1393,7 +1399,17 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const float beta = st_beta[sl];
         const int cnt = st_cnt[sl];
         const float adg = st_ad[sl];
+        const float sdg = st_sd[sl];
+        const ColOwner dg = owner_of<T>(ii, tid);
+        const int dle = dg.mine ? 4 * dg.j + dg.e : -1;   // local index of the diagonal
         const int xcnt = rcnt[i - r0];
+        // The exemplar decision: column ii wins iff no column k < ii has
+        // a+r >= D and no column k > ii has a+r > D, D = a(i,i) + r(i,i)
+        // (lowest index on ties).  v > D is tested as v >= next float above D.
+        const float rdg = (al * sdg - beta) + (st_gdr[sl] == ii ? st_gd[sl] : 0.0f);
+        const float D = adg + rdg;
+        const float Dn = __int_as_float(D >= 0.0f ? (D == 0.0f ? 1 : __float_as_int(D) + 1) : __float_as_int(D) - 1);
+        bool fl = false;   // this thread saw a column that beats the diagonal
         const uint8_t *mb8 = mask8 + (size_t)xs * mw * 4;
         // previous exemplar flag of the row, read before the next row's S is
         // in flight (a later global load would wait for it)
@@ -1401,9 +1417,13 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // next row's R state and list, in flight during this row
         uint32_t nstate = 0u;
         int ncnt = 0;
+        float ngam = 0.0f;
         if (i + 1 < r1) {
             nstate = fetch_state(i + 1);
-            ncnt = tid < IMP_K ? cnt_in[i + 1] : 0;
+            if (tid < IMP_K) {
+                ncnt = cnt_in[i + 1];
+                ngam = gam_in[(i + 1) * IMP_K + tid];
+            }
             fetch_x(i + 1, nxt_c, nxt_v);
         }
         // R-list entry tid (lanes of wavefront 0): column, gamma, s, acol_t
@@ -1419,7 +1439,6 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 rk = -1;
             }
         }
-        const float sdg = tid == 0 ? p.S[i * ld + ii] : 0.0f;
         // exception-list entries: s(i,k) and t_k
         float xsv[EPT], xtv[EPT];
 #pragma unroll
@@ -1433,9 +1452,9 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
 
         // ---- scan of the ordinary elements
-        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf, s1 = 0.0f;
+        float v1 = kNegInf, v2 = kNegInf, s1 = 0.0f;
         float smax = kNegInf;   // largest s of the thread's columns that phase 2 leaves to it
-        int l1 = -1, dl = -1;
+        int l1 = -1;
         uint32_t fch = 0;       // chunks holding a first positive responsibility
         bool has_sp = false;    // the thread owns a special column (GP phase 2)
 #pragma unroll
@@ -1450,6 +1469,9 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             const uint32_t mb = mb8[j * T + tid];
             const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
             has_sp = has_sp || (mb >> 4) != 0u;
+            // columns of this chunk below the diagonal beat it with a tie
+            // (the diagonal's own chunk is finished after the scan)
+            const float dth = c + 3 < ii ? D : Dn;
             bool fr = false;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -1460,10 +1482,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 const bool pos = r > 0.0f;
                 fr = fr || (inb && !x && pos);
                 const float a = (x || pos || !inb) ? kNegInf : f4get(av, e);
-                const float v = a + r;
-                const bool gd = v > dv;
-                dl = gd ? 4 * j + e : dl;
-                dv = gd ? v : dv;
+                fl = fl || (a + r >= dth);
                 const float w = a + s;
                 const bool g1 = w > v1;
                 l1 = g1 ? 4 * j + e : l1;
@@ -1475,11 +1494,35 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             fch |= fr ? (1u << j) : 0u;
         }
         Top2S t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2, s1};
-        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
         auto merge = [&](float v, float w, int k, float s) {
-            argmax_merge(dm, v, k);
+            fl = fl || (k < ii ? v >= D : v > D);
             top2s_merge(t2, w, k, kNegInf, s);
         };
+        // the diagonal's chunk: its columns below the diagonal were tested
+        // against Dn; a tie with D there also beats the diagonal
+        if (__any(dle >= 0)) {
+            if (dle >= 0) {
+                float4 sv = s4[0];
+                float4 av;
+#pragma unroll
+                for (int jj = 1; jj < J; ++jj)
+                    if (jj == dle >> 2) sv = s4[jj];
+                if constexpr (ACV) {
+                    av = acv[0];
+#pragma unroll
+                    for (int jj = 1; jj < J; ++jj)
+                        if (jj == dle >> 2) av = acv[jj];
+                } else {
+                    av = ld4(acol_t + c0 + (dle >> 2) * T * 4);
+                }
+                const uint32_t mb = mb8[(dle >> 2) * T + tid];
+                const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+                for (int e = 0; e < (dle & 3); ++e) {
+                    const float r = al * f4get(sv, e) - beta;
+                    if (!((ex >> e) & 1u) && !(r > 0.0f) && f4get(av, e) + r == D) fl = true;
+                }
+            }
+        }
         // first positive responsibility: A from acol_{t-1}, a new list entry
         auto fresh = [&](int k, float s, float r) {
             const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
@@ -1516,17 +1559,14 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         if (rk >= 0) {
             const float r = (al * rs - beta) + rg;
             if (rk == ii) {
-                merge(adg + r, adg + rs, ii, rs);
+                top2s_merge(t2, adg + rs, ii, kNegInf, rs);
             } else if (!((mask8[(size_t)xs * mw * 4 + (rk >> 2)] >> (rk & 3)) & 1u)) {
                 if (r > 0.0f) fresh(rk, rs, r);
                 else merge(rav + r, rav + rs, rk, rs);
             }
         }
-        // the diagonal (thread 0) unless it is R-listed
-        if (tid == 0 && !rl_diag) {
-            const float r = al * sdg - beta;
-            merge(adg + r, adg + sdg, ii, sdg);
-        }
+        // the diagonal (thread 0) unless it is R-listed: top-2 only
+        if (tid == 0 && !rl_diag) top2s_merge(t2, adg + sdg, ii, kNegInf, sdg);
         // exception-list entries: A from the stored value
         bool xrl[EPT];   // the column is R-listed (its R-list holder forms the partial)
 #pragma unroll
@@ -1546,19 +1586,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 xval_out[i * IMP_KA + tid + u * T] = an;
             }
         }
+        if (__any(fl) && lane == 0) atomicOr(&dec_fail[xs], 1);
         __builtin_amdgcn_sched_barrier(0);
         if (i + 1 < r1) {
-            put_state(i + 1, nstate, ncnt);
+            put_state(i + 1, nstate, ncnt, ngam);
             mark_x(i + 1, nxt_c);
             load_row(i + 1, s4);
         }
         __builtin_amdgcn_sched_barrier(0);
 
-        wg_reduce_s<NW>(t2, dm, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        wg_reduce_t<NW>(t2, sh_f[i & 1], sh_i[i & 1], lane, wave);
         if (tid == 0) {
-            const int k = dm.k;
-            if (p.dec) p.dec[ii] = k;
-            const uint8_t ef = (uint8_t)(k == ii);
+            const uint8_t ef = (uint8_t)(dec_fail[xs] == 0);
             if (ef_prev != ef) my_changed = 1;
             p.eflag[ii] = ef;
             my_nex += ef;

@@ -164,3 +164,55 @@ def test_long_rows_global_partials():
     rng = float(Sd.max() - Sd.min())
     assert float((out["0"][0] - Re).abs().max()) <= TOL * rng
     assert float((out["0"][1] - Ae).abs().max()) <= TOL * rng
+
+
+def tie_matrix(n, dims, hi, seed, pref_q):
+    """Duplicated integer points: S = -||x_i - x_k||^2 is integer and every
+    column has a twin, so a+s and a+r are tied in many rows."""
+    rng = np.random.default_rng(seed)
+    base = rng.integers(0, hi, size=(n // 2, dims))
+    X = np.concatenate([base, base])[rng.permutation(n)].astype(np.float64)
+    S = -((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    off = S[~np.eye(n, dtype=bool)]
+    np.fill_diagonal(S, np.floor(np.quantile(off, pref_q)))
+    return S
+
+
+def tied_rows(M):
+    return int(((M == M.max(axis=1, keepdims=True)).sum(axis=1) > 1).sum())
+
+
+def test_exact_ties_against_oracle():
+    # damping 1/2 and a short fixed run on a small integer S: every message
+    # is a short dyadic fraction, exact in FP32 and FP64, so ties survive and
+    # the lowest-index rule decides them; all three forms equal the oracle
+    n = 64
+    say(f"exact ties n={n}")
+    S = tie_matrix(n, 1, 6, 4306, 0.5)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    ref = oracle.ap(S, 0.5, 10, 0)
+    assert tied_rows(ref.A + ref.R) > 0
+    for name, cr, ca in (("R and A", 16, 1024), ("R", 16, 0), ("explicit", 0, 0)):
+        R, A, idx, res, info = solve(Sd, cr, ca, lam=0.5, max_iter=10, conv_iter=0)
+        assert np.array_equal(idx.cpu().numpy(), ref.idx), name
+        assert np.array_equal(host(R), ref.R) and np.array_equal(host(A), ref.A), name
+        if name == "R and A":
+            # twins put several R-listed columns on one thread: the run may
+            # hand over to explicit messages before the end
+            assert info[2] >= 1
+            say(f"  implicit A for {info[2]} of 10 iterations")
+
+
+def test_ties_implicit_a_equals_implicit_r():
+    # 1024-thread rows: implicit A gives the same R, A and labels as implicit
+    # R with explicit A, bit for bit, on a matrix full of exact ties
+    n = 5000
+    say(f"ties, implicit A vs implicit R, n={n}")
+    S = tie_matrix(n, 2, 10, 4242 + n, 0.5)
+    Sd = apx.to_matrix(torch.from_numpy(S.astype(np.float32)))
+    Ra, Aa, ia, ra, info = solve(Sd, 16, 1024, lam=0.5, max_iter=30, conv_iter=0)
+    Rr, Ar, ir, rr, _ = solve(Sd, 16, 0, lam=0.5, max_iter=30, conv_iter=0)
+    say(f"  implicit A for {info[2]} of 30 iterations")
+    assert info[2] >= 5          # (twins can overflow the R list: both runs hand over alike)
+    assert tied_rows(host(Aa) + host(Ra)) > 0 and tied_rows(host(Aa) + S) > 0
+    assert torch.equal(ia, ir) and torch.equal(Ra, Rr) and torch.equal(Aa, Ar)
