@@ -1136,21 +1136,6 @@ constexpr int kMaxDynLdsIa = 160 * 1024 - 4 * 1024;
 
 __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) << 3) + (k & 3)); }
 
-// Top-2 of a+s that also carries s at the top-1 column.
-struct Top2S {
-    float v1;
-    int k1;
-    float v2;
-    float s1;
-};
-__device__ __forceinline__ void top2s_merge(Top2S &t, float ov1, int ok1, float ov2, float os1) {
-    const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
-    const float nv2 = take ? fmaxf(ov2, t.v1) : fmaxf(t.v2, ov1);
-    t.v1 = take ? ov1 : t.v1;
-    t.k1 = take ? ok1 : t.k1;
-    t.s1 = take ? os1 : t.s1;
-    t.v2 = nv2;
-}
 // max(a, b) as one med3 (no canonicalisation of the operands; no NaNs here).
 __device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
 
@@ -1164,55 +1149,56 @@ __device__ __forceinline__ int dpp_i(int x) {
 }
 __device__ __forceinline__ float rdl_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
 
-__device__ __forceinline__ void t2_merge(Top2S &t, float ov1, int ok1, float ov2, float os1) {
-    const bool take = (ov1 > t.v1) || (ov1 == t.v1 && ok1 < t.k1);
-    const float nv2 = max3f(fminf(t.v1, ov1), max3f(t.v2, ov2));   // second largest of both
-    t.v1 = take ? ov1 : t.v1;
-    t.k1 = take ? ok1 : t.k1;
-    t.s1 = take ? os1 : t.s1;
-    t.v2 = nv2;
-}
 template <int CTRL>
-__device__ __forceinline__ void t2_step(Top2S &t) {
-    t2_merge(t, dpp_f<CTRL>(t.v1), dpp_i<CTRL>(t.k1), dpp_f<CTRL>(t.v2), dpp_f<CTRL>(t.s1));
+__device__ __forceinline__ float dmax(float x) { return max3f(x, dpp_f<CTRL>(x)); }
+template <int CTRL>
+__device__ __forceinline__ int dmin(int x) { return min(x, dpp_i<CTRL>(x)); }
+// max / min over each 16-lane row (every lane of the row gets it): quad
+// swaps, then half-row and row mirrors
+__device__ __forceinline__ float row_max(float x) {
+    return dmax<0x140>(dmax<0x141>(dmax<0x4E>(dmax<0xB1>(x))));
 }
-__device__ __forceinline__ void t2_row(Top2S &t) {
-    t2_step<0xB1>(t);    // quad_perm [1,0,3,2]
-    t2_step<0x4E>(t);    // quad_perm [2,3,0,1]
-    t2_step<0x141>(t);   // row_half_mirror
-    t2_step<0x140>(t);   // row_mirror
+__device__ __forceinline__ int row_min(int x) {
+    return dmin<0x140>(dmin<0x141>(dmin<0x4E>(dmin<0xB1>(x))));
 }
-template <int R>
-__device__ __forceinline__ void t2_rows(Top2S &t) {
-    Top2S u{rdl_f(t.v1, 0), __builtin_amdgcn_readlane(t.k1, 0), rdl_f(t.v2, 0), rdl_f(t.s1, 0)};
-#pragma unroll
-    for (int r = 1; r < R; ++r)
-        t2_merge(u, rdl_f(t.v1, 16 * r), __builtin_amdgcn_readlane(t.k1, 16 * r), rdl_f(t.v2, 16 * r),
-                 rdl_f(t.s1, 16 * r));
-    t = u;
+__device__ __forceinline__ float wave_max(float x) {
+    x = row_max(x);
+    return max3f(max3f(rdl_f(x, 0), rdl_f(x, 16)), max3f(rdl_f(x, 32), rdl_f(x, 48)));
 }
-// Workgroup reduction of Top2S: DPP steps inside each 16-lane row (quad
-// swaps, half-row and row mirrors: every lane ends with its row's merge),
-// lane reads across the four rows, one LDS slot per wavefront, and the same
-// row reduction over the NW slots.  The merge only compares and selects,
-// with ties broken by column, so any merge order gives the same result.
+__device__ __forceinline__ int wave_min(int x) {
+    x = row_min(x);
+    return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+               min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+// Workgroup top-2 of a+s from each lane's (v1, k1, v2), in three passes
+// that need no merge order: the largest v1, the lowest column reaching it,
+// and the largest of the winner's v2 and every other lane's v1 (a candidate
+// column is held by one lane only).  Per wavefront with DPP row steps and
+// lane reads, then over one LDS slot per wavefront in the first row.
 template <int NW>
-__device__ __forceinline__ void wg_reduce_t(Top2S &t2, float (*sh_f)[4], int (*sh_i)[2], int lane, int wave) {
+__device__ __forceinline__ void wg_top2(Top2 &t, float (*sh_f)[4], int (*sh_i)[2], int lane, int wave) {
     static_assert(NW <= 16, "one slot per lane of the first row");
-    t2_row(t2);
-    t2_rows<4>(t2);
+    {
+        const float V = wave_max(t.v1);
+        const int K = wave_min(t.v1 == V ? t.k1 : INT32_MAX);
+        const float V2 = wave_max(t.v1 == V && t.k1 == K ? t.v2 : t.v1);
+        t = Top2{V, K, V2};
+    }
     if (lane == 0) {
-        sh_f[wave][0] = t2.v1;
-        sh_f[wave][1] = t2.v2;
-        sh_f[wave][3] = t2.s1;
-        sh_i[wave][0] = t2.k1;
+        sh_f[wave][0] = t.v1;
+        sh_f[wave][1] = t.v2;
+        sh_i[wave][0] = t.k1;
     }
     lds_barrier();
     const bool has = lane < NW;
     const int w = has ? lane : 0;
-    t2 = has ? Top2S{sh_f[w][0], sh_i[w][0], sh_f[w][1], sh_f[w][3]} : Top2S{kNegInf, INT32_MAX, kNegInf, 0.0f};
-    t2_row(t2);
-    t2_rows<1>(t2);
+    const float v1 = has ? sh_f[w][0] : kNegInf;
+    const int k1 = has ? sh_i[w][0] : INT32_MAX;
+    const float v2 = has ? sh_f[w][1] : kNegInf;
+    const float V = rdl_f(row_max(v1), 0);
+    const int K = __builtin_amdgcn_readlane(row_min(v1 == V ? k1 : INT32_MAX), 0);
+    const float V2 = rdl_f(row_max(v1 == V && k1 == K ? v2 : v1), 0);
+    t = Top2{V, K, V2};
 }
 
 template <int T, int J, bool GP>
@@ -1452,7 +1438,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
 
         // ---- scan of the ordinary elements
-        float v1 = kNegInf, v2 = kNegInf, s1 = 0.0f;
+        float v1 = kNegInf, v2 = kNegInf;
         float smax = kNegInf;   // largest s of the thread's columns that phase 2 leaves to it
         int l1 = -1;
         uint32_t fch = 0;       // chunks holding a first positive responsibility
@@ -1486,17 +1472,16 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 const float w = a + s;
                 const bool g1 = w > v1;
                 l1 = g1 ? 4 * j + e : l1;
-                s1 = g1 ? s : s1;
                 v2 = __builtin_amdgcn_fmed3f(v1, v2, w);
                 v1 = g1 ? w : v1;
                 smax = max3f(smax, (inb && (GP || !x)) ? s : kNegInf);
             }
             fch |= fr ? (1u << j) : 0u;
         }
-        Top2S t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2, s1};
-        auto merge = [&](float v, float w, int k, float s) {
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        auto merge = [&](float v, float w, int k) {
             fl = fl || (k < ii ? v >= D : v > D);
-            top2s_merge(t2, w, k, kNegInf, s);
+            top2_merge(t2, w, k, kNegInf);
         };
         // the diagonal's chunk: its columns below the diagonal were tested
         // against Dn; a tie with D there also beats the diagonal
@@ -1526,7 +1511,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // first positive responsibility: A from acol_{t-1}, a new list entry
         auto fresh = [&](int k, float s, float r) {
             const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
-            merge(an + r, an + s, k, s);
+            merge(an + r, an + s, k);
             const int pos = xcnt + atomicAdd(&xa_new[xs], 1);
             if (pos < xcap) {
                 xcol_out[i * IMP_KA + pos] = k;
@@ -1559,14 +1544,14 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         if (rk >= 0) {
             const float r = (al * rs - beta) + rg;
             if (rk == ii) {
-                top2s_merge(t2, adg + rs, ii, kNegInf, rs);
+                top2_merge(t2, adg + rs, ii, kNegInf);
             } else if (!((mask8[(size_t)xs * mw * 4 + (rk >> 2)] >> (rk & 3)) & 1u)) {
                 if (r > 0.0f) fresh(rk, rs, r);
-                else merge(rav + r, rav + rs, rk, rs);
+                else merge(rav + r, rav + rs, rk);
             }
         }
         // the diagonal (thread 0) unless it is R-listed: top-2 only
-        if (tid == 0 && !rl_diag) top2s_merge(t2, adg + sdg, ii, kNegInf, sdg);
+        if (tid == 0 && !rl_diag) top2_merge(t2, adg + sdg, ii, kNegInf);
         // exception-list entries: A from the stored value
         bool xrl[EPT];   // the column is R-listed (its R-list holder forms the partial)
 #pragma unroll
@@ -1581,7 +1566,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                         if (st_col[sl][qq] == k) r = r + st_gam[sl][qq];
                 }
                 const float an = lam * cur_v[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
-                merge(an + r, an + xsv[u], k, xsv[u]);
+                merge(an + r, an + xsv[u], k);
                 xcol_out[i * IMP_KA + tid + u * T] = k;
                 xval_out[i * IMP_KA + tid + u * T] = an;
             }
@@ -1595,7 +1580,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
         __builtin_amdgcn_sched_barrier(0);
 
-        wg_reduce_t<NW>(t2, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        wg_top2<NW>(t2, sh_f[i & 1], sh_i[i & 1], lane, wave);
         if (tid == 0) {
             const uint8_t ef = (uint8_t)(dec_fail[xs] == 0);
             if (ef_prev != ef) my_changed = 1;
@@ -1660,7 +1645,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             }
             if (tid == 0) {
                 if (pos1 < 0) {
-                    const float r = (al1 * t2.s1 - beta1) + d;
+                    // a new list column: its s (one load, rare once the lists settle)
+                    const float r = (al1 * p.S[i * ld + k1] - beta1) + d;
                     if (k1 == ii) p.rdiag[ii] = r;
                     else if (r > 0.0f) lp[k1] = lp[k1] + r;
                 }
