@@ -101,9 +101,11 @@ apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n);
  * iteration reads S and writes no matrix (4 bytes per element).  When a row
  * needs more entries, A is made explicit and the run continues with
  * explicit A.  0 = explicit A; default 1024 (the maximum); the environment
- * variable APX_IMPLICIT_A sets it at context creation.  A is the same
- * arithmetic as the explicit update, element for element. */
-apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity);
+ * variable APX_IMPLICIT_A sets it at context creation.  Only cold starts
+ * with n >= min_n use it (default 4096: below that the explicit pass is
+ * faster); with it, R is implicit too whatever apx_set_implicit's min_n.
+ * A is the same arithmetic as the explicit update, element for element. */
+apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity, int64_t min_n);
 
 /* apx_last_solve_info -- how many iterations of the last ap_solve on this
  * context ran with implicit R and how many with explicit R; and (nullable)

@@ -64,7 +64,7 @@ SIGNATURES = {
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
-    "apx_set_implicit_a": (ctypes.c_int, [_P, _I32]),
+    "apx_set_implicit_a": (ctypes.c_int, [_P, _I32, _I64]),
     "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "apx_autotune": (ctypes.c_int, [_P, _I64]),
     "apx_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -253,11 +253,12 @@ def apx_set_implicit(list_capacity: int, min_n: int = 8192, device=None) -> None
     _check(ctx, lib().apx_set_implicit(ctx, list_capacity, min_n), "apx_set_implicit")
 
 
-def apx_set_implicit_a(list_capacity: int, device=None) -> None:
-    """Implicit availabilities in ap_solve on a cold start (with implicit R):
-    exception list capacity 1..1024 per row, or 0 for explicit A."""
+def apx_set_implicit_a(list_capacity: int, min_n: int = 4096, device=None) -> None:
+    """Implicit availabilities in ap_solve on a cold start with n >= min_n
+    (with implicit R): exception list capacity 1..1024 per row, or 0 for
+    explicit A."""
     ctx = context(device)
-    _check(ctx, lib().apx_set_implicit_a(ctx, list_capacity), "apx_set_implicit_a")
+    _check(ctx, lib().apx_set_implicit_a(ctx, list_capacity, min_n), "apx_set_implicit_a")
 
 
 def apx_last_solve_info(device=None) -> tuple[int, int, int]:

@@ -420,11 +420,13 @@ apx_status apx_set_implicit(apx_ctx *ctx, int32_t list_capacity, int64_t min_n) 
     return APX_OK;
 }
 
-apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity) {
+apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity, int64_t min_n) {
     if (!ctx) return APX_EINVAL;
     if (list_capacity < 0 || list_capacity > IMP_KA)
         return set_err(ctx, APX_EINVAL, "exception list capacity must be in [0, %d]", IMP_KA);
+    if (min_n < 0) return set_err(ctx, APX_EINVAL, "min_n < 0");
     ctx->implicit_a = list_capacity;
+    ctx->implicit_a_min_n = min_n;
     return APX_OK;
 }
 
@@ -535,13 +537,14 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     // R_t lives in buf[t & 1]; buf[0] is the caller's R.  With R_0 = 0 (cold
     // start or A_0 only) R is kept implicitly (ImpArgs) unless disabled.
     float *buf[2] = {R, w.R2};
-    PassPlan ipl{};
-    bool implicit = ctx->implicit_k > 0 && n >= ctx->implicit_min_n && warm != APX_WARM_AR &&
-                    imp_plan(n, ctx->num_cus, &ipl);
+    // Cold start: A is kept implicitly too (XLayout) unless disabled; each
+    // form has its own size threshold (below it the explicit pass is faster).
+    PassPlan ipl{}, apl{};
+    const bool r_ok = ctx->implicit_k > 0 && warm != APX_WARM_AR && imp_plan(n, ctx->num_cus, &ipl);
+    bool imp_a = r_ok && warm == APX_COLD && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
+                 ia_plan(n, ctx->num_cus, &apl);
+    bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
-    // Cold start: A is kept implicitly too (XLayout) unless disabled.
-    PassPlan apl{};
-    bool imp_a = implicit && warm == APX_COLD && ctx->implicit_a > 0 && ia_plan(n, ctx->num_cus, &apl);
     int32_t ia_until = imp_a ? INT32_MAX : 0;       // last iteration run with implicit A
     if (implicit) {
         // parity 0 holds R_0 = 0: beta = 0 and empty lists

@@ -243,6 +243,7 @@ struct apx_ctx {
     int32_t last_imp_iters = 0;       // iterations of the last ap_solve run with implicit R
     int32_t last_exp_iters = 0;       // ... and with explicit R
     int implicit_a = apx::IMP_KA;     // implicit-A exception list capacity (0 = explicit A)
+    int64_t implicit_a_min_n = 4096;  // smaller cold starts run explicit (faster there)
     int32_t last_ia_iters = 0;        // iterations of the last ap_solve run with implicit A
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use

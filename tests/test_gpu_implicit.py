@@ -36,6 +36,7 @@ def host(M):
 def restore():
     yield
     apx.apx_set_implicit(16, 8192)
+    apx.apx_set_implicit_a(1024, 4096)
     apx.apx_set_graphs(True)
 
 
@@ -47,6 +48,7 @@ def mixture(n, seed, d=8, k=12):
 
 def solve(Sd, cap, lam=0.9, max_iter=2000, conv_iter=15, warm=apx.APX_COLD, A0=None):
     apx.apx_set_implicit(cap, 0)     # every size: these tests use small problems
+    apx.apx_set_implicit_a(0, 0)     # explicit A (implicit A: test_gpu_implicit_a.py)
     n = Sd.shape[0]
     R, A = apx.empty_matrix(n), apx.empty_matrix(n)
     if A0 is not None:
@@ -110,6 +112,7 @@ def test_warm_a_start_matches_explicit():
     out = {}
     for cap in (16, 0):
         apx.apx_set_implicit(cap, 0)
+        apx.apx_set_implicit_a(0, 0)
         R, A = apx.empty_matrix(n), apx.empty_matrix(n)
         idx, res, _ = apx.pap_solve(Sd, R, A, 4, damping=0.9, max_iter=2000, conv_iter=15)
         torch.cuda.synchronize()

@@ -40,7 +40,7 @@ def host(M):
 def restore():
     yield
     apx.apx_set_implicit(16, 8192)
-    apx.apx_set_implicit_a(1024)
+    apx.apx_set_implicit_a(1024, 4096)
     apx.apx_set_graphs(True)
     os.environ.pop("APX_IMPLICIT_A_GP", None)
 
@@ -53,7 +53,7 @@ def mixture(n, seed, d=8, k=12):
 
 def solve(Sd, cap_r, cap_a, lam=0.9, max_iter=2000, conv_iter=15):
     apx.apx_set_implicit(cap_r, 0)     # every size: these tests use small problems
-    apx.apx_set_implicit_a(cap_a)
+    apx.apx_set_implicit_a(cap_a, 0)
     n = Sd.shape[0]
     R, A = apx.empty_matrix(n), apx.empty_matrix(n)
     idx, res = apx.ap_solve(Sd, R, A, lam, max_iter, conv_iter)
