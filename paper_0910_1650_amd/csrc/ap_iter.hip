@@ -1173,31 +1173,31 @@ __device__ __forceinline__ int wave_min(int x) {
 // Workgroup top-2 of a+s from each lane's (v1, k1, v2), in three passes
 // that need no merge order: the largest v1, the lowest column reaching it,
 // and the largest of the winner's v2 and every other lane's v1 (a candidate
-// column is held by one lane only).  Per wavefront with DPP row steps and
-// lane reads, then over one LDS slot per wavefront in the first row.
+// column is held by one lane only).  Each 16-lane row reduces with DPP and
+// writes one LDS slot (4 per wavefront); after the barrier every wavefront
+// reduces the 4*NW slots, one per lane.
 template <int NW>
-__device__ __forceinline__ void wg_top2(Top2 &t, float (*sh_f)[4], int (*sh_i)[2], int lane, int wave) {
-    static_assert(NW <= 16, "one slot per lane of the first row");
+__device__ __forceinline__ void wg_top2(Top2 &t, float (*sh_f)[2], int *sh_i, int lane, int wave) {
+    static_assert(4 * NW <= 64, "one slot per lane");
     {
-        const float V = wave_max(t.v1);
-        const int K = wave_min(t.v1 == V ? t.k1 : INT32_MAX);
-        const float V2 = wave_max(t.v1 == V && t.k1 == K ? t.v2 : t.v1);
-        t = Top2{V, K, V2};
-    }
-    if (lane == 0) {
-        sh_f[wave][0] = t.v1;
-        sh_f[wave][1] = t.v2;
-        sh_i[wave][0] = t.k1;
+        const float V = row_max(t.v1);
+        const int K = row_min(t.v1 == V ? t.k1 : INT32_MAX);
+        const float V2 = row_max(t.v1 == V && t.k1 == K ? t.v2 : t.v1);
+        if ((lane & 15) == 0) {
+            const int slot = wave * 4 + (lane >> 4);
+            sh_f[slot][0] = V;
+            sh_f[slot][1] = V2;
+            sh_i[slot] = K;
+        }
     }
     lds_barrier();
-    const bool has = lane < NW;
-    const int w = has ? lane : 0;
-    const float v1 = has ? sh_f[w][0] : kNegInf;
-    const int k1 = has ? sh_i[w][0] : INT32_MAX;
-    const float v2 = has ? sh_f[w][1] : kNegInf;
-    const float V = rdl_f(row_max(v1), 0);
-    const int K = __builtin_amdgcn_readlane(row_min(v1 == V ? k1 : INT32_MAX), 0);
-    const float V2 = rdl_f(row_max(v1 == V && k1 == K ? v2 : v1), 0);
+    const bool has = lane < 4 * NW;
+    const float v1 = has ? sh_f[lane][0] : kNegInf;
+    const int k1 = has ? sh_i[lane] : INT32_MAX;
+    const float v2 = has ? sh_f[lane][1] : kNegInf;
+    const float V = wave_max(v1);
+    const int K = wave_min(v1 == V ? k1 : INT32_MAX);
+    const float V2 = wave_max(v1 == V && k1 == K ? v2 : v1);
     t = Top2{V, K, V2};
 }
 
@@ -1210,8 +1210,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     static_assert(IMP_K <= 64, "R-list holders are lanes of wavefront 0");
 
     if (p.st->frozen) return;
-    __shared__ float sh_f[2][NW][4];
-    __shared__ int sh_i[2][NW][2];
+    __shared__ float sh_f[2][4 * NW][2];
+    __shared__ int sh_i[2][4 * NW];
     __shared__ int st_col[3][IMP_K];
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
@@ -1464,17 +1464,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 const float s = f4get(sv, e);
                 const float r = al * s - beta;
                 const bool inb = full || c + e < n;
-                const bool x = (ex >> e) & 1u;
+                // one test of the mask bit, in the "ordinary" sense only
+                const bool nx = ((ex >> e) & 1u) == 0u;
                 const bool pos = r > 0.0f;
-                fr = fr || (inb && !x && pos);
-                const float a = (x || pos || !inb) ? kNegInf : f4get(av, e);
+                fr = fr || (nx && pos && inb);
+                const float a = (nx && !pos && inb) ? f4get(av, e) : kNegInf;
                 fl = fl || (a + r >= dth);
                 const float w = a + s;
                 const bool g1 = w > v1;
                 l1 = g1 ? 4 * j + e : l1;
                 v2 = __builtin_amdgcn_fmed3f(v1, v2, w);
                 v1 = g1 ? w : v1;
-                smax = max3f(smax, (inb && (GP || !x)) ? s : kNegInf);
+                smax = max3f(smax, (inb && (GP || nx)) ? s : kNegInf);
             }
             fch |= fr ? (1u << j) : 0u;
         }
