@@ -1137,7 +1137,10 @@ constexpr int kMaxDynLdsIa = 160 * 1024 - 4 * 1024;
 __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) << 3) + (k & 3)); }
 
 // max(a, b) as one med3 (no canonicalisation of the operands; no NaNs here).
-__device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+// max(a, b) for a, b below +inf (finite values and the -inf sentinel): one
+// v_med3 against the largest finite float, which needs no NaN quieting of
+// its inputs (a max against +inf is folded into a canonicalising max)
+__device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 3.40282347e+38f); }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
@@ -1212,7 +1215,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     if (p.st->frozen) return;
     __shared__ float sh_f[2][4 * NW][2];
     __shared__ int sh_i[2][4 * NW];
-    __shared__ int st_col[3][IMP_K];
+    __shared__ __align__(16) int st_col[3][IMP_K];
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
     __shared__ int st_cnt[3];
@@ -1245,6 +1248,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     const int cl = ((J - 1) * T + tid) * 4;
     const bool last_in = cl < n;
     const bool last_full = cl + 3 < n;
+    // mask bits of the last chunk's columns at or beyond n (both nibbles)
+    const uint32_t oob_bits = last_full ? 0u : (0x11u * ((0xFu << (n - cl > 0 ? n - cl : 0)) & 0xFu)) & 0xFFu;
     const int tpass = p.st->iter + 1;
     const float al = p.st->imp_al;               // alpha_t
     const float al1 = p.st->imp_al1;             // alpha_{t+1}
@@ -1291,48 +1296,59 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     int my_nex = 0, my_changed = 0;
     __syncthreads();
 
+    // The next row's R state is fetched and staged by wavefront SW (on
+    // another SIMD than wavefront 0, which holds the R list, and the
+    // wavefronts that hold the exception lists' first entries): one word per
+    // lane: list columns, gammas, beta, count, a(i,i), s(i,i)
+    constexpr int SW = 3;
+    static_assert(NW > SW, "state wavefront");
+    const bool sw = wave == SW;
     auto fetch_state = [&](int64_t i) -> uint32_t {
-        if (tid < IMP_K) return (uint32_t)col_in[i * IMP_K + tid];
-        if (tid < 2 * IMP_K) return __float_as_uint(gam_in[i * IMP_K + tid - IMP_K]);
-        if (tid == 2 * IMP_K) return __float_as_uint(beta_in[i]);
-        if (tid == 2 * IMP_K + 1) return (uint32_t)cnt_in[i];
-        if (tid == 2 * IMP_K + 2) return __float_as_uint(adiag_t[i]);
-        if (tid == 2 * IMP_K + 3) return __float_as_uint(p.S[i * ld + i]);
-        return 0u;
+        if (!sw || lane >= 2 * IMP_K + 4) return 0u;
+        const void *src = lane < IMP_K ? (const void *)(col_in + i * IMP_K + lane)
+                        : lane < 2 * IMP_K ? (const void *)(gam_in + i * IMP_K + lane - IMP_K)
+                        : lane == 2 * IMP_K ? (const void *)(beta_in + i)
+                        : lane == 2 * IMP_K + 1 ? (const void *)(cnt_in + i)
+                        : lane == 2 * IMP_K + 2 ? (const void *)(adiag_t + i)
+                        : (const void *)(p.S + i * ld + i);
+        return *reinterpret_cast<const uint32_t *>(src);
     };
     // R state of row i into its LDS slot; the R-listed columns and the
     // diagonal are marked in the high nibble of the row's mask bytes
     auto put_state = [&](int64_t i, uint32_t v, int rc, float rgam) {
+        if (!sw) return;
         const int sl = (int)(i % 3);
         uint32_t *m = mask + (i % NXS) * mw;
-        if (tid < IMP_K) {
-            st_col[sl][tid] = (int)v;
+        if (lane < IMP_K) {
+            st_col[sl][lane] = (int)v;
             const int c = (int)v;
-            if (tid < rc && (unsigned)c < (unsigned)n) atomicOr(&m[c >> 4], xbit(c) << 4);
-            if (tid < rc && c == (int)i) {
+            if (lane < rc && (unsigned)c < (unsigned)n) atomicOr(&m[c >> 4], xbit(c) << 4);
+            if (lane < rc && c == (int)i) {
                 st_gd[sl] = rgam;
                 st_gdr[sl] = (int)i;
             }
-        } else if (tid < 2 * IMP_K) {
-            st_gam[sl][tid - IMP_K] = __uint_as_float(v);
-        } else if (tid == 2 * IMP_K) {
+        } else if (lane < 2 * IMP_K) {
+            st_gam[sl][lane - IMP_K] = __uint_as_float(v);
+        } else if (lane == 2 * IMP_K) {
             st_beta[sl] = __uint_as_float(v);
-        } else if (tid == 2 * IMP_K + 1) {
+        } else if (lane == 2 * IMP_K + 1) {
             st_cnt[sl] = (int)v;
-        } else if (tid == 2 * IMP_K + 2) {
+        } else if (lane == 2 * IMP_K + 2) {
             st_ad[sl] = __uint_as_float(v);
-        } else if (tid == 2 * IMP_K + 3) {
+        } else if (lane == 2 * IMP_K + 3) {
             st_sd[sl] = __uint_as_float(v);
         }
-        if (tid == 0) atomicOr(&m[i >> 4], xbit((int)i) << 4);
+        if (lane == 0) atomicOr(&m[i >> 4], xbit((int)i) << 4);
     };
-    // Exception list of a row: thread tid holds entries tid + u*T in
-    // registers (column -1 when absent).
+    // Exception list of a row: thread tid holds entries xq0 + u*T in
+    // registers (column -1 when absent); the first entries go to wavefronts
+    // 1.. so that wavefront 0, which holds the R list, does not hold them too
+    const int xq0 = (tid + T - 64) % T;
     auto fetch_x = [&](int64_t i, int *xc, float *xv) {
         const int len = rcnt[i - r0];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
-            const int qx = tid + u * T;
+            const int qx = xq0 + u * T;
             xc[u] = -1;
             xv[u] = 0.0f;
             if (qx < len) {
@@ -1350,6 +1366,21 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             xa_new[xs] = 0;
             dec_fail[xs] = 0;
         }
+    };
+    // position of column k in the R list of slot sl (-1 if absent); the
+    // listed columns are distinct
+    auto rl_find = [&](int sl, int cnt, int k) -> int {
+        const int4 *cv = reinterpret_cast<const int4 *>(st_col[sl]);
+        int at = -1;
+#pragma unroll 1
+        for (int q4 = 0; q4 < IMP_K / 4; ++q4) {
+            const int4 c = cv[q4];
+            at = (c.x == k && 4 * q4 < cnt) ? 4 * q4 : at;
+            at = (c.y == k && 4 * q4 + 1 < cnt) ? 4 * q4 + 1 : at;
+            at = (c.z == k && 4 * q4 + 2 < cnt) ? 4 * q4 + 2 : at;
+            at = (c.w == k && 4 * q4 + 3 < cnt) ? 4 * q4 + 3 : at;
+        }
+        return at;
     };
     // acol_t of this thread's columns is the same for every row of the pass:
     // short rows keep it in registers, long rows read it per chunk
@@ -1369,8 +1400,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     int cur_c[EPT], nxt_c[EPT];
     float cur_v[EPT], nxt_v[EPT];
     if (r0 < r1) {
-        const int rc = tid < IMP_K ? cnt_in[r0] : 0;
-        const float rgam = tid < IMP_K ? gam_in[r0 * IMP_K + tid] : 0.0f;
+        const int rc = sw && lane < IMP_K ? cnt_in[r0] : 0;
+        const float rgam = sw && lane < IMP_K ? gam_in[r0 * IMP_K + lane] : 0.0f;
         put_state(r0, fetch_state(r0), rc, rgam);
         fetch_x(r0, cur_c, cur_v);
         mark_x(r0, cur_c);
@@ -1402,14 +1433,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const uint8_t ef_prev = tid == 0 ? p.eflag[ii] : 0;
         // next row's R state and list, in flight during this row
         uint32_t nstate = 0u;
-        int ncnt = 0;
-        float ngam = 0.0f;
         if (i + 1 < r1) {
             nstate = fetch_state(i + 1);
-            if (tid < IMP_K) {
-                ncnt = cnt_in[i + 1];
-                ngam = gam_in[(i + 1) * IMP_K + tid];
-            }
             fetch_x(i + 1, nxt_c, nxt_v);
         }
         // R-list entry tid (lanes of wavefront 0): column, gamma, s, acol_t
@@ -1452,9 +1477,9 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             float4 av;
             if constexpr (ACV) av = acv[j];
             else av = ld4(acol_t + c);
-            const uint32_t mb = mb8[j * T + tid];
-            const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
-            has_sp = has_sp || (mb >> 4) != 0u;
+            // out-of-range columns of the last chunk count as listed
+            const uint32_t mb = mb8[j * T + tid] | (full ? 0u : oob_bits);
+            has_sp = has_sp || (mb8[j * T + tid] >> 4) != 0u;
             // columns of this chunk below the diagonal beat it with a tie
             // (the diagonal's own chunk is finished after the scan)
             const float dth = c + 3 < ii ? D : Dn;
@@ -1463,22 +1488,31 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             for (int e = 0; e < 4; ++e) {
                 const float s = f4get(sv, e);
                 const float r = al * s - beta;
-                const bool inb = full || c + e < n;
-                // one test of the mask bit, in the "ordinary" sense only
-                const bool nx = ((ex >> e) & 1u) == 0u;
+                // listed in either list (or out of range): one mask test
+                const bool lst = (mb & (0x11u << e)) != 0u;
                 const bool pos = r > 0.0f;
-                fr = fr || (nx && pos && inb);
-                const float a = (nx && !pos && inb) ? f4get(av, e) : kNegInf;
+                if constexpr (GP) fr = fr || (pos && !lst);
+                // ordinary with r <= 0: A is the column value
+                const bool ord = !(lst || pos);
+                const float a = ord ? f4get(av, e) : kNegInf;
                 fl = fl || (a + r >= dth);
                 const float w = a + s;
                 const bool g1 = w > v1;
                 l1 = g1 ? 4 * j + e : l1;
                 v2 = __builtin_amdgcn_fmed3f(v1, v2, w);
                 v1 = g1 ? w : v1;
-                smax = max3f(smax, (inb && (GP || nx)) ? s : kNegInf);
+                // largest s of the ordinary columns (positive r included):
+                // r = al s - beta is monotone in s, so it tells whether the
+                // thread holds a first positive, and bounds phase 2's values
+                if constexpr (GP) smax = max3f(smax, (full || c + e < n) ? s : kNegInf);
+                else smax = max3f(smax, lst ? kNegInf : s);
             }
-            fch |= fr ? (1u << j) : 0u;
+            if constexpr (GP) fch |= fr ? (1u << j) : 0u;
         }
+        // a first positive somewhere in the thread's ordinary columns: every
+        // chunk is searched (rare once the lists settle)
+        if constexpr (!GP)
+            fch = (al * smax - beta > 0.0f) ? ((1u << J) - 1u) & (last_in ? ~0u : ~(1u << (J - 1))) : 0u;
         Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
         auto merge = [&](float v, float w, int k) {
             fl = fl || (k < ii ? v >= D : v > D);
@@ -1563,18 +1597,25 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 float r = al * xsv[u] - beta;
                 if ((mb8[k >> 2] >> (4 + (k & 3))) & 1u) {
                     xrl[u] = true;
-                    for (int qq = 0; qq < cnt; ++qq)
-                        if (st_col[sl][qq] == k) r = r + st_gam[sl][qq];
+                    const int at = rl_find(sl, cnt, k);
+                    if (at >= 0) r = r + st_gam[sl][at];
                 }
                 const float an = lam * cur_v[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
                 merge(an + r, an + xsv[u], k);
-                xcol_out[i * IMP_KA + tid + u * T] = k;
-                xval_out[i * IMP_KA + tid + u * T] = an;
+                xcol_out[i * IMP_KA + xq0 + u * T] = k;
+                xval_out[i * IMP_KA + xq0 + u * T] = an;
             }
         }
         if (__any(fl) && lane == 0) atomicOr(&dec_fail[xs], 1);
         __builtin_amdgcn_sched_barrier(0);
         if (i + 1 < r1) {
+            int ncnt = 0;
+            float ngam = 0.0f;
+            if (sw) {
+                // the count (lane 2K+1) and gamma (lane + K) of the state words
+                ncnt = __builtin_amdgcn_readlane((int)nstate, 2 * IMP_K + 1);
+                ngam = __uint_as_float((uint32_t)__shfl((int)nstate, lane + IMP_K));
+            }
             put_state(i + 1, nstate, ncnt, ngam);
             mark_x(i + 1, nxt_c);
             load_row(i + 1, s4);
