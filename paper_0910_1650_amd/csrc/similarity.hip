@@ -172,14 +172,27 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             }
         }
     }
-    // Block min/max of the upper off-diagonal entries.
+    // Block min/max of the upper off-diagonal entries: wavefronts, then the
+    // tile, then one atomic per bound, skipped when it cannot change the value
+    // (all tiles update the same two words).
     for (int off = 32; off >= 1; off >>= 1) {
         kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
         kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
     }
+    __shared__ uint32_t red[2][NT / 64];
     if (lane == 0) {
-        atomicMin(&a.minmax[0], kmin);
-        atomicMax(&a.minmax[1], kmax);
+        red[0][wave] = kmin;
+        red[1][wave] = kmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
+            kmin = min(kmin, red[0][w]);
+            kmax = max(kmax, red[1][w]);
+        }
+        if (kmin < __atomic_load_n(&a.minmax[0], __ATOMIC_RELAXED)) atomicMin(&a.minmax[0], kmin);
+        if (kmax > __atomic_load_n(&a.minmax[1], __ATOMIC_RELAXED)) atomicMax(&a.minmax[1], kmax);
     }
 }
 
@@ -216,41 +229,66 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
     for (uint32_t b = threadIdx.x; b < 2 * 2048; b += blockDim.x) (&h[0][0])[b] = 0u;
     __syncthreads();
     const uint32_t p0 = st->prefix[0], p1 = st->prefix[1];
+    // both ranks inside one prefix (always on the first pass): one count
+    // serves both histograms
+    const bool same = p0 == p1;
     for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
         const float *row = S + i * ld;
         for (int64_t k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
             const uint32_t key = fkey(row[k]);
             const uint32_t dig = (key >> shift) & (nb - 1u);
             if ((key & hmask) == p0) atomicAdd(&h[0][dig], 1u);
-            if ((key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
+            if (!same && (key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
         }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const uint32_t c1 = same ? h[0][b] : h[1][b];
         if (h[0][b]) atomicAdd(&hist[b], (unsigned long long)h[0][b]);
-        if (h[1][b]) atomicAdd(&hist[2048 + b], (unsigned long long)h[1][b]);
+        if (c1) atomicAdd(&hist[2048 + b], (unsigned long long)c1);
     }
 }
 
 // Pick the digit holding each rank; extend the prefixes; clear the histogram.
-__global__ void k_sel_pick(SelState *st, int pass, unsigned long long *hist) {
+// 256 threads: each sums 8 consecutive digits, a block scan of the sums
+// finds the segment holding the rank, its owner walks its 8 digits.
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int pass, unsigned long long *hist) {
     const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
     const int bits = pass == 2 ? 10 : 11;
     const uint32_t nb = 1u << bits;
-    if (threadIdx.x < 2) {
-        const int r = threadIdx.x;
-        unsigned long long rank = st->rank[r], cum = 0ull;
-        uint32_t b = 0;
-        for (; b < nb; ++b) {
-            const unsigned long long c = hist[r * 2048 + b];
-            if (rank < cum + c) break;
-            cum += c;
+    const uint32_t per = nb / 256;               // digits per thread (8 or 4)
+    __shared__ unsigned long long sc[256];
+    const int t = threadIdx.x;
+    for (int r = 0; r < 2; ++r) {
+        const unsigned long long *hr = hist + r * 2048;
+        unsigned long long own = 0ull;
+        for (uint32_t q = 0; q < per; ++q) own += hr[t * per + q];
+        sc[t] = own;
+        __syncthreads();
+        // inclusive scan (Hillis-Steele)
+        for (int off = 1; off < 256; off <<= 1) {
+            const unsigned long long v = t >= off ? sc[t - off] : 0ull;
+            __syncthreads();
+            sc[t] += v;
+            __syncthreads();
         }
-        st->rank[r] = rank - cum;
-        st->prefix[r] |= (b << shift);
+        const unsigned long long rank = st->rank[r];
+        const unsigned long long before = sc[t] - own;    // digits below this thread's segment
+        __syncthreads();
+        if (rank >= before && rank < sc[t]) {
+            unsigned long long cum = before;
+            uint32_t b = t * per;
+            for (;; ++b) {
+                const unsigned long long c = hr[b];
+                if (rank < cum + c) break;
+                cum += c;
+            }
+            st->rank[r] = rank - cum;
+            st->prefix[r] |= (b << shift);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
+    for (int b = t; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
 }
 
 struct PrefArgs {
