@@ -1142,20 +1142,25 @@ __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) 
 // its inputs (a max against +inf is folded into a canonicalising max)
 __device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 3.40282347e+38f); }
 
-template <int CTRL>
+// DPP lane moves; lanes a row mask leaves out keep the identity of the
+// reduction (-inf for max, INT32_MAX for min), so an integer min fuses the
+// move into one v_min_i32_dpp
+template <int CTRL, int RM = 0xF>
 __device__ __forceinline__ float dpp_f(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+    if constexpr (RM == 0xF)   // every lane written: no identity to load
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+    else
+        return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(x), CTRL, RM, 0xF, false));
 }
-template <int CTRL>
+template <int CTRL, int RM = 0xF>
 __device__ __forceinline__ int dpp_i(int x) {
-    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(INT32_MAX, x, CTRL, RM, 0xF, false);
 }
-__device__ __forceinline__ float rdl_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
 
-template <int CTRL>
-__device__ __forceinline__ float dmax(float x) { return max3f(x, dpp_f<CTRL>(x)); }
-template <int CTRL>
-__device__ __forceinline__ int dmin(int x) { return min(x, dpp_i<CTRL>(x)); }
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ float dmax(float x) { return max3f(x, dpp_f<CTRL, RM>(x)); }
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dmin(int x) { return min(x, dpp_i<CTRL, RM>(x)); }
 // max / min over each 16-lane row (every lane of the row gets it): quad
 // swaps, then half-row and row mirrors
 __device__ __forceinline__ float row_max(float x) {
@@ -1164,15 +1169,19 @@ __device__ __forceinline__ float row_max(float x) {
 __device__ __forceinline__ int row_min(int x) {
     return dmin<0x140>(dmin<0x141>(dmin<0x4E>(dmin<0xB1>(x))));
 }
+// over the wavefront: rows, then row broadcasts of lane 15 (into rows 1, 3)
+// and lane 31 (into rows 2, 3); lane 63 holds the result
 __device__ __forceinline__ float wave_max(float x) {
-    x = row_max(x);
-    return max3f(max3f(rdl_f(x, 0), rdl_f(x, 16)), max3f(rdl_f(x, 32), rdl_f(x, 48)));
+    x = dmax<0x143, 0xC>(dmax<0x142, 0xA>(row_max(x)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 __device__ __forceinline__ int wave_min(int x) {
-    x = row_min(x);
-    return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
-               min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+    x = dmin<0x143, 0xC>(dmin<0x142, 0xA>(row_min(x)));
+    return __builtin_amdgcn_readlane(x, 63);
 }
+// bucket of an R-listed column in a row's 64-entry hash table
+__device__ __forceinline__ int rl_hash(int c) { return (int)(((uint32_t)c * 2654435761u) >> 26); }
+
 // Workgroup top-2 of a+s from each lane's (v1, k1, v2), in three passes
 // that need no merge order: the largest v1, the lowest column reaching it,
 // and the largest of the winner's v2 and every other lane's v1 (a candidate
@@ -1216,6 +1225,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     __shared__ float sh_f[2][4 * NW][2];
     __shared__ int sh_i[2][4 * NW];
     __shared__ __align__(16) int st_col[3][IMP_K];
+    __shared__ int st_hash[3][64];               // R-listed column -> list position
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
     __shared__ int st_cnt[3];
@@ -1303,26 +1313,42 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     constexpr int SW = 3;
     static_assert(NW > SW, "state wavefront");
     const bool sw = wave == SW;
-    auto fetch_state = [&](int64_t i) -> uint32_t {
-        if (!sw || lane >= 2 * IMP_K + 4) return 0u;
-        const void *src = lane < IMP_K ? (const void *)(col_in + i * IMP_K + lane)
-                        : lane < 2 * IMP_K ? (const void *)(gam_in + i * IMP_K + lane - IMP_K)
-                        : lane == 2 * IMP_K ? (const void *)(beta_in + i)
-                        : lane == 2 * IMP_K + 1 ? (const void *)(cnt_in + i)
-                        : lane == 2 * IMP_K + 2 ? (const void *)(adiag_t + i)
-                        : (const void *)(p.S + i * ld + i);
-        return *reinterpret_cast<const uint32_t *>(src);
+    // (list words by byte offsets from the state buffer, whose size is far
+    // below 4 GB; a(i,i) and s(i,i) are uniform loads, used at the put)
+    struct RowState { uint32_t v; float ad, sd; };
+    auto fetch_state = [&](int64_t i) -> RowState {
+        RowState r{0u, 0.0f, 0.0f};
+        if (!sw) return r;
+        if (lane < 2 * IMP_K + 2) {
+            const uint32_t ri = (uint32_t)i;
+            const uint32_t off = lane < 2 * IMP_K
+                ? (uint32_t)(lane < IMP_K ? L.col : L.gam) + (ri * IMP_K + (lane & (IMP_K - 1))) * 4u
+                : (uint32_t)(lane == 2 * IMP_K ? L.beta : L.cnt) + ri * 4u;
+            r.v = *reinterpret_cast<const uint32_t *>(sin + off);
+        }
+        r.ad = adiag_t[i];
+        r.sd = p.S[i * ld + i];
+        return r;
     };
     // R state of row i into its LDS slot; the R-listed columns and the
     // diagonal are marked in the high nibble of the row's mask bytes
-    auto put_state = [&](int64_t i, uint32_t v, int rc, float rgam) {
+    auto put_state = [&](int64_t i, const RowState &rs, int rc, float rgam) {
         if (!sw) return;
+        const uint32_t v = rs.v;
         const int sl = (int)(i % 3);
         uint32_t *m = mask + (i % NXS) * mw;
+        // the slot's hash table is empty before the inserts (one wavefront:
+        // its LDS operations are ordered)
+        st_hash[sl][lane] = -1;
         if (lane < IMP_K) {
             st_col[sl][lane] = (int)v;
             const int c = (int)v;
-            if (lane < rc && (unsigned)c < (unsigned)n) atomicOr(&m[c >> 4], xbit(c) << 4);
+            if (lane < rc && (unsigned)c < (unsigned)n) {
+                atomicOr(&m[c >> 4], xbit(c) << 4);
+                // open addressing, at most IMP_K entries in 64 buckets
+                int h = rl_hash(c);
+                while (atomicCAS(&st_hash[sl][h], -1, c * IMP_K + lane) != -1) h = (h + 1) & 63;
+            }
             if (lane < rc && c == (int)i) {
                 st_gd[sl] = rgam;
                 st_gdr[sl] = (int)i;
@@ -1334,9 +1360,9 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         } else if (lane == 2 * IMP_K + 1) {
             st_cnt[sl] = (int)v;
         } else if (lane == 2 * IMP_K + 2) {
-            st_ad[sl] = __uint_as_float(v);
+            st_ad[sl] = rs.ad;
         } else if (lane == 2 * IMP_K + 3) {
-            st_sd[sl] = __uint_as_float(v);
+            st_sd[sl] = rs.sd;
         }
         if (lane == 0) atomicOr(&m[i >> 4], xbit((int)i) << 4);
     };
@@ -1367,20 +1393,19 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             dec_fail[xs] = 0;
         }
     };
-    // position of column k in the R list of slot sl (-1 if absent); the
-    // listed columns are distinct
-    auto rl_find = [&](int sl, int cnt, int k) -> int {
-        const int4 *cv = reinterpret_cast<const int4 *>(st_col[sl]);
-        int at = -1;
+    // position of column k in the R list of slot sl (-1 if absent), from
+    // the slot's hash table (the listed columns are distinct; the table has
+    // at least 64 - IMP_K empty buckets, so a probe ends)
+    auto rl_find = [&](int sl, int k) -> int {
+        int h = rl_hash(k);
 #pragma unroll 1
-        for (int q4 = 0; q4 < IMP_K / 4; ++q4) {
-            const int4 c = cv[q4];
-            at = (c.x == k && 4 * q4 < cnt) ? 4 * q4 : at;
-            at = (c.y == k && 4 * q4 + 1 < cnt) ? 4 * q4 + 1 : at;
-            at = (c.z == k && 4 * q4 + 2 < cnt) ? 4 * q4 + 2 : at;
-            at = (c.w == k && 4 * q4 + 3 < cnt) ? 4 * q4 + 3 : at;
+        for (int probe = 0; probe < 64; ++probe) {
+            const int e = st_hash[sl][h];
+            if (e < 0) break;
+            if (e / IMP_K == k) return e % IMP_K;
+            h = (h + 1) & 63;
         }
-        return at;
+        return -1;
     };
     // acol_t of this thread's columns is the same for every row of the pass:
     // short rows keep it in registers, long rows read it per chunk
@@ -1432,7 +1457,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // in flight (a later global load would wait for it)
         const uint8_t ef_prev = tid == 0 ? p.eflag[ii] : 0;
         // next row's R state and list, in flight during this row
-        uint32_t nstate = 0u;
+        RowState nstate{0u, 0.0f, 0.0f};
         if (i + 1 < r1) {
             nstate = fetch_state(i + 1);
             fetch_x(i + 1, nxt_c, nxt_v);
@@ -1597,7 +1622,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 float r = al * xsv[u] - beta;
                 if ((mb8[k >> 2] >> (4 + (k & 3))) & 1u) {
                     xrl[u] = true;
-                    const int at = rl_find(sl, cnt, k);
+                    const int at = rl_find(sl, k);
                     if (at >= 0) r = r + st_gam[sl][at];
                 }
                 const float an = lam * cur_v[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
@@ -1613,8 +1638,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             float ngam = 0.0f;
             if (sw) {
                 // the count (lane 2K+1) and gamma (lane + K) of the state words
-                ncnt = __builtin_amdgcn_readlane((int)nstate, 2 * IMP_K + 1);
-                ngam = __uint_as_float((uint32_t)__shfl((int)nstate, lane + IMP_K));
+                ncnt = __builtin_amdgcn_readlane((int)nstate.v, 2 * IMP_K + 1);
+                ngam = __uint_as_float((uint32_t)__shfl((int)nstate.v, lane + IMP_K));
             }
             put_state(i + 1, nstate, ncnt, ngam);
             mark_x(i + 1, nxt_c);
