@@ -1740,6 +1740,17 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                         const int c = c0 + j * T * 4;
                         const float4 sv = ld4(srow + c);
                         const uint32_t mb = mb8[j * T + tid];
+                        if (mb == 0u && (k1 >> 2) != (c >> 2) && c + 3 < n) {
+                            // no listed column and not k1's chunk: no other
+                            // thread adds to these columns in this row
+                            float4 a4 = lpart[c >> 2];
+                            a4.x = (al1 * sv.x - beta1 > 0.0f) ? a4.x + (al1 * sv.x - beta1) : a4.x;
+                            a4.y = (al1 * sv.y - beta1 > 0.0f) ? a4.y + (al1 * sv.y - beta1) : a4.y;
+                            a4.z = (al1 * sv.z - beta1 > 0.0f) ? a4.z + (al1 * sv.z - beta1) : a4.z;
+                            a4.w = (al1 * sv.w - beta1 > 0.0f) ? a4.w + (al1 * sv.w - beta1) : a4.w;
+                            lpart[c >> 2] = a4;
+                            continue;
+                        }
                         const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
                         for (int e = 0; e < 4; ++e) {
                             const int k = c + e;
