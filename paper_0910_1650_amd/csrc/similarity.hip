@@ -232,13 +232,29 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
     // both ranks inside one prefix (always on the first pass): one count
     // serves both histograms
     const bool same = p0 == p1;
+    auto count = [&](float v) {
+        const uint32_t key = fkey(v);
+        const uint32_t dig = (key >> shift) & (nb - 1u);
+        if ((key & hmask) == p0) atomicAdd(&h[0][dig], 1u);
+        if (!same && (key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
+    };
     for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
         const float *row = S + i * ld;
-        for (int64_t k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
-            const uint32_t key = fkey(row[k]);
-            const uint32_t dig = (key >> shift) & (nb - 1u);
-            if ((key & hmask) == p0) atomicAdd(&h[0][dig], 1u);
-            if (!same && (key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
+        // columns i+1 .. n-1: the unaligned head one by one, then 16-byte
+        // loads (rows start 16-byte aligned: ld is a multiple of 4)
+        const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
+        const int64_t kh = k4 < n ? k4 : n;
+        if (i + 1 + threadIdx.x < kh) count(row[i + 1 + threadIdx.x]);
+        for (int64_t k = k4 + 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
+            if (k + 3 < n) {
+                const float4 v = *reinterpret_cast<const float4 *>(row + k);
+                count(v.x);
+                count(v.y);
+                count(v.z);
+                count(v.w);
+            } else {
+                for (int64_t q = k; q < n; ++q) count(row[q]);
+            }
         }
     }
     __syncthreads();
