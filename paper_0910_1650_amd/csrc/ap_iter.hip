@@ -1873,7 +1873,21 @@ __global__ void k_ia_materialize(float *A, int64_t ld, int32_t n, const float *a
         const int c = cnt[i];
         if (c < 0) continue;
         float *row = A + i * ld;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) row[k] = (k == i) ? adiag[i] : acol[k];
+        const float ad = adiag[i];
+        // 16-byte stores (rows are 16-byte aligned, the column vector is
+        // padded to a multiple of four); the tail past n is left alone
+        for (int64_t k = 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
+            if (k + 3 < n) {
+                float4 v = *reinterpret_cast<const float4 *>(acol + k);
+                v.x = k == i ? ad : v.x;
+                v.y = k + 1 == i ? ad : v.y;
+                v.z = k + 2 == i ? ad : v.z;
+                v.w = k + 3 == i ? ad : v.w;
+                *reinterpret_cast<float4 *>(row + k) = v;
+            } else {
+                for (int64_t q = k; q < n; ++q) row[q] = (q == i) ? ad : acol[q];
+            }
+        }
         __syncthreads();
         for (int qq = threadIdx.x; qq < c && qq < IMP_KA; qq += blockDim.x) {
             const int k = col[i * IMP_KA + qq];
@@ -1900,7 +1914,19 @@ __global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t 
         const float b = beta[i];
         const float *srow = S + i * ld;
         float *rrow = R + i * ld;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) rrow[k] = al * srow[k] - b;
+        for (int64_t k = 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
+            if (k + 3 < n) {
+                const float4 sv = *reinterpret_cast<const float4 *>(srow + k);
+                float4 rv;
+                rv.x = al * sv.x - b;
+                rv.y = al * sv.y - b;
+                rv.z = al * sv.z - b;
+                rv.w = al * sv.w - b;
+                *reinterpret_cast<float4 *>(rrow + k) = rv;
+            } else {
+                for (int64_t q = k; q < n; ++q) rrow[q] = al * srow[q] - b;
+            }
+        }
         __syncthreads();
         if (threadIdx.x < c) {
             const int64_t k = col[i * IMP_K + threadIdx.x];
