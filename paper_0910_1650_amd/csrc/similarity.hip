@@ -374,9 +374,23 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
     for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
         float *row = a.S + i * a.ld;
         if (a.noise_rel > 0.0) {
-            for (int64_t k = threadIdx.x; k < a.n; k += blockDim.x) {
-                const double base = (k == i) ? pref_of(a, i, pm) : (double)row[k];
-                row[k] = (float)(base + scale * noise_u(a.seed, a.n, i, k));
+            auto one = [&](int64_t k, float v) -> float {
+                const double base = (k == i) ? pref_of(a, i, pm) : (double)v;
+                return (float)(base + scale * noise_u(a.seed, a.n, i, k));
+            };
+            // 16-byte loads and stores (rows are 16-byte aligned); the
+            // padding past n is left alone
+            for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.n; k += 4 * (int64_t)blockDim.x) {
+                if (k + 3 < a.n) {
+                    float4 v = *reinterpret_cast<const float4 *>(row + k);
+                    v.x = one(k, v.x);
+                    v.y = one(k + 1, v.y);
+                    v.z = one(k + 2, v.z);
+                    v.w = one(k + 3, v.w);
+                    *reinterpret_cast<float4 *>(row + k) = v;
+                } else {
+                    for (int64_t q = k; q < a.n; ++q) row[q] = one(q, row[q]);
+                }
             }
         } else if (threadIdx.x == 0) {
             row[i] = (float)pref_of(a, i, pm);
