@@ -82,13 +82,25 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.0f;
 
     for (int64_t k0 = 0; k0 < a.d; k0 += KB) {
-        // Stage X[row0 .. +BM, k0 .. +KB] and X[col0 .. +BM, k0 .. +KB], k-major.
-        for (int e = tid; e < BM * KB; e += NT) {
+        // Stage X[row0 .. +BM, k0 .. +KB] and X[col0 .. +BM, k0 .. +KB], k-major:
+        // every load of the chunk in flight first, then the LDS stores.
+        constexpr int SU = BM * KB / NT;
+        float va[SU], vb[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int e = tid + u * NT;
             const int m = e / KB, kk = e % KB;
             const int64_t kg = k0 + kk;
             const int64_t ra = row0 + m, rb = col0 + m;
-            As[kk * LDA + m] = (ra < a.n && kg < a.d) ? a.X[ra * a.ldx + kg] : 0.0f;
-            Bs[kk * LDA + m] = (rb < a.n && kg < a.d) ? a.X[rb * a.ldx + kg] : 0.0f;
+            va[u] = (ra < a.n && kg < a.d) ? a.X[ra * a.ldx + kg] : 0.0f;
+            vb[u] = (rb < a.n && kg < a.d) ? a.X[rb * a.ldx + kg] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int e = tid + u * NT;
+            const int m = e / KB, kk = e % KB;
+            As[kk * LDA + m] = va[u];
+            Bs[kk * LDA + m] = vb[u];
         }
         __syncthreads();
 #pragma unroll
