@@ -542,23 +542,42 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
     __shared__ double part[16][64];
     const int cx = threadIdx.x & 63, gs = threadIdx.x >> 6;
     const int k = blockIdx.x * 64 + cx;
+    // the column's own values, in flight with the partials
+    float rd = 0.0f, ai = 0.0f, di = 0.0f;
+    if (gs == 0 && k < a.n) {
+        rd = a.rdiag[k];
+        if (a.acol_out != nullptr) {
+            ai = a.acol_in[k];
+            di = a.adiag_in[k];
+        }
+    }
     double c = 0.0;
-    if (k < a.n)
-        for (int g = gs; g < a.nparts; g += 16) c += (double)a.partial[(int64_t)g * a.ldp + k];
+    if (k < a.n) {
+        // eight partials in flight per step, summed in the same order
+        int g = gs;
+        for (; g + 7 * 16 < a.nparts; g += 8 * 16) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = a.partial[(int64_t)(g + u * 16) * a.ldp + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c += (double)v[u];
+        }
+        for (; g < a.nparts; g += 16) c += (double)a.partial[(int64_t)g * a.ldp + k];
+    }
     part[gs][cx] = c;
     __syncthreads();
     if (gs == 0 && k < a.n) {
         double tot = 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) tot += part[q][cx];
-        const float tf = (float)((double)a.rdiag[k] + tot), cf = (float)tot;
+        const float tf = (float)((double)rd + tot), cf = (float)tot;
         a.tcol[k] = tf;
         a.ccol[k] = cf;
         if (a.acol_out != nullptr) {
             // the explicit update of Eqs. (3), (4) for elements with r <= 0, in its rounding
             const float oml = 1.0f - a.lam;
-            a.acol_out[k] = a.lam * a.acol_in[k] + oml * fminf(0.0f, tf);
-            a.adiag_out[k] = a.lam * a.adiag_in[k] + oml * cf;
+            a.acol_out[k] = a.lam * ai + oml * fminf(0.0f, tf);
+            a.adiag_out[k] = a.lam * di + oml * cf;
         }
     }
     if (a.bookkeep && a.st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
