@@ -89,8 +89,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1928337925, "write": 46029051, "path": "implicit_RA",
-                    "sha256": "aa766b2bd50bc00109fb68c5acf190e8ee65fa0c94f02eace8d7bd20388251c3"}
+ROW_PASS_TRAFFIC = {"read": 1928585477, "write": 46023659, "path": "implicit_RA",
+                    "sha256": "fd66c3e8ad7de7be6fca665e74013a41f1e3b4e3f772359863f492b037e874be"}
 PAP_K = 8
 
 
