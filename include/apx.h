@@ -47,7 +47,7 @@ typedef enum {
     APX_EINVAL = 1,    /* invalid argument (shape, alignment, range, null) */
     APX_ENOMEM = 2,    /* device workspace could not be allocated */
     APX_EDEVICE = 3,   /* HIP runtime error; text via apx_last_error */
-    APX_ENOTIMPL = 4   /* size or mode outside what this build supports */
+    APX_ENOTIMPL = 4   /* size or mode outside what the library supports */
 } apx_status;
 
 /* Preference modes for ap_similarity (Section 2: the diagonal s(k,k)). */

@@ -12,7 +12,7 @@ this wrapper marshals numpy arrays and composes the paper's algorithms:
 * the learned warm start (features, network, targets, A_0) in ``warm.py``,
   a definition of this project's own: the paper has no learned part
 
-Readings of the paper that the oracle fixes (all listed in the design doc):
+Readings of the paper that the oracle fixes:
 R_0 = 0; R is updated and damped before A, and A uses the damped R; damping
 weights the old value by lambda; ties go to the lowest index; the exemplar
 set is E = {i : argmax_k a(i,k)+r(i,k) = i} and labels are the valid

@@ -11,7 +11,7 @@ Held-out instances here use seeds 60000+.
   loss is dominated by the few large exemplar targets).
   The oracle's FP64 network evaluates both loss values, so this part does
   not depend on the GPU forward pass.
-* Against cold-start AP (the method without it, and the judge): the warm-
+* Against cold-start AP (the method without it, and the reference point): the warm-
   started run from ap_warmstart, with cold start as its fallback, is timed
   in iterations against the oracle's cold run.  The test prints the
   iterations, whether the exemplar set equals the oracle's and the
