@@ -216,6 +216,16 @@ struct SelState {
     unsigned long long rank[2];   // remaining rank inside the current prefix
 };
 
+// Digits of the 32-bit key: 13 bits (the first pass, when both ranks share
+// the empty prefix and one histogram counts for both: more bins spread the
+// counter contention of keys that share their exponent), then 10 and 9.
+constexpr int SEL_BINS = 8192;   // bins per rank in the global histogram
+__device__ __forceinline__ void sel_digit(int pass, int &shift, int &bits, uint32_t &hmask) {
+    shift = pass == 0 ? 19 : (pass == 1 ? 9 : 0);
+    bits = pass == 0 ? 13 : (pass == 1 ? 10 : 9);
+    hmask = pass == 0 ? 0u : (pass == 1 ? 0xfff80000u : 0xfffffe00u);
+}
+
 __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo,
                            unsigned long long hi, unsigned long long *hist) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -225,7 +235,7 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
         minmax[0] = 0xffffffffu;
         minmax[1] = 0u;
     }
-    for (int b = threadIdx.x; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
+    for (int b = threadIdx.x; b < 2 * SEL_BINS; b += blockDim.x) hist[b] = 0ull;
 }
 
 // Histogram of the keys of upper-triangle entries whose high bits match the
@@ -233,22 +243,27 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
 __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int64_t ld,
                                                   const SelState *st, int pass,
                                                   unsigned long long *hist) {
-    __shared__ uint32_t h[2][2048];
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const int bits = pass == 2 ? 10 : 11;
+    // dynamic LDS: one histogram of nb bins on the first pass (both ranks
+    // start from the same empty prefix), two on the others
+    extern __shared__ uint32_t hsh[];
+    int shift, bits;
+    uint32_t hmask;
+    sel_digit(pass, shift, bits, hmask);
     const uint32_t nb = 1u << bits;
-    const uint32_t hmask = pass == 0 ? 0u : (pass == 1 ? 0xffe00000u : 0xfffffc00u);
-    for (uint32_t b = threadIdx.x; b < 2 * 2048; b += blockDim.x) (&h[0][0])[b] = 0u;
+    const uint32_t nh = pass == 0 ? 1u : 2u;
+    for (uint32_t b = threadIdx.x; b < nh * nb; b += blockDim.x) hsh[b] = 0u;
     __syncthreads();
     const uint32_t p0 = st->prefix[0], p1 = st->prefix[1];
     // both ranks inside one prefix (always on the first pass): one count
     // serves both histograms
     const bool same = p0 == p1;
+    uint32_t *const h0 = hsh;
+    uint32_t *const h1 = hsh + (nh - 1) * nb;
     auto count = [&](float v) {
         const uint32_t key = fkey(v);
         const uint32_t dig = (key >> shift) & (nb - 1u);
-        if ((key & hmask) == p0) atomicAdd(&h[0][dig], 1u);
-        if (!same && (key & hmask) == p1) atomicAdd(&h[1][dig], 1u);
+        if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
+        if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
     };
     for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
         const float *row = S + i * ld;
@@ -271,24 +286,25 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        const uint32_t c1 = same ? h[0][b] : h[1][b];
-        if (h[0][b]) atomicAdd(&hist[b], (unsigned long long)h[0][b]);
-        if (c1) atomicAdd(&hist[2048 + b], (unsigned long long)c1);
+        const uint32_t c0 = h0[b], c1 = same ? c0 : h1[b];
+        if (c0) atomicAdd(&hist[b], (unsigned long long)c0);
+        if (c1) atomicAdd(&hist[SEL_BINS + b], (unsigned long long)c1);
     }
 }
 
 // Pick the digit holding each rank; extend the prefixes; clear the histogram.
-// 256 threads: each sums 8 consecutive digits, a block scan of the sums
-// finds the segment holding the rank, its owner walks its 8 digits.
+// 256 threads: each sums nb/256 consecutive digits, a block scan of the
+// sums finds the segment holding the rank, its owner walks its digits.
 __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int pass, unsigned long long *hist) {
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const int bits = pass == 2 ? 10 : 11;
+    int shift, bits;
+    uint32_t hmask;
+    sel_digit(pass, shift, bits, hmask);
     const uint32_t nb = 1u << bits;
-    const uint32_t per = nb / 256;               // digits per thread (8 or 4)
+    const uint32_t per = nb / 256;               // digits per thread (32, 4 or 2)
     __shared__ unsigned long long sc[256];
     const int t = threadIdx.x;
     for (int r = 0; r < 2; ++r) {
-        const unsigned long long *hr = hist + r * 2048;
+        const unsigned long long *hr = hist + r * SEL_BINS;
         unsigned long long own = 0ull;
         for (uint32_t q = 0; q < per; ++q) own += hr[t * per + q];
         sc[t] = own;
@@ -316,7 +332,7 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int pass, unsign
         }
         __syncthreads();
     }
-    for (int b = t; b < 2 * 2048; b += blockDim.x) hist[b] = 0ull;
+    for (int b = t; b < 2 * SEL_BINS; b += blockDim.x) hist[b] = 0ull;
 }
 
 struct PrefArgs {
@@ -447,7 +463,7 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     size_t o_n = L.take(sizeof(float) * (size_t)n);
     size_t o_mm = L.take(sizeof(uint32_t) * 2);
     size_t o_sel = L.take(sizeof(SelState));
-    size_t o_h = L.take(sizeof(unsigned long long) * 2 * 2048);
+    size_t o_h = L.take(sizeof(unsigned long long) * 2 * SEL_BINS);
     size_t o_r = L.take(sizeof(double) * 2);
     apx_status st = ws_reserve(ctx, ctx->ws_base + L.off);
     if (st != APX_OK) return st;
@@ -472,7 +488,8 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     if (pref_mode == APX_PREF_MEDIAN) {
         const int g = (int)(n - 1 < 2048 ? n - 1 : 2048);
         for (int pass = 0; pass < 3; ++pass) {
-            k_sel_hist<<<g, 256, 0, s>>>(S, n, ld, sel, pass, hist);
+            const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
+            k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist);
             HIP_TRY(hipGetLastError(), "select histogram");
             k_sel_pick<<<1, 256, 0, s>>>(sel, pass, hist);
             HIP_TRY(hipGetLastError(), "select pick");
