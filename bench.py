@@ -89,8 +89,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1928585477, "write": 46023659, "path": "implicit_RA",
-                    "sha256": "fd66c3e8ad7de7be6fca665e74013a41f1e3b4e3f772359863f492b037e874be"}
+ROW_PASS_TRAFFIC = {"read": 1928730457, "write": 46030314, "path": "implicit_RA",
+                    "sha256": "03594824d7ad193391030693bcf3e0c46d063d9f75ea0e0ed800a7378457a8bd"}
 PAP_K = 8
 
 

@@ -1201,35 +1201,56 @@ __device__ __forceinline__ int wave_min(int x) {
 // bucket of an R-listed column in a row's 64-entry hash table
 __device__ __forceinline__ int rl_hash(int c) { return (int)(((uint32_t)c * 2654435761u) >> 26); }
 
+// Order-preserving integer key of a float that is finite or -inf (-0 is
+// taken as +0 first, so keys are equal exactly when the floats are equal):
+// integer max and min fuse their DPP lane moves, float max does not.
+__device__ __forceinline__ int okey(float x) {
+    const int b = __float_as_int(x + 0.0f);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float okey_f(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF)); }
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dmaxi(int x) {
+    return max(x, __builtin_amdgcn_update_dpp(INT32_MIN, x, CTRL, RM, 0xF, false));
+}
+__device__ __forceinline__ int row_maxi(int x) {
+    return dmaxi<0x140>(dmaxi<0x141>(dmaxi<0x4E>(dmaxi<0xB1>(x))));
+}
+__device__ __forceinline__ int wave_maxi(int x) {
+    x = dmaxi<0x143, 0xC>(dmaxi<0x142, 0xA>(row_maxi(x)));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // Workgroup top-2 of a+s from each lane's (v1, k1, v2), in three passes
 // that need no merge order: the largest v1, the lowest column reaching it,
 // and the largest of the winner's v2 and every other lane's v1 (a candidate
 // column is held by one lane only).  Each 16-lane row reduces with DPP and
 // writes one LDS slot (4 per wavefront); after the barrier every wavefront
-// reduces the 4*NW slots, one per lane.
+// reduces the 4*NW slots, one per lane.  The values travel as okey keys.
 template <int NW>
-__device__ __forceinline__ void wg_top2(Top2 &t, float (*sh_f)[2], int *sh_i, int lane, int wave) {
+__device__ __forceinline__ void wg_top2(Top2 &t, int (*sh_v)[2], int *sh_i, int lane, int wave) {
     static_assert(4 * NW <= 64, "one slot per lane");
     {
-        const float V = row_max(t.v1);
-        const int K = row_min(t.v1 == V ? t.k1 : INT32_MAX);
-        const float V2 = row_max(t.v1 == V && t.k1 == K ? t.v2 : t.v1);
+        const int a1 = okey(t.v1), a2 = okey(t.v2);
+        const int V = row_maxi(a1);
+        const int K = row_min(a1 == V ? t.k1 : INT32_MAX);
+        const int V2 = row_maxi(a1 == V && t.k1 == K ? a2 : a1);
         if ((lane & 15) == 0) {
             const int slot = wave * 4 + (lane >> 4);
-            sh_f[slot][0] = V;
-            sh_f[slot][1] = V2;
+            sh_v[slot][0] = V;
+            sh_v[slot][1] = V2;
             sh_i[slot] = K;
         }
     }
     lds_barrier();
     const bool has = lane < 4 * NW;
-    const float v1 = has ? sh_f[lane][0] : kNegInf;
+    const int v1 = has ? sh_v[lane][0] : INT32_MIN;
     const int k1 = has ? sh_i[lane] : INT32_MAX;
-    const float v2 = has ? sh_f[lane][1] : kNegInf;
-    const float V = wave_max(v1);
+    const int v2 = has ? sh_v[lane][1] : INT32_MIN;
+    const int V = wave_maxi(v1);
     const int K = wave_min(v1 == V ? k1 : INT32_MAX);
-    const float V2 = wave_max(v1 == V && k1 == K ? v2 : v1);
-    t = Top2{V, K, V2};
+    const int V2 = wave_maxi(v1 == V && k1 == K ? v2 : v1);
+    t = Top2{okey_f(V), K, okey_f(V2)};
 }
 
 template <int T, int J, bool GP>
@@ -1241,7 +1262,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     static_assert(IMP_K <= 64, "R-list holders are lanes of wavefront 0");
 
     if (p.st->frozen) return;
-    __shared__ float sh_f[2][4 * NW][2];
+    __shared__ int sh_v[2][4 * NW][2];
     __shared__ int sh_i[2][4 * NW];
     __shared__ __align__(16) int st_col[3][IMP_K];
     __shared__ int st_hash[3][64];               // R-listed column -> list position
@@ -1666,7 +1687,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
         __builtin_amdgcn_sched_barrier(0);
 
-        wg_top2<NW>(t2, sh_f[i & 1], sh_i[i & 1], lane, wave);
+        wg_top2<NW>(t2, sh_v[i & 1], sh_i[i & 1], lane, wave);
         if (tid == 0) {
             const uint8_t ef = (uint8_t)(dec_fail[xs] == 0);
             if (ef_prev != ef) my_changed = 1;
