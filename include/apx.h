@@ -21,15 +21,21 @@
  * - Label / decision vectors are DEVICE int32 arrays of length n, 0-based.
  *   A label of -1 means "no exemplar" (only when the exemplar set is empty).
  * - Host-side arrays (partition permutations, offsets, results) are marked
- *   "host".  The caller owns every buffer it passes; the library owns only
- *   its internal workspace (allocated per context on first need, grown on
- *   demand, released by apx_destroy).
+ *   "host".  The caller owns every buffer it passes.  Scratch memory (column
+ *   partials, run state, implicit-message lists, sub-problem matrices) comes
+ *   from the context's workspace: either a device buffer the caller hands
+ *   over with apx_set_workspace (sized with apx_workspace_size; the library
+ *   then never allocates device memory on a compute call and returns
+ *   APX_ENOMEM when a call needs more than was set), or, by default, a
+ *   buffer the library allocates on first need, grows on demand and
+ *   releases in apx_destroy.
  * - Every call returns an apx_status and never aborts.  Arguments are
  *   validated before any write, so APX_EINVAL leaves all outputs untouched.
  *   apx_last_error() returns a text for the last failure on the context.
- * - Work is enqueued on the context's HIP stream.  ap_similarity and
- *   ap_iterate are asynchronous (stream-ordered); the *_solve calls
- *   synchronise the stream before filling their host result structs.
+ * - Work is enqueued on the context's HIP stream.  ap_iterate is
+ *   asynchronous (stream-ordered); ap_similarity and the *_solve calls
+ *   synchronise the stream before they return (ap_similarity to report
+ *   non-finite input, the solves to fill their host result structs).
  * - One context per host thread; contexts share no mutable state.
  */
 #ifndef APX_H
@@ -72,8 +78,48 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream);
 void apx_destroy(apx_ctx *ctx);
 apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream);
 const char *apx_last_error(const apx_ctx *ctx);
-/* Bytes of device workspace currently held by the context. */
+/* Bytes of device workspace currently held by (or set on) the context. */
 size_t apx_workspace_bytes(const apx_ctx *ctx);
+
+/* Operations for apx_workspace_size. */
+enum {
+    APX_OP_SIMILARITY = 0,    /* ap_similarity: n points (d unused)                    */
+    APX_OP_ITERATE = 1,       /* ap_iterate: n x n, leading dimension ld                */
+    APX_OP_SOLVE = 2,         /* ap_solve (and pap_solve's Step 4): n x n, ld           */
+    APX_OP_SOLVE_BATCHED = 3, /* ap_solve_batched: count instances of sizes[j] points,
+                                 leading dimensions rounded up to 4 (sizes: host)      */
+    APX_OP_PAP = 4,           /* pap_solve: n x n, ld, k = count parts of sizes[j]
+                                 points (sizes: host, nullable = the paper's split)    */
+    APX_OP_LAP = 5,           /* lap_solve: n points in d dimensions, count landmarks  */
+    APX_OP_FEATURES = 6,      /* apx_features: n points                                */
+    APX_OP_MLP_BACKWARD = 7,  /* apx_mlp_backward: count points                        */
+    APX_OP_WARMSTART = 8      /* ap_warmstart: n x n, ld                               */
+};
+
+/*
+ * apx_workspace_size -- device workspace bytes one call of `op` needs for
+ * the given sizes (see the op list above for which arguments are used).
+ * Returns 0 for an unknown op or invalid sizes.  Every call uses the
+ * workspace from its start, so one buffer of the largest size any call
+ * needs serves a sequence of calls on one stream.
+ */
+size_t apx_workspace_size(const apx_ctx *ctx, int32_t op, int64_t n, int64_t ld, int64_t d,
+                          int32_t count, const int64_t *sizes);
+
+/*
+ * apx_set_workspace -- use `bytes` bytes of caller-owned device memory at
+ * dev_ptr (256-byte aligned, e.g. torch.empty(bytes, dtype=torch.uint8,
+ * device='cuda')) as the context's workspace.  The library frees its own
+ * buffer (after synchronising the stream) and from then on calls no
+ * hipMalloc on compute calls: a call that needs more than `bytes` returns
+ * APX_ENOMEM without launching work, and the automatic tuner (which
+ * allocates a scratch problem) stays off for unseen sizes.  The caller keeps
+ * the memory alive and unused by others until it sets another workspace or
+ * destroys the context.  dev_ptr = NULL (bytes ignored) returns to a
+ * library-owned workspace.  Calls that overlap on one stream are ordered;
+ * contexts must not share one buffer.
+ */
+apx_status apx_set_workspace(apx_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* apx_set_implicit -- list capacity of the implicit responsibilities used by
  * ap_solve when R_0 = 0 (APX_COLD, APX_WARM_A): unrolling the damped Eq. (2)
@@ -161,16 +207,38 @@ apx_status apx_tune_load(apx_ctx *ctx, const char *path);
 apx_status apx_profile(apx_ctx *ctx, int enable);
 apx_status apx_profile_read(apx_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* apx_params.flags */
+enum {
+    /* idx receives the raw decisions d_i = argmax_k a(i,k)+r(i,k) of the stop
+     * iteration (lowest k on ties) instead of the valid labelling; dpsim and
+     * expref are then summed over those labels (Section 2, the decision rule). */
+    APX_RAW_LABELS = 1,
+    /* Before any write, scan S (the solve's input) and return APX_EINVAL if
+     * any entry is NaN or infinite.  Without it, non-finite S gives
+     * unspecified messages and labels. */
+    APX_CHECK_FINITE = 2,
+    /* Also stop (converged = 1) after the first iteration t >= 2 whose
+     * message changes are all at most msg_tol:
+     * max_{i,k} |r_t(i,k) - r_{t-1}(i,k)| <= msg_tol and
+     * max_{i,k} |a_t(i,k) - a_{t-1}(i,k)| <= msg_tol (Algorithm 1, Step 4,
+     * "changes in the messages fall below a threshold").  Runs the explicit
+     * form of the iteration (R and A in memory). */
+    APX_MSG_THRESHOLD = 4
+};
+
 typedef struct {
     float damping;       /* lambda in [0,1): new = lambda*old + (1-lambda)*update (Section 2) */
     int32_t max_iter;    /* >= 1: iteration cap (Section 2, Step 4) */
     int32_t conv_iter;   /* >= 0: stop once the exemplar set has been the same, and
                             non-empty, for conv_iter consecutive iterations;
-                            0 = run exactly max_iter iterations */
+                            0 = no exemplar-set rule (max_iter, or the message
+                            threshold, ends the run) */
     int32_t check_every; /* iterations between host polls of the stop flag
                             (0 = library default 16; odd values are rounded
                             up to even, the length of one graph replay);
                             never changes results */
+    uint32_t flags;      /* APX_RAW_LABELS | APX_CHECK_FINITE | APX_MSG_THRESHOLD */
+    float msg_tol;       /* >= 0: threshold of APX_MSG_THRESHOLD (units of S) */
 } apx_params;
 
 typedef struct {
@@ -193,7 +261,10 @@ typedef struct {
  * u is the SplitMix64 output function of the counter i*n+k+1 (top 53 bits
  * scaled to [0,1)) and the range is taken over S with the preferences set.
  * pref_out (host, nullable) receives the preference used (median or scalar).
- * Requires n >= 2, 1 <= d.
+ * Non-finite input: X or pref_vec holding a NaN or infinity gives
+ * APX_EINVAL before S is written; finite X whose similarities overflow
+ * FP32 gives APX_EINVAL after the build (S is then unspecified).
+ * Requires n >= 2, 1 <= d.  Synchronises the stream.
  */
 apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
                          float *S, int64_t ld, int32_t pref_mode, const float *pref_vec,
@@ -272,21 +343,26 @@ apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float 
  * 1-2 without the per-class distance threshold).  Step 1: the landmark set M
  * (host array `landmarks` of n_landmarks distinct indices, or NULL to draw a
  * uniform sample without replacement from a SplitMix64 stream seeded with
- * `seed`) gets its similarity matrix (ap_similarity: median preference, tie
- * noise noise_rel from `seed`) and AP with `params`.  Step 2: every point
+ * `seed`) gets its similarity matrix (ap_similarity with pref_mode
+ * APX_PREF_MEDIAN, the median of the landmark similarities, or
+ * APX_PREF_SCALAR, pref_scalar for every landmark; tie noise noise_rel from
+ * `seed`) and AP with `params`.  Step 2: every point
  * goes to the exemplar of least squared Euclidean distance (exact: FP32
  * distances with an FP64 recheck of every candidate within the FP32 error
  * bound; lowest exemplar index on ties); exemplars label themselves.  The
  * n x n similarity matrix is never formed.  X: device n x d (ldx).  idx:
  * device, n global labels.  res: iterations/converged of the landmark AP,
  * |E|, dpsim = -sum of squared distances of non-exemplars to their exemplar
- * (FP64), expref = |E| * landmark preference, netsim.  exemplars_out (host,
+ * (FP64), expref = |E| * landmark preference, netsim.  params->flags:
+ * APX_CHECK_FINITE and APX_MSG_THRESHOLD apply to the landmark AP;
+ * APX_RAW_LABELS is rejected (labels here are assignments).  exemplars_out (host,
  * nullable, capacity n_landmarks) receives the exemplar indices ascending.
  * Needs 2 <= n_landmarks <= n, d <= 4096.  Synchronises.
  */
 apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
                      int64_t n_landmarks, const int64_t *landmarks, uint64_t seed, double noise_rel,
-                     const apx_params *params, int32_t *idx, apx_result *res, int64_t *exemplars_out);
+                     int32_t pref_mode, float pref_scalar, const apx_params *params, int32_t *idx,
+                     apx_result *res, int64_t *exemplars_out);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start.  The paper starts Algorithm 1 from a(i,k) = 0 (Eq. (1))

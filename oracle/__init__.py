@@ -60,6 +60,9 @@ def lib():
     L.apo_ap.argtypes = [_i64, _f64p, _dbl, _i32, _i32, _f64p, _f64p, _i32p,
                          ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.c_void_p]
     L.apo_ap.restype = ctypes.c_int
+    L.apo_ap_tol.argtypes = [_i64, _f64p, _dbl, _i32, _i32, _dbl, _f64p, _f64p, _i32p,
+                             ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.c_void_p]
+    L.apo_ap_tol.restype = ctypes.c_int
     L.apo_decisions.argtypes = [_i64, _f64p, _f64p, _i32p]
     L.apo_finalize.argtypes = [_i64, _f64p, _i32p, _i32p, ctypes.POINTER(_dbl),
                                ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
@@ -169,9 +172,11 @@ class APResult:
 
 def ap(S: np.ndarray, lam: float = 0.5, max_iter: int = 200, conv_iter: int = 15,
        A0: np.ndarray | None = None, R0: np.ndarray | None = None,
-       finalize_labels: bool = True) -> APResult:
+       finalize_labels: bool = True, msg_tol: float | None = None) -> APResult:
     """Run Algorithm 1 on S (diagonal = preferences) from A0 (default 0, Eq. (1))
-    and R0 (default 0).  conv_iter=0 runs exactly max_iter iterations."""
+    and R0 (default 0).  conv_iter=0 runs exactly max_iter iterations.
+    msg_tol (Algorithm 1, Step 4): also stop after the first iteration t >= 2
+    whose every message changed by at most msg_tol."""
     S = np.ascontiguousarray(S, dtype=np.float64)
     n = S.shape[0]
     R = np.zeros((n, n)) if R0 is None else np.array(R0, dtype=np.float64, order="C", copy=True)
@@ -179,8 +184,9 @@ def ap(S: np.ndarray, lam: float = 0.5, max_iter: int = 200, conv_iter: int = 15
     dec = np.empty(n, dtype=np.int32)
     it, cv = _i32(0), _i32(0)
     trace = np.zeros(max_iter, dtype=np.int32)
-    rc = lib().apo_ap(n, S, lam, max_iter, conv_iter, R, A, dec, ctypes.byref(it),
-                      ctypes.byref(cv), trace.ctypes.data)
+    tol = -1.0 if msg_tol is None else float(msg_tol)
+    rc = lib().apo_ap_tol(n, S, lam, max_iter, conv_iter, tol, R, A, dec, ctypes.byref(it),
+                          ctypes.byref(cv), trace.ctypes.data)
     if rc != 0:
         raise ValueError(f"apo_ap failed with code {rc}")
     res = APResult(R, A, dec, int(it.value), bool(cv.value), trace[: it.value].copy())
@@ -299,14 +305,16 @@ class LAPResult:
 
 
 def lap(X: np.ndarray, landmarks: np.ndarray, seed: int = 0, lam: float = 0.9,
-        max_iter: int = 2000, conv_iter: int = 15, noise_rel: float = 1e-12) -> LAPResult:
-    """AP on the landmark points (median preference, tie noise), then every
-    point goes to its nearest exemplar by FP64 squared distance.  The
-    landmark matrix lists the landmarks in ascending point index."""
+        max_iter: int = 2000, conv_iter: int = 15, noise_rel: float = 1e-12,
+        pref="median") -> LAPResult:
+    """AP on the landmark points (preference: the median of the landmark
+    similarities, or one given value; tie noise), then every point goes to
+    its nearest exemplar by FP64 squared distance.  The landmark matrix lists
+    the landmarks in ascending point index."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     M = np.sort(np.asarray(landmarks, dtype=np.int64))
     XM = np.ascontiguousarray(X[M])
-    prep = prepare(similarity(XM), "median", seed, noise_rel)
+    prep = prepare(similarity(XM), pref, seed, noise_rel)
     res = ap(prep.S, lam, max_iter, conv_iter)
     ex_local = res.exemplars
     ex = np.sort(M[ex_local]).astype(np.int64)

@@ -160,9 +160,27 @@ static int32_t decision_row(int64_t n, int64_t i, const double *A, const double 
     return bk;
 }
 
+/* Largest |x - y| over n*n entries. */
+static double max_abs_diff(int64_t n, const double *x, const double *y)
+{
+    double m = 0.0;
+    for (int64_t q = 0; q < n * n; ++q) {
+        const double v = fabs(x[q] - y[q]);
+        if (v > m) m = v;
+    }
+    return m;
+}
+
 int apo_ap(int64_t n, const double *S, double lam, int32_t max_iter, int32_t conv_iter,
            double *R, double *A, int32_t *dec, int32_t *iters_out, int32_t *converged_out,
            int32_t *trace_nex)
+{
+    return apo_ap_tol(n, S, lam, max_iter, conv_iter, -1.0, R, A, dec, iters_out, converged_out, trace_nex);
+}
+
+int apo_ap_tol(int64_t n, const double *S, double lam, int32_t max_iter, int32_t conv_iter, double msg_tol,
+               double *R, double *A, int32_t *dec, int32_t *iters_out, int32_t *converged_out,
+               int32_t *trace_nex)
 {
     if (n < 1 || max_iter < 1 || !(lam >= 0.0 && lam < 1.0) || conv_iter < 0) return 1;
     if (n == 1) {
@@ -176,10 +194,21 @@ int apo_ap(int64_t n, const double *S, double lam, int32_t max_iter, int32_t con
     double *c = (double *)malloc(sizeof(double) * (size_t)n);
     uint8_t *e_prev = (uint8_t *)calloc((size_t)n, 1);
     uint8_t *e_cur = (uint8_t *)calloc((size_t)n, 1);
-    if (!c || !e_prev || !e_cur) { free(c); free(e_prev); free(e_cur); return 2; }
+    /* message-change rule: copies of the previous iteration's messages */
+    const int msg_on = msg_tol >= 0.0;
+    double *Rp = msg_on ? (double *)malloc(sizeof(double) * (size_t)(n * n)) : NULL;
+    double *Ap = msg_on ? (double *)malloc(sizeof(double) * (size_t)(n * n)) : NULL;
+    if (!c || !e_prev || !e_cur || (msg_on && (!Rp || !Ap))) {
+        free(c); free(e_prev); free(e_cur); free(Rp); free(Ap);
+        return 2;
+    }
 
     int32_t run = 0, t = 0, converged = 0;
     for (t = 1; t <= max_iter; ++t) {
+        if (msg_on) {
+            memcpy(Rp, R, sizeof(double) * (size_t)(n * n));
+            memcpy(Ap, A, sizeof(double) * (size_t)(n * n));
+        }
         /* Step 2: responsibilities from the previous availabilities. */
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) responsibility_row(n, i, S, A, R, lam);
@@ -203,11 +232,17 @@ int apo_ap(int64_t n, const double *S, double lam, int32_t max_iter, int32_t con
         run = same ? run + 1 : 1;
         uint8_t *tmp = e_prev; e_prev = e_cur; e_cur = tmp;
         if (conv_iter > 0 && run >= conv_iter && nex > 0) { converged = 1; break; }
+        /* Step 4, second rule: every message changed by at most msg_tol in
+         * this iteration (from the second iteration on). */
+        if (msg_on && t >= 2 && max_abs_diff(n, R, Rp) <= msg_tol && max_abs_diff(n, A, Ap) <= msg_tol) {
+            converged = 1;
+            break;
+        }
     }
     if (t > max_iter) t = max_iter;
     if (iters_out) *iters_out = t;
     if (converged_out) *converged_out = converged;
-    free(c); free(e_prev); free(e_cur);
+    free(c); free(e_prev); free(e_cur); free(Rp); free(Ap);
     return 0;
 }
 

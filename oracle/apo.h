@@ -30,6 +30,13 @@ void apo_add_noise(int64_t n, double *S, uint64_t seed, double scale);
 int apo_ap(int64_t n, const double *S, double lam, int32_t max_iter, int32_t conv_iter,
            double *R, double *A, int32_t *dec, int32_t *iters_out, int32_t *converged_out,
            int32_t *trace_nex);
+/* apo_ap with the message-change rule of Algorithm 1, Step 4 as well:
+ * msg_tol >= 0 also stops (converged) after the first iteration t >= 2 in
+ * which every r and every a changed by at most msg_tol; msg_tol < 0 is
+ * apo_ap. */
+int apo_ap_tol(int64_t n, const double *S, double lam, int32_t max_iter, int32_t conv_iter, double msg_tol,
+               double *R, double *A, int32_t *dec, int32_t *iters_out, int32_t *converged_out,
+               int32_t *trace_nex);
 void apo_decisions(int64_t n, const double *A, const double *R, int32_t *dec);
 
 /* Algorithm 1 outputs idx, dpsim, expref, netsim from the decisions. */

@@ -23,6 +23,9 @@ APX_OK, APX_EINVAL, APX_ENOMEM, APX_EDEVICE, APX_ENOTIMPL = range(5)
 APX_PREF_MEDIAN, APX_PREF_SCALAR, APX_PREF_VECTOR = range(3)
 APX_COLD, APX_WARM_A, APX_WARM_AR = range(3)
 APX_MLP_FEATURES, APX_MLP_PARAMS = 16, 18946
+APX_RAW_LABELS, APX_CHECK_FINITE, APX_MSG_THRESHOLD = 1, 2, 4
+(APX_OP_SIMILARITY, APX_OP_ITERATE, APX_OP_SOLVE, APX_OP_SOLVE_BATCHED, APX_OP_PAP, APX_OP_LAP,
+ APX_OP_FEATURES, APX_OP_MLP_BACKWARD, APX_OP_WARMSTART) = range(9)
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTIMPL"}
 
 
@@ -34,7 +37,8 @@ class ApxError(RuntimeError):
 
 class apx_params(ctypes.Structure):
     _fields_ = [("damping", ctypes.c_float), ("max_iter", ctypes.c_int32),
-                ("conv_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("conv_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("msg_tol", ctypes.c_float)]
 
 
 class apx_result(ctypes.Structure):
@@ -61,6 +65,8 @@ SIGNATURES = {
     "apx_set_stream": (ctypes.c_int, [_P, _P]),
     "apx_last_error": (ctypes.c_char_p, [_P]),
     "apx_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "apx_workspace_size": (ctypes.c_size_t, [_P, _I32, _I64, _I64, _I64, _I32, _P]),
+    "apx_set_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
@@ -85,7 +91,8 @@ SIGNATURES = {
     "pap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, _P, _P, ctypes.POINTER(apx_params),
                                  _P, ctypes.POINTER(apx_result), ctypes.POINTER(apx_result)]),
     "lap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
-                                 ctypes.POINTER(apx_params), _P, ctypes.POINTER(apx_result), _P]),
+                                 _I32, ctypes.c_float, ctypes.POINTER(apx_params), _P,
+                                 ctypes.POINTER(apx_result), _P]),
     "apx_features": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P]),
     "apx_mlp_forward": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
     "apx_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P, _P]),
@@ -229,8 +236,10 @@ def ap_iterate(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float
 
 def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float = 0.5,
              max_iter: int = 200, conv_iter: int = 15, warm: int = APX_COLD,
-             idx: torch.Tensor | None = None, check_every: int = 0):
-    """Algorithm 1 to its stop rule; returns (idx int32 tensor, Result)."""
+             idx: torch.Tensor | None = None, check_every: int = 0, flags: int = 0,
+             msg_tol: float = 0.0):
+    """Algorithm 1 to its stop rule; returns (idx int32 tensor, Result).
+    flags: APX_RAW_LABELS | APX_CHECK_FINITE | APX_MSG_THRESHOLD (with msg_tol)."""
     Sp, n, ld = _mat(S, "S")
     Rp, _, ldr = _mat(R, "R", n)
     Ap, _, lda = _mat(A, "A", n)
@@ -238,12 +247,39 @@ def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float =
         raise ValueError("S, R and A must share one leading dimension")
     if idx is None:
         idx = torch.empty(n, dtype=torch.int32, device=S.device)
-    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, msg_tol)
     res = apx_result()
     ctx = context(S.device)
     _check(ctx, lib().ap_solve(ctx, Sp, n, ld, Rp, Ap, warm, ctypes.byref(prm), _P(idx.data_ptr()),
                                ctypes.byref(res)), "ap_solve")
     return idx, _res(res)
+
+
+def apx_workspace_size(op: int, n: int = 0, ld: int = 0, d: int = 0, count: int = 0, sizes=None,
+                       device=None) -> int:
+    """Device workspace bytes one call of `op` (APX_OP_*) needs."""
+    import numpy as np
+    sz = None if sizes is None else np.ascontiguousarray(sizes, dtype=np.int64)
+    ctx = context(device)
+    return int(lib().apx_workspace_size(ctx, op, n, ld, d, count,
+                                        None if sz is None else _P(sz.ctypes.data)))
+
+
+def apx_set_workspace(buf: torch.Tensor | None, device=None) -> None:
+    """Hand a caller-owned uint8 CUDA tensor to the library as its workspace
+    (None: back to a library-owned one).  Keep `buf` alive while it is set."""
+    ctx = context(device)
+    if buf is None:
+        _check(ctx, lib().apx_set_workspace(ctx, None, 0), "apx_set_workspace")
+        return
+    if not (buf.is_cuda and buf.dtype == torch.uint8 and buf.is_contiguous()):
+        raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+    _check(ctx, lib().apx_set_workspace(ctx, _P(buf.data_ptr()), buf.numel()), "apx_set_workspace")
+
+
+def apx_workspace_bytes(device=None) -> int:
+    ctx = context(device)
+    return int(lib().apx_workspace_bytes(ctx))
 
 
 def apx_set_implicit(list_capacity: int, min_n: int = 8192, device=None) -> None:
@@ -333,7 +369,7 @@ def apx_profile_read(device=None) -> tuple[int, float]:
 
 
 def ap_solve_batched(S_list, R_list=None, A_list=None, damping: float = 0.5, max_iter: int = 200,
-                     conv_iter: int = 15, warm: int = APX_COLD, check_every: int = 0):
+                     conv_iter: int = 15, warm: int = APX_COLD, check_every: int = 0, flags: int = 0):
     """Algorithm 1 on many instances in one batch; returns ([idx tensors], [Result])."""
     count = len(S_list)
     R_list = R_list or [empty_matrix(S.shape[0], device=S.device) for S in S_list]
@@ -349,7 +385,7 @@ def ap_solve_batched(S_list, R_list=None, A_list=None, damping: float = 0.5, max
         idx = torch.empty(n, dtype=torch.int32, device=S.device)
         idxs.append(idx)
         insts[j] = apx_instance(n, ld, Sp, Rp, Ap, _P(idx.data_ptr()))
-    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, 0.0)
     res = (apx_result * count)()
     ctx = context(S_list[0].device)
     _check(ctx, lib().ap_solve_batched(ctx, count, insts, warm, ctypes.byref(prm), res), "ap_solve_batched")
@@ -357,7 +393,8 @@ def ap_solve_batched(S_list, R_list=None, A_list=None, damping: float = 0.5, max
 
 
 def pap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, k: int, perm=None, offsets=None,
-              damping: float = 0.5, max_iter: int = 200, conv_iter: int = 15, check_every: int = 0):
+              damping: float = 0.5, max_iter: int = 200, conv_iter: int = 15, check_every: int = 0,
+              flags: int = 0, msg_tol: float = 0.0):
     """Partition AP (Algorithm 2); returns (idx, Result, [Result per part])."""
     import numpy as np
     Sp, n, ld = _mat(S, "S")
@@ -368,7 +405,7 @@ def pap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, k: int, perm=No
     pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
     of = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64)
     idx = torch.empty(n, dtype=torch.int32, device=S.device)
-    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, msg_tol)
     res = apx_result()
     sub = (apx_result * k)()
     ctx = context(S.device)
@@ -380,8 +417,10 @@ def pap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, k: int, perm=No
 
 
 def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, noise_rel: float = 1e-12,
-              damping: float = 0.9, max_iter: int = 2000, conv_iter: int = 15, check_every: int = 0):
-    """Landmark AP (Algorithm 3, Steps 1-2); returns (idx, Result, exemplar indices)."""
+              damping: float = 0.9, max_iter: int = 2000, conv_iter: int = 15, check_every: int = 0,
+              pref: str | float = "median", flags: int = 0, msg_tol: float = 0.0):
+    """Landmark AP (Algorithm 3, Steps 1-2); returns (idx, Result, exemplar indices).
+    pref: "median" (of the landmark similarities) or one float for every landmark."""
     import numpy as np
     if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
         raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
@@ -390,13 +429,14 @@ def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, 
     if lm is not None and lm.size != n_landmarks:
         raise ValueError(f"landmarks has {lm.size} entries, expected {n_landmarks}")
     idx = torch.empty(n, dtype=torch.int32, device=X.device)
-    prm = apx_params(damping, max_iter, conv_iter, check_every)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, msg_tol)
     res = apx_result()
     ex = np.zeros(n_landmarks, dtype=np.int64)
+    mode, scal = (APX_PREF_MEDIAN, 0.0) if isinstance(pref, str) else (APX_PREF_SCALAR, float(pref))
     ctx = context(X.device)
     _check(ctx, lib().lap_solve(ctx, _P(X.data_ptr()), n, d, X.stride(0), n_landmarks,
                                 None if lm is None else _P(lm.ctypes.data), seed, noise_rel,
-                                ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res),
+                                mode, scal, ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res),
                                 _P(ex.ctypes.data)), "lap_solve")
     r = _res(res)
     return idx, r, ex[: r.n_exemplars].copy()

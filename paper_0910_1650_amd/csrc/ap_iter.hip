@@ -424,9 +424,12 @@ __global__ __launch_bounds__(T) void k_row_pass(PassArgs p) {
 // Row pass, register variant for long rows (LDS too small for u and the
 // partials): u and the partials live in registers, t_k is read per chunk
 // from L2, and rows are not prefetched.
+// PASS_FULL_DELTA also records the largest message changes of the pass,
+// max |a_t - a_{t-1}| and max |r_{t+1} - r_t| over the valid elements.
 template <int T, int J, int MODE>
 __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
-    constexpr bool DO_A = (MODE == PASS_FULL || MODE == PASS_A_ONLY);
+    constexpr bool DELTA = (MODE == PASS_FULL_DELTA);
+    constexpr bool DO_A = (MODE == PASS_FULL || MODE == PASS_A_ONLY || DELTA);
     constexpr bool DO_R = (MODE != PASS_A_ONLY);
     constexpr bool LD_S = DO_R;
     constexpr bool LD_RA = (MODE != PASS_R_COLD);
@@ -458,6 +461,7 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
     for (int j = 0; j < J; ++j)
         if constexpr (DO_R) part[j] = z4;
     int my_nex = 0, my_changed = 0;
+    float mda = 0.0f, mdr = 0.0f;   // DELTA: largest |change| of A and R seen by this thread
     const rsrc_t t_rs = row_rsrc(p.tcol, p.ldp);
 
     for (int64_t i = r0; i < r1; ++i) {
@@ -472,6 +476,7 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
         float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
         int l1 = -1, dl = -1;
         float4 u[DO_R ? J : 1];
+        float4 rold[DELTA ? J : 1];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (!(j < J - 1 || last_in)) continue;
@@ -484,8 +489,15 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
             }
             if constexpr (LD_S) sv = bld4(s_rs, voff, j * T * 16);
             if constexpr (DO_A) {
+                const float4 aold = a;
                 chunk_avail(a, r, bld4(t_rs, voff, j * T * 16), ci, j, dg, c, n, full, lam, oml, dv, dl);
                 store_chunk(Arow, a_rs, voff, j * T * 16, c, n, full, a);
+                if constexpr (DELTA) {
+                    rold[j] = r;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (full || c + e < n) mda = fmaxf(mda, fabsf(f4get(a, e) - f4get(aold, e)));
+                }
             }
             if constexpr (DO_R) u[j] = chunk_top2(a, r, sv, j, c, n, full, lam, oml, v1, l1, v2);
         }
@@ -511,6 +523,11 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
                 add4(part[j], chunk_resp(u[j], j, ko, dg, m_self, m_other, c, n, full, rn,
                                          p.rdiag + ii));
                 store_chunk(Rout, o_rs, voff, j * T * 16, c, n, full, rn);
+                if constexpr (DELTA) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (full || c + e < n) mdr = fmaxf(mdr, fabsf(f4get(rn, e) - f4get(rold[j], e)));
+                }
             }
         }
     }
@@ -524,6 +541,18 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
         if (tid == 0 && p.st != nullptr) {
             if (my_nex) atomicAdd(&p.st->nex, my_nex);
             if (my_changed) atomicOr(&p.st->changed, 1);
+        }
+    }
+    if constexpr (DELTA) {
+        // non-negative floats: their bit patterns order like the values
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mda = fmaxf(mda, __shfl_xor(mda, off, 64));
+            mdr = fmaxf(mdr, __shfl_xor(mdr, off, 64));
+        }
+        if (lane == 0 && p.st != nullptr) {
+            atomicMax(&p.st->d_a, __float_as_uint(mda));
+            atomicMax(&p.st->d_r_next, __float_as_uint(mdr));
         }
     }
 }
@@ -592,7 +621,14 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
         st->iter = t;
         st->run = run;
         st->last_nex = st->nex;
-        if (st->conv_iter > 0 && run >= st->conv_iter && st->nex > 0) {
+        // message changes of iteration t: |A_t - A_{t-1}| from this pass,
+        // |R_t - R_{t-1}| from the previous one
+        const bool msg_stop = st->msg_on && t >= 2 &&
+                              fmaxf(__uint_as_float(st->d_a), __uint_as_float(st->d_r)) <= st->msg_tol;
+        st->d_r = st->d_r_next;
+        st->d_r_next = 0u;
+        st->d_a = 0u;
+        if ((st->conv_iter > 0 && run >= st->conv_iter && st->nex > 0) || msg_stop) {
             st->converged = 1;
             st->frozen = 1;
         } else if (t >= st->max_iter) {
@@ -605,11 +641,14 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
     }
 }
 
-__global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam) {
+__global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, int msg_on,
+                             float msg_tol) {
     if (threadIdx.x == 0) {
         ApState s{};
         s.max_iter = max_iter;
         s.conv_iter = conv_iter;
+        s.msg_on = msg_on;
+        s.msg_tol = msg_tol;
         s.imp_lam = lam;
         s.imp_al = imp_alpha(lam, 1);
         s.imp_al1 = imp_alpha(lam, 2);
@@ -636,6 +675,49 @@ __global__ void k_copy_rows(float *dst, const float *src, int64_t rows, int64_t 
         for (int64_t c = threadIdx.x; c < c4; c += blockDim.x) d4[c] = s4[c];
         for (int64_t c = c4 * 4 + threadIdx.x; c < cols; c += blockDim.x) dst[r * ld + c] = src[r * ld + c];
     }
+}
+
+// flag |= 1 when an entry of the rows x cols block (leading dimension ld) is
+// NaN or infinite (exponent field all ones).
+__global__ __launch_bounds__(256) void k_check_finite(const float *M, int64_t rows, int64_t cols, int64_t ld,
+                                                      int32_t *flag) {
+    uint32_t bad = 0u;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const float *row = M + r * ld;
+        for (int64_t c = threadIdx.x; c < cols; c += blockDim.x)
+            bad |= (uint32_t)((__float_as_uint(row[c]) & 0x7f800000u) == 0x7f800000u);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// One wavefront per row: d_i = argmax_k a(i,k) + r(i,k) in FP32, lowest k
+// on ties (the decision the row passes take).
+__global__ __launch_bounds__(256) void k_decide(const float *A, const float *R, int64_t n, int64_t ld,
+                                                int32_t *dec) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float *ar = A + i * ld, *rr = R + i * ld;
+    float bv = kNegInf;
+    int bk = INT32_MAX;
+    for (int64_t k = lane; k < n; k += 64) {
+        const float v = ar[k] + rr[k];
+        if (v > bv) {   // ascending k within a lane: a tie keeps the lower k
+            bv = v;
+            bk = (int)k;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const int ok = __shfl_xor(bk, off, 64);
+        if (ov > bv || (ov == bv && ok < bk)) {
+            bv = ov;
+            bk = ok;
+        }
+    }
+    if (lane == 0) dec[i] = bk;
 }
 
 // ---- finalize ------------------------------------------------------------
@@ -677,7 +759,12 @@ __global__ __launch_bounds__(256) void k_labels(FinalArgs a) {
     const float *Srow = a.S + i * a.ld;
     double dp = 0.0, ep = 0.0;
     int lab;
-    if (m == 0) {
+    if (a.raw != nullptr) {
+        // raw decisions as labels: exemplars (d_i = i) add s(i,i) to expref
+        lab = a.raw[i];
+        if (lab == (int)i) ep = (double)Srow[i];
+        else dp = (double)Srow[lab];
+    } else if (m == 0) {
         lab = -1;
     } else if (a.eflag[i]) {
         lab = (int)i;
@@ -752,6 +839,11 @@ hipError_t launch_lds(const PassArgs &a, int grid, size_t lds, hipStream_t s) {
 
 template <int T, int J>
 hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t s) {
+    if (mode == PASS_FULL_DELTA) {
+        // register variant only (keeps R_t of the row for the change)
+        k_row_pass_reg<T, J, PASS_FULL_DELTA><<<pl.grid, T, 0, s>>>(a);
+        return hipGetLastError();
+    }
     if (pl.lds_bytes > 0) {
         switch (mode) {
         case PASS_FULL: return launch_lds<T, J, PASS_FULL>(a, pl.grid, pl.lds_bytes, s);
@@ -2128,8 +2220,21 @@ hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s) {
-    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter, lam);
+hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s,
+                             int msg_on, float msg_tol) {
+    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter, lam, msg_on, msg_tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float *M, int64_t rows, int64_t cols, int64_t ld, int32_t *flag,
+                               hipStream_t s) {
+    const int g = (int)(rows < 8192 ? (rows > 0 ? rows : 1) : 8192);
+    k_check_finite<<<g, 256, 0, s>>>(M, rows, cols, ld, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide(const float *A, const float *R, int64_t n, int64_t ld, int32_t *dec, hipStream_t s) {
+    k_decide<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(A, R, n, ld, dec);
     return hipGetLastError();
 }
 

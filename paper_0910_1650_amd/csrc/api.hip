@@ -32,6 +32,9 @@ apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what) {
 
 apx_status ws_reserve(apx_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return APX_OK;
+    if (ctx->ws_external)
+        return set_err(ctx, APX_ENOMEM, "the call needs %zu bytes of workspace; apx_set_workspace set %zu",
+                       bytes, ctx->ws_bytes);
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_err(ctx, e, "workspace sync");
     if (ctx->ws) {
@@ -47,6 +50,30 @@ apx_status ws_reserve(apx_ctx *ctx, size_t bytes) {
         return set_err(ctx, APX_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
     }
     ctx->ws_bytes = want;
+    return APX_OK;
+}
+
+apx_status check_params(apx_ctx *ctx, const apx_params *p) {
+    if (!p) return set_err(ctx, APX_EINVAL, "params is null");
+    if (!(p->damping >= 0.0f && p->damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
+    if (p->max_iter < 1 || p->conv_iter < 0)
+        return set_err(ctx, APX_EINVAL, "max_iter must be >= 1 and conv_iter >= 0");
+    if (p->flags & ~(uint32_t)(APX_RAW_LABELS | APX_CHECK_FINITE | APX_MSG_THRESHOLD))
+        return set_err(ctx, APX_EINVAL, "unknown flags 0x%x", p->flags);
+    if ((p->flags & APX_MSG_THRESHOLD) && !(p->msg_tol >= 0.0f && std::isfinite(p->msg_tol)))
+        return set_err(ctx, APX_EINVAL, "msg_tol must be finite and >= 0");
+    return APX_OK;
+}
+
+apx_status check_finite(apx_ctx *ctx, const float *M, int64_t n, int64_t ld, const char *name) {
+    hipStream_t s = ctx->stream;
+    hipError_t e = launch_fill_u8(reinterpret_cast<uint8_t *>(ctx->dflag), sizeof(int32_t), 0, s);
+    if (e == hipSuccess) e = launch_check_finite(M, n, n, ld, ctx->dflag, s);
+    int32_t *h = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 2048);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, ctx->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "finite check");
+    if (*h) return set_err(ctx, APX_EINVAL, "%s holds a NaN or infinite entry", name);
     return APX_OK;
 }
 
@@ -252,7 +279,8 @@ namespace {
 
 // How ap_solve keeps the messages: both explicit; R implicit (ImpArgs);
 // R and A implicit (XLayout, cold start).
-enum SolveMode : int { SOLVE_EXPLICIT = 0, SOLVE_IMPLICIT_R = 1, SOLVE_IMPLICIT_A = 2 };
+// SOLVE_EXPLICIT_DELTA: explicit, recording the message changes of each pass.
+enum SolveMode : int { SOLVE_EXPLICIT = 0, SOLVE_IMPLICIT_R = 1, SOLVE_IMPLICIT_A = 2, SOLVE_EXPLICIT_DELTA = 3 };
 
 // Runs iterations t0 .. t0+chunk-1 of ap_solve as one replay of a captured
 // graph on the context's private stream, ordered after everything already
@@ -292,7 +320,7 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
                                    ctx->cap);
             } else {
                 PassArgs pf = pass_args(S, buf[t & 1], buf[(t + 1) & 1], A, n, ld, lam, w, w.dec, w.eflag, w.st);
-                e = launch_row_pass(pl, PASS_FULL, pf, ctx->cap);
+                e = launch_row_pass(pl, mode == SOLVE_EXPLICIT_DELTA ? PASS_FULL_DELTA : PASS_FULL, pf, ctx->cap);
             }
             if (e == hipSuccess)
                 e = launch_col_reduce(col_args(w, n, w.st, 1, mode == SOLVE_IMPLICIT_A ? t : -1, lam), ctx->cap);
@@ -363,6 +391,11 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return APX_ENOMEM;
     }
+    if (hipMalloc(&ctx->dflag, 256) != hipSuccess) {
+        (void)hipHostFree(ctx->pinned);
+        delete ctx;
+        return APX_ENOMEM;
+    }
     const char *gv = getenv("APX_GRAPHS");
     if (gv && gv[0] == '0') ctx->graphs = false;
     const char *iv = getenv("APX_IMPLICIT_K");
@@ -395,9 +428,59 @@ void apx_destroy(apx_ctx *ctx) {
         (void)hipStreamDestroy(ctx->cap);
     }
     if (ctx->join) (void)hipEventDestroy(ctx->join);
-    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->ws && !ctx->ws_external) (void)hipFree(ctx->ws);
+    if (ctx->dflag) (void)hipFree(ctx->dflag);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
+}
+
+apx_status apx_set_workspace(apx_ctx *ctx, void *dev_ptr, size_t bytes) {
+    if (!ctx) return APX_EINVAL;
+    if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) != 0)
+        return set_err(ctx, APX_EINVAL, "workspace must be 256-byte aligned");
+    DevGuard g(ctx->device);
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "workspace sync");
+    if (ctx->ws && !ctx->ws_external) (void)hipFree(ctx->ws);
+    ctx->ws = dev_ptr;
+    ctx->ws_bytes = dev_ptr ? bytes : 0;
+    ctx->ws_external = dev_ptr != nullptr;
+    ctx->ws_base = 0;
+    return APX_OK;
+}
+
+size_t apx_workspace_size(const apx_ctx *ctx, int32_t op, int64_t n, int64_t ld, int64_t d, int32_t count,
+                          const int64_t *sizes) {
+    if (!ctx) return 0;
+    const int cus = ctx->num_cus;
+    switch (op) {
+    case APX_OP_SIMILARITY:
+        return n >= 2 ? similarity_ws_bytes(n) : 0;
+    case APX_OP_ITERATE:
+        return (n >= 2 && ld >= n) ? resp_step_ws_bytes(n, ld, cus) : 0;
+    case APX_OP_SOLVE:
+        return (n >= 1 && ld >= n) ? solve_ws_bytes(n, ld, cus) : 0;
+    case APX_OP_SOLVE_BATCHED: {
+        if (count < 1 || !sizes) return 0;
+        std::vector<BatchSpec> spec(count);
+        for (int j = 0; j < count; ++j) {
+            if (sizes[j] < 2) return 0;
+            spec[j] = BatchSpec{sizes[j], round4(sizes[j]), nullptr, nullptr, nullptr, nullptr};
+        }
+        return batched_ws_bytes(count, spec.data(), cus);
+    }
+    case APX_OP_PAP:
+        return (n >= 2 && ld >= n && count >= 1 && count <= n) ? pap_ws_bytes(n, ld, count, sizes, cus) : 0;
+    case APX_OP_LAP:
+        return (n >= 2 && d >= 1 && count >= 2 && count <= n) ? lap_ws_bytes(n, d, count, cus) : 0;
+    case APX_OP_FEATURES:
+        return n >= 2 ? features_ws_bytes(n) : 0;
+    case APX_OP_MLP_BACKWARD:
+        return count >= 1 ? mlp_backward_ws_bytes(count) : 0;
+    case APX_OP_WARMSTART:
+        return (n >= 2 && ld >= n) ? warmstart_ws_bytes(n, ld, cus) : 0;
+    default:
+        return 0;
+    }
 }
 
 apx_status apx_set_stream(apx_ctx *ctx, void *hip_stream) {
@@ -500,12 +583,13 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     APX_TRY(check_matrix(ctx, A, "A", n, ld));
     if (!params || !res || !idx) return set_err(ctx, APX_EINVAL, "params, idx and res must be non-null");
     if (warm < APX_COLD || warm > APX_WARM_AR) return set_err(ctx, APX_EINVAL, "bad warm mode %d", warm);
+    APX_TRY(check_params(ctx, params));
     const float lam = params->damping;
-    if (!(lam >= 0.0f && lam < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
-    if (params->max_iter < 1 || params->conv_iter < 0)
-        return set_err(ctx, APX_EINVAL, "max_iter must be >= 1 and conv_iter >= 0");
+    const bool raw_labels = (params->flags & APX_RAW_LABELS) != 0;
+    const bool msg_rule = (params->flags & APX_MSG_THRESHOLD) != 0;
     DevGuard g(ctx->device);
     hipStream_t s = ctx->stream;
+    if (params->flags & APX_CHECK_FINITE) APX_TRY(check_finite(ctx, S, n, ld, "S"));
     std::memset(res, 0, sizeof *res);
 
     if (n == 1) {
@@ -531,7 +615,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
-    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, lam, s), "state init");
+    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, lam, s, msg_rule ? 1 : 0,
+                              params->msg_tol), "state init");
     HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
 
     // R_t lives in buf[t & 1]; buf[0] is the caller's R.  With R_0 = 0 (cold
@@ -540,7 +625,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     // Cold start: A is kept implicitly too (XLayout) unless disabled; each
     // form has its own size threshold (below it the explicit pass is faster).
     PassPlan ipl{}, apl{};
-    const bool r_ok = ctx->implicit_k > 0 && warm != APX_WARM_AR && imp_plan(n, ctx->num_cus, &ipl);
+    // the message-change rule needs both messages in memory: explicit form
+    const bool r_ok = !msg_rule && ctx->implicit_k > 0 && warm != APX_WARM_AR && imp_plan(n, ctx->num_cus, &ipl);
     bool imp_a = r_ok && warm == APX_COLD && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
                  ia_plan(n, ctx->num_cus, &apl);
     bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
@@ -600,7 +686,10 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         const int32_t t_first = t;
         bool done = false;
         if (use_graph && stop_at - t == chunk) {
-            const int mode = imp_a ? SOLVE_IMPLICIT_A : implicit ? SOLVE_IMPLICIT_R : SOLVE_EXPLICIT;
+            const int mode = imp_a      ? SOLVE_IMPLICIT_A
+                             : implicit ? SOLVE_IMPLICIT_R
+                             : msg_rule ? SOLVE_EXPLICIT_DELTA
+                                        : SOLVE_EXPLICIT;
             const apx_status gs = graph_chunk(ctx, imp_a ? apl : implicit ? ipl : pl, mode, S, buf, A, n, ld, lam, w,
                                               chunk, t, hst);
             if (gs == APX_OK) {
@@ -627,7 +716,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                                            imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k), s),
                             "row pass");
                 else
-                    HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
+                    HIP_TRY(launch_row_pass(pl, msg_rule ? PASS_FULL_DELTA : PASS_FULL, pf, s), "row pass");
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot + 1], s), "event");
                 HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1, imp_a ? t : -1, lam), s), "column reduce");
             }
@@ -699,6 +788,11 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     fa.idx = idx;
     fa.contrib = w.contrib;
     fa.sums = w.sums;
+    if (raw_labels) {
+        // d_T = argmax_k a_T(i,k) + r_T(i,k) from the messages just returned
+        HIP_TRY(launch_decide(A, R, n, ld, w.dec, s), "decisions");
+        fa.raw = w.dec;
+    }
     HIP_TRY(launch_finalize(fa, s), "finalize");
     double *hd = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 256);
     int32_t *hn = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 512);

@@ -30,7 +30,14 @@ struct ApState {
     float imp_al;       // alpha_t for the next full pass t (1 - lambda^t)
     float imp_al1;      // alpha_{t+1}
     float imp_al_prev;  // alpha of the last full pass that ran
-    int32_t pad[2];
+    // Message-change stop rule (Algorithm 1, Step 4), explicit passes only:
+    // bit patterns of non-negative floats, so unsigned atomicMax orders them.
+    uint32_t d_a;       // max |a_t - a_{t-1}| of the running pass t
+    uint32_t d_r_next;  // max |r_{t+1} - r_t| of the running pass t
+    uint32_t d_r;       // max |r_t - r_{t-1}| (from pass t-1)
+    int32_t msg_on;     // 1: stop once both changes are <= msg_tol (t >= 2)
+    float msg_tol;
+    int32_t pad[3];
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -40,7 +47,9 @@ struct ApState {
 //   PASS_R_ONLY  R_{t+1} from (R_t, A_t)           (reads S, R, A)
 //   PASS_R_COLD  R_1 from R_0 = A_0 = 0            (reads S)
 //   PASS_A_ONLY  A_t and decisions, no R_{t+1}      (reads R, A)
-enum PassMode : int { PASS_FULL = 0, PASS_R_ONLY = 1, PASS_A_ONLY = 2, PASS_R_COLD = 3 };
+//   PASS_FULL_DELTA  PASS_FULL that also records max |a_t - a_{t-1}| and
+//                max |r_{t+1} - r_t| in the run state (message-change stop)
+enum PassMode : int { PASS_FULL = 0, PASS_R_ONLY = 1, PASS_A_ONLY = 2, PASS_R_COLD = 3, PASS_FULL_DELTA = 4 };
 
 struct PassArgs {
     const float *S;
@@ -93,7 +102,14 @@ PassPlan plan_pass(int64_t n, int num_cus);
 PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds);
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);
 hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s);
-hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s);
+hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s,
+                             int msg_on = 0, float msg_tol = 0.0f);
+// flag |= 1 if any of the n x n entries of M (leading dimension ld) is NaN or
+// infinite; flag |= 1 likewise for the rows x cols entries of X (ldx).
+hipError_t launch_check_finite(const float *M, int64_t rows, int64_t cols, int64_t ld, int32_t *flag,
+                               hipStream_t s);
+// Raw decisions d_i = argmax_k a(i,k) + r(i,k), lowest k on ties.
+hipError_t launch_decide(const float *A, const float *R, int64_t n, int64_t ld, int32_t *dec, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f32_rows(float *p, int64_t rows, int64_t cols, int64_t ld, float v,
                                 hipStream_t s);
@@ -204,6 +220,7 @@ struct FinalArgs {
     int32_t *idx;       // labels out
     double *contrib;    // 2n scratch
     double *sums;       // [dpsim, expref]
+    const int32_t *raw; // nullable: raw decisions to use as the labels
 };
 hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
 
@@ -228,6 +245,8 @@ struct apx_ctx {
     std::string err;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    bool ws_external = false; // ws belongs to the caller (apx_set_workspace): never grown
+    int32_t *dflag = nullptr; // small device buffer of the context (finite checks)
     size_t ws_base = 0;       // start of the slice handed to the running solver
     void *pinned = nullptr;   // small pinned host buffer for state read-back
     // hipGraph replay of the iteration loop: one captured chunk of
@@ -279,6 +298,18 @@ struct BatchSpec {
     int32_t *idx;
 };
 size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus);
+// Workspace bytes of the other calls (apx_workspace_size).
+size_t similarity_ws_bytes(int64_t n);
+size_t pap_ws_bytes(int64_t n, int64_t ld, int32_t k, const int64_t *sizes, int num_cus);
+size_t lap_ws_bytes(int64_t n, int64_t d, int64_t L, int num_cus);
+size_t features_ws_bytes(int64_t n);
+size_t mlp_backward_ws_bytes(int64_t count);
+size_t warmstart_ws_bytes(int64_t n, int64_t ld, int num_cus);
+// APX_EINVAL (with a message) if any entry of the n x n matrix M is not
+// finite; synchronises the context stream.
+apx_status check_finite(apx_ctx *ctx, const float *M, int64_t n, int64_t ld, const char *name);
+// Validates apx_params (damping, counts, flags, msg_tol).
+apx_status check_params(apx_ctx *ctx, const apx_params *p);
 apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int32_t warm,
                          const apx_params *params, apx_result *res);
 // Single-instance solve on the workspace slice starting at ctx->ws_base.

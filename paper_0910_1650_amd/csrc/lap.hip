@@ -213,17 +213,62 @@ int64_t round64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
 }  // namespace
 
+namespace {
+
+// Workspace of lap_solve: [landmark tables, X_M, S_M, R_M, A_M, exemplars,
+// flags, distances] then the slice of the landmark similarity and solve.
+struct LapLayout {
+    size_t o_lm, o_xm, o_S, o_R, o_A, o_lab, o_ex, o_m, o_EX, o_flag, o_dist, o_sum, head, tail;
+};
+LapLayout lap_layout(int64_t n, int64_t d, int64_t L, int num_cus) {
+    const int64_t ldL = round64(L), ldm = d;
+    WsLayout W;
+    LapLayout o{};
+    o.o_lm = W.take(sizeof(int64_t) * L);
+    o.o_xm = W.take(sizeof(float) * L * ldm);
+    o.o_S = W.take(sizeof(float) * L * ldL);
+    o.o_R = W.take(sizeof(float) * L * ldL);
+    o.o_A = W.take(sizeof(float) * L * ldL);
+    o.o_lab = W.take(sizeof(int32_t) * L);
+    o.o_ex = W.take(sizeof(int64_t) * L);
+    o.o_m = W.take(sizeof(int32_t) * 4);
+    o.o_EX = W.take(sizeof(float) * L * ldm);
+    o.o_flag = W.take((size_t)n);
+    o.o_dist = W.take(sizeof(double) * n);
+    o.o_sum = W.take(sizeof(double) * 2);
+    o.head = W.off;
+    const size_t sim = similarity_ws_bytes(L), sol = solve_ws_bytes(L, ldL, num_cus);
+    o.tail = sim > sol ? sim : sol;
+    return o;
+}
+
+}  // namespace
+
+size_t apx::lap_ws_bytes(int64_t n, int64_t d, int64_t L, int num_cus) {
+    const LapLayout o = lap_layout(n, d, L, num_cus);
+    return o.head + o.tail;
+}
+
 extern "C" apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
                                 int64_t n_landmarks, const int64_t *landmarks, uint64_t seed,
-                                double noise_rel, const apx_params *params, int32_t *idx,
-                                apx_result *res, int64_t *exemplars_out) {
+                                double noise_rel, int32_t pref_mode, float pref_scalar,
+                                const apx_params *params, int32_t *idx, apx_result *res,
+                                int64_t *exemplars_out) {
     if (!ctx) return APX_EINVAL;
     if (!X || !idx || !res || !params) return set_err(ctx, APX_EINVAL, "null argument");
     if (n < 2 || d < 1 || ldx < d) return set_err(ctx, APX_EINVAL, "need n >= 2, d >= 1, ldx >= d");
     if (n_landmarks < 2 || n_landmarks > n) return set_err(ctx, APX_EINVAL, "need 2 <= n_landmarks <= n");
     if (d > 4096) return set_err(ctx, APX_ENOTIMPL, "d > 4096");
-    if (!(params->damping >= 0.0f && params->damping < 1.0f) || params->max_iter < 1 || params->conv_iter < 0)
-        return set_err(ctx, APX_EINVAL, "bad params");
+    {
+        const apx_status ps = check_params(ctx, params);
+        if (ps != APX_OK) return ps;
+    }
+    if (params->flags & APX_RAW_LABELS)
+        return set_err(ctx, APX_EINVAL, "APX_RAW_LABELS does not apply to lap_solve (labels are assignments)");
+    if (pref_mode != APX_PREF_MEDIAN && pref_mode != APX_PREF_SCALAR)
+        return set_err(ctx, APX_EINVAL, "lap_solve takes APX_PREF_MEDIAN or APX_PREF_SCALAR");
+    if (pref_mode == APX_PREF_SCALAR && !std::isfinite(pref_scalar))
+        return set_err(ctx, APX_EINVAL, "pref_scalar is not finite");
     const int64_t L = n_landmarks;
     std::vector<int64_t> lm(L);
     if (landmarks) {
@@ -253,23 +298,12 @@ extern "C" apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t
     hipStream_t s = ctx->stream;
 
     const int64_t ldL = round64(L), ldm = d;
-    WsLayout W;
-    const size_t o_lm = W.take(sizeof(int64_t) * L);
-    const size_t o_xm = W.take(sizeof(float) * L * ldm);
-    const size_t o_S = W.take(sizeof(float) * L * ldL);
-    const size_t o_R = W.take(sizeof(float) * L * ldL);
-    const size_t o_A = W.take(sizeof(float) * L * ldL);
-    const size_t o_lab = W.take(sizeof(int32_t) * L);
-    const size_t o_ex = W.take(sizeof(int64_t) * L);
-    const size_t o_m = W.take(sizeof(int32_t) * 4);
-    const size_t o_EX = W.take(sizeof(float) * L * ldm);
-    const size_t o_flag = W.take((size_t)n);
-    const size_t o_dist = W.take(sizeof(double) * n);
-    const size_t o_sum = W.take(sizeof(double) * 2);
-    const size_t head = W.off;
-    const size_t tail = solve_ws_bytes(L, ldL, ctx->num_cus) + sizeof(float) * L + (1 << 20);
+    const LapLayout LL = lap_layout(n, d, L, ctx->num_cus);
+    const size_t o_lm = LL.o_lm, o_xm = LL.o_xm, o_S = LL.o_S, o_R = LL.o_R, o_A = LL.o_A, o_lab = LL.o_lab,
+                 o_ex = LL.o_ex, o_m = LL.o_m, o_EX = LL.o_EX, o_flag = LL.o_flag, o_dist = LL.o_dist,
+                 o_sum = LL.o_sum, head = LL.head;
     ctx->ws_base = 0;
-    apx_status st = ws_reserve(ctx, head + tail);
+    apx_status st = ws_reserve(ctx, head + LL.tail);
     if (st != APX_OK) return st;
     char *b = static_cast<char *>(ctx->ws);
     int64_t *dlm = reinterpret_cast<int64_t *>(b + o_lm);
@@ -292,7 +326,7 @@ extern "C" apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t
     // Step 1: AP on the landmarks.
     ctx->ws_base = head;
     double pref = NAN;
-    st = ap_similarity(ctx, XM, L, d, ldm, SL, ldL, APX_PREF_MEDIAN, nullptr, 0.0f, seed, noise_rel, &pref);
+    st = ap_similarity(ctx, XM, L, d, ldm, SL, ldL, pref_mode, nullptr, pref_scalar, seed, noise_rel, &pref);
     if (st == APX_OK) st = ap_solve(ctx, SL, L, ldL, RL, AL, APX_COLD, params, lab, res);
     ctx->ws_base = 0;
     if (st != APX_OK) return st;

@@ -58,16 +58,85 @@ int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
         if (_e != hipSuccess) return hip_err(ctx, _e, what);  \
     } while (0)
 
-apx_status check_params(apx_ctx *ctx, const apx_params *p) {
-    if (!p) return set_err(ctx, APX_EINVAL, "params is null");
-    if (!(p->damping >= 0.0f && p->damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
-    if (p->max_iter < 1 || p->conv_iter < 0) return set_err(ctx, APX_EINVAL, "max_iter must be >= 1 and conv_iter >= 0");
-    return APX_OK;
-}
-
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
+
+namespace {
+
+// Workspace of pap_solve for parts of sizes nj: [tables | S_jj R_jj A_jj idx_jj]
+// followed by the batch solver's slice, or the full solve's from 0.
+struct PapLayout {
+    size_t o_perm, o_off, o_ptr, o_ld, o_rp, head, bbytes, fbytes;
+    std::vector<size_t> o_s, o_r, o_a, o_i;
+    std::vector<int64_t> ldj;
+    bool batch_sub;
+    size_t total() const { return head + bbytes > fbytes ? head + bbytes : fbytes; }
+};
+
+PapLayout pap_layout(int64_t n, int64_t ld, int32_t k, const std::vector<int64_t> &nj, int num_cus) {
+    PapLayout P;
+    WsLayout L;
+    P.o_perm = L.take(sizeof(int64_t) * n);
+    P.o_off = L.take(sizeof(int64_t) * (k + 1));
+    P.o_ptr = L.take(sizeof(float *) * k);
+    P.o_ld = L.take(sizeof(int64_t) * k);
+    P.o_rp = L.take(sizeof(int32_t) * n);
+    P.o_s.resize(k);
+    P.o_r.resize(k);
+    P.o_a.resize(k);
+    P.o_i.resize(k);
+    P.ldj.resize(k);
+    for (int j = 0; j < k; ++j) {
+        P.ldj[j] = round4(nj[j]);
+        P.o_s[j] = L.take(sizeof(float) * nj[j] * P.ldj[j]);
+        P.o_r[j] = L.take(sizeof(float) * nj[j] * P.ldj[j]);
+        P.o_a[j] = L.take(sizeof(float) * nj[j] * P.ldj[j]);
+        P.o_i[j] = L.take(sizeof(int32_t) * nj[j]);
+    }
+    P.head = L.off;
+    std::vector<BatchSpec> spec(k);
+    P.batch_sub = true;
+    for (int j = 0; j < k; ++j) {
+        spec[j] = BatchSpec{nj[j], P.ldj[j], nullptr, nullptr, nullptr, nullptr};
+        P.batch_sub = P.batch_sub && nj[j] >= 2;
+    }
+    if (P.batch_sub) {
+        P.bbytes = batched_ws_bytes(k, spec.data(), num_cus);
+    } else {
+        // parts solved one at a time: the largest part's slice
+        P.bbytes = 0;
+        for (int j = 0; j < k; ++j)
+            if (nj[j] >= 2) {
+                const size_t b = batched_ws_bytes(1, &spec[j], num_cus);
+                P.bbytes = b > P.bbytes ? b : P.bbytes;
+            }
+    }
+    P.fbytes = solve_ws_bytes(n, ld, num_cus);
+    return P;
+}
+
+std::vector<int64_t> even_sizes(int64_t n, int32_t k) {
+    const int64_t m = n / k;
+    std::vector<int64_t> nj(k, m);
+    nj[k - 1] = n - m * (k - 1);
+    return nj;
+}
+
+}  // namespace
+
+namespace apx {
+size_t pap_ws_bytes(int64_t n, int64_t ld, int32_t k, const int64_t *sizes, int num_cus) {
+    std::vector<int64_t> nj = sizes ? std::vector<int64_t>(sizes, sizes + k) : even_sizes(n, k);
+    int64_t tot = 0;
+    for (int j = 0; j < k; ++j) {
+        if (nj[j] < 1) return 0;
+        tot += nj[j];
+    }
+    if (tot != n) return 0;
+    return pap_layout(n, ld, k, nj, num_cus).total();
+}
+}  // namespace apx
 
 extern "C" apx_status ap_solve_batched(apx_ctx *ctx, int32_t count, const apx_instance *inst,
                                        int32_t warm, const apx_params *params, apx_result *res) {
@@ -76,6 +145,8 @@ extern "C" apx_status ap_solve_batched(apx_ctx *ctx, int32_t count, const apx_in
     apx_status st = check_params(ctx, params);
     if (st != APX_OK) return st;
     if (warm < APX_COLD || warm > APX_WARM_AR) return set_err(ctx, APX_EINVAL, "bad warm mode %d", warm);
+    if (params->flags & (APX_RAW_LABELS | APX_MSG_THRESHOLD))
+        return set_err(ctx, APX_ENOTIMPL, "ap_solve_batched supports only the APX_CHECK_FINITE flag");
     std::vector<BatchSpec> spec(count);
     for (int j = 0; j < count; ++j) {
         const apx_instance &I = inst[j];
@@ -89,6 +160,11 @@ extern "C" apx_status ap_solve_batched(apx_ctx *ctx, int32_t count, const apx_in
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (cur != ctx->device) (void)hipSetDevice(ctx->device);
+    if (params->flags & APX_CHECK_FINITE)
+        for (int j = 0; j < count; ++j) {
+            st = check_finite(ctx, spec[j].S, spec[j].n, spec[j].ld, "an instance's S");
+            if (st != APX_OK) return st;
+        }
     ctx->ws_base = 0;
     return batched_solve(ctx, count, spec.data(), warm, params, res);
 }
@@ -104,6 +180,7 @@ extern "C" apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t
     if (k < 1 || k > n) return set_err(ctx, APX_EINVAL, "need 1 <= k <= n");
     apx_status st = check_params(ctx, params);
     if (st != APX_OK) return st;
+    const apx_params *const orig_params = params;
 
     // Step 1: the partition (the paper's even split unless given).
     std::vector<int64_t> off(k + 1), pm(n);
@@ -131,35 +208,24 @@ extern "C" apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t
     (void)hipGetDevice(&cur);
     if (cur != ctx->device) (void)hipSetDevice(ctx->device);
     hipStream_t s = ctx->stream;
+    if (params->flags & APX_CHECK_FINITE) {
+        st = check_finite(ctx, S, n, ld, "S");
+        if (st != APX_OK) return st;
+    }
 
     // Workspace: [tables | S_jj | R_jj | A_jj | idx_jj] then the batch solver's slice;
     // the final full solve reuses the workspace from 0.
-    WsLayout L;
-    const size_t o_perm = L.take(sizeof(int64_t) * n);
-    const size_t o_off = L.take(sizeof(int64_t) * (k + 1));
-    const size_t o_ptr = L.take(sizeof(float *) * k);
-    const size_t o_ld = L.take(sizeof(int64_t) * k);
-    const size_t o_rp = L.take(sizeof(int32_t) * n);
-    std::vector<size_t> o_s(k), o_r(k), o_a(k), o_i(k);
-    std::vector<int64_t> nj(k), ldj(k);
-    for (int j = 0; j < k; ++j) {
-        nj[j] = off[j + 1] - off[j];
-        ldj[j] = round4(nj[j]);
-        o_s[j] = L.take(sizeof(float) * nj[j] * ldj[j]);
-        o_r[j] = L.take(sizeof(float) * nj[j] * ldj[j]);
-        o_a[j] = L.take(sizeof(float) * nj[j] * ldj[j]);
-        o_i[j] = L.take(sizeof(int32_t) * nj[j]);
-    }
-    const size_t head = L.off;
-    // sizes of the batch solve and of the full solve
+    std::vector<int64_t> nj(k);
+    for (int j = 0; j < k; ++j) nj[j] = off[j + 1] - off[j];
+    const PapLayout P = pap_layout(n, ld, k, nj, ctx->num_cus);
+    const size_t o_perm = P.o_perm, o_off = P.o_off, o_ptr = P.o_ptr, o_ld = P.o_ld, o_rp = P.o_rp;
+    const size_t head = P.head;
+    const std::vector<size_t> &o_s = P.o_s, &o_r = P.o_r, &o_a = P.o_a, &o_i = P.o_i;
+    const std::vector<int64_t> &ldj = P.ldj;
+    const bool batch_sub = P.batch_sub;
     std::vector<BatchSpec> spec(k);
-    for (int j = 0; j < k; ++j) spec[j] = BatchSpec{nj[j], ldj[j], nullptr, nullptr, nullptr, nullptr};
-    bool batch_sub = true;
-    for (int j = 0; j < k; ++j) batch_sub = batch_sub && nj[j] >= 2;
-    const size_t bbytes = batch_sub ? batched_ws_bytes(k, spec.data(), ctx->num_cus) : 0;
-    const size_t fbytes = solve_ws_bytes(n, ld, ctx->num_cus);
     ctx->ws_base = 0;
-    st = ws_reserve(ctx, head + bbytes > fbytes ? head + bbytes : fbytes);
+    st = ws_reserve(ctx, P.total());
     if (st != APX_OK) return st;
     char *b = static_cast<char *>(ctx->ws);
 
@@ -181,8 +247,12 @@ extern "C" apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t
     k_pap_gather<<<(unsigned)n, 256, 0, s>>>(g, rp);
     HIP_TRY(hipGetLastError(), "gather");
 
-    // Step 2: AP on every block, all blocks in one batch.
+    // Step 2: AP on every block, all blocks in one batch (the flags apply to
+    // Step 4 only; S was checked above).
     std::vector<apx_result> subres(k);
+    apx_params sp = *params;
+    sp.flags = 0;
+    params = &sp;
     if (batch_sub) {
         for (int j = 0; j < k; ++j)
             spec[j] = BatchSpec{nj[j], ldj[j], subp[j], reinterpret_cast<float *>(b + o_r[j]),
@@ -220,5 +290,7 @@ extern "C" apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t
     HIP_TRY(hipStreamSynchronize(s), "sync");
 
     // Step 4: AP on the whole S from A' (R_0 = 0).
-    return ap_solve(ctx, S, n, ld, R, A, APX_WARM_A, params, idx, res);
+    apx_params fp = *orig_params;
+    fp.flags &= ~(uint32_t)APX_CHECK_FINITE;
+    return ap_solve(ctx, S, n, ld, R, A, APX_WARM_A, &fp, idx, res);
 }

@@ -437,6 +437,25 @@ using namespace apx;
         if (_e != hipSuccess) return hip_err(ctx, _e, what);  \
     } while (0)
 
+namespace {
+struct SimLayout {
+    size_t o_n, o_mm, o_sel, o_h, o_r, bytes;
+};
+SimLayout sim_layout(int64_t n) {
+    WsLayout L;
+    SimLayout o{};
+    o.o_n = L.take(sizeof(float) * (size_t)n);
+    o.o_mm = L.take(sizeof(uint32_t) * 2);
+    o.o_sel = L.take(sizeof(SelState));
+    o.o_h = L.take(sizeof(unsigned long long) * 2 * SEL_BINS);
+    o.o_r = L.take(sizeof(double) * 2);
+    o.bytes = L.off;
+    return o;
+}
+}  // namespace
+
+size_t apx::similarity_ws_bytes(int64_t n) { return sim_layout(n).bytes; }
+
 extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
                                     float *S, int64_t ld, int32_t pref_mode, const float *pref_vec,
                                     float pref_scalar, uint64_t noise_seed, double noise_rel,
@@ -459,14 +478,19 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     if (cur != ctx->device) (void)hipSetDevice(ctx->device);
     hipStream_t s = ctx->stream;
 
-    WsLayout L;
-    size_t o_n = L.take(sizeof(float) * (size_t)n);
-    size_t o_mm = L.take(sizeof(uint32_t) * 2);
-    size_t o_sel = L.take(sizeof(SelState));
-    size_t o_h = L.take(sizeof(unsigned long long) * 2 * SEL_BINS);
-    size_t o_r = L.take(sizeof(double) * 2);
-    apx_status st = ws_reserve(ctx, ctx->ws_base + L.off);
+    const SimLayout SL = sim_layout(n);
+    const size_t o_n = SL.o_n, o_mm = SL.o_mm, o_sel = SL.o_sel, o_h = SL.o_h, o_r = SL.o_r;
+    apx_status st = ws_reserve(ctx, ctx->ws_base + SL.bytes);
     if (st != APX_OK) return st;
+
+    // Non-finite input is rejected before S is written.
+    int32_t *hflag = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 2048);
+    HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(ctx->dflag), sizeof(int32_t), 0, s), "finite check");
+    HIP_TRY(launch_check_finite(X, n, d, ldx, ctx->dflag, s), "finite check");
+    if (pref_mode == APX_PREF_VECTOR) HIP_TRY(launch_check_finite(pref_vec, 1, n, n, ctx->dflag, s), "finite check");
+    HIP_TRY(hipMemcpyAsync(hflag, ctx->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "finite check");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (*hflag) return set_err(ctx, APX_EINVAL, "X or pref_vec holds a NaN or infinite value");
     char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
     float *nrm = reinterpret_cast<float *>(b + o_n);
     uint32_t *mm = reinterpret_cast<uint32_t *>(b + o_mm);
@@ -501,11 +525,16 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     const int g = (int)(n < 8192 ? n : 8192);
     k_pref_noise<<<g, 256, 0, s>>>(pa, &dvals[0]);
     HIP_TRY(hipGetLastError(), "preference/noise");
-    if (pref_out) {
-        double *h = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 1024);
-        HIP_TRY(hipMemcpyAsync(h, &dvals[1], sizeof(double), hipMemcpyDeviceToHost, s), "pref copy");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        *pref_out = pref_mode == APX_PREF_VECTOR ? NAN : *h;
-    }
+    // The bounds of the off-diagonal keys tell whether a similarity overflowed
+    // (a key at or beyond the one of +inf or -inf: infinities and NaNs).
+    double *h = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 1024);
+    uint32_t *hk = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->pinned) + 1088);
+    HIP_TRY(hipMemcpyAsync(h, &dvals[1], sizeof(double), hipMemcpyDeviceToHost, s), "pref copy");
+    HIP_TRY(hipMemcpyAsync(hk, mm, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "bounds copy");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    const uint32_t key_pinf = 0xff800000u, key_ninf = 0x007fffffu;   // fkey(+inf), fkey(-inf)
+    if (hk[1] >= key_pinf || hk[0] <= key_ninf)
+        return set_err(ctx, APX_EINVAL, "similarities overflow FP32 (S holds non-finite values)");
+    if (pref_out) *pref_out = pref_mode == APX_PREF_VECTOR ? NAN : *h;
     return APX_OK;
 }

@@ -700,7 +700,51 @@ apx_status run_forward(apx_ctx *ctx, const FwdArgs &fa, bool stash) {
 
 int64_t round64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
+struct BwdLayout {
+    size_t o_y, o_z1, o_z2, o_h1, o_h2, o_gp, o_lp, bytes;
+};
+BwdLayout bwd_layout(int64_t count) {
+    const int64_t nblk = (count + BW_P - 1) / BW_P;
+    WsLayout W;
+    BwdLayout o{};
+    o.o_y = W.take(sizeof(float) * NO * (size_t)count);
+    o.o_z1 = W.take(sizeof(float) * NH * (size_t)count);
+    o.o_z2 = W.take(sizeof(float) * NH * (size_t)count);
+    o.o_h1 = W.take(sizeof(uint16_t) * NH * (size_t)count);
+    o.o_h2 = W.take(sizeof(uint16_t) * NH * (size_t)count);
+    o.o_gp = W.take(sizeof(float) * NPARAM * (size_t)nblk);
+    o.o_lp = W.take(sizeof(double) * (size_t)nblk);
+    o.bytes = W.off;
+    return o;
+}
+
+struct WarmLayout {
+    size_t o_st, o_f, o_y, o_s, head;
+};
+WarmLayout warm_layout(int64_t n) {
+    WsLayout W;
+    WarmLayout o{};
+    o.o_st = W.take(sizeof(RowStats) * (size_t)n);
+    o.o_f = W.take(sizeof(float) * NF * (size_t)n);
+    o.o_y = W.take(sizeof(float) * NO * (size_t)n);
+    o.o_s = W.take(sizeof(float) * 4);
+    o.head = W.off;
+    return o;
+}
+
 }  // namespace
+
+namespace apx {
+size_t features_ws_bytes(int64_t n) {
+    WsLayout W;
+    W.take(sizeof(RowStats) * (size_t)n);
+    return W.off;
+}
+size_t mlp_backward_ws_bytes(int64_t count) { return bwd_layout(count).bytes; }
+size_t warmstart_ws_bytes(int64_t n, int64_t ld, int num_cus) {
+    return warm_layout(n).head + resp_step_ws_bytes(n, ld, num_cus);
+}
+}  // namespace apx
 
 extern "C" {
 
@@ -741,15 +785,10 @@ apx_status apx_mlp_backward(apx_ctx *ctx, const float *theta, const float *F, co
     if (count < 1) return set_err(ctx, APX_EINVAL, "count must be >= 1");
     DevGuard g(ctx->device);
     const int64_t nblk = (count + BW_P - 1) / BW_P;
-    WsLayout W;
-    const size_t o_y = W.take(sizeof(float) * NO * (size_t)count);
-    const size_t o_z1 = W.take(sizeof(float) * NH * (size_t)count);
-    const size_t o_z2 = W.take(sizeof(float) * NH * (size_t)count);
-    const size_t o_h1 = W.take(sizeof(uint16_t) * NH * (size_t)count);
-    const size_t o_h2 = W.take(sizeof(uint16_t) * NH * (size_t)count);
-    const size_t o_gp = W.take(sizeof(float) * NPARAM * (size_t)nblk);
-    const size_t o_lp = W.take(sizeof(double) * (size_t)nblk);
-    APX_TRY(ws_reserve(ctx, ctx->ws_base + W.off));
+    const BwdLayout BL = bwd_layout(count);
+    const size_t o_y = BL.o_y, o_z1 = BL.o_z1, o_z2 = BL.o_z2, o_h1 = BL.o_h1, o_h2 = BL.o_h2, o_gp = BL.o_gp,
+                 o_lp = BL.o_lp;
+    APX_TRY(ws_reserve(ctx, ctx->ws_base + BL.bytes));
     char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
     FwdArgs fa{};
     fa.theta = theta;
@@ -835,12 +874,8 @@ apx_status ap_warmstart(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, con
     APX_TRY(check_sq(ctx, A, "A", n, ld));
     if (!theta) return set_err(ctx, APX_EINVAL, "theta is null");
     DevGuard g(ctx->device);
-    WsLayout W;
-    const size_t o_st = W.take(sizeof(RowStats) * (size_t)n);
-    const size_t o_f = W.take(sizeof(float) * NF * (size_t)n);
-    const size_t o_y = W.take(sizeof(float) * NO * (size_t)n);
-    const size_t o_s = W.take(sizeof(float) * 4);
-    const size_t head = W.off;
+    const WarmLayout WL = warm_layout(n);
+    const size_t o_st = WL.o_st, o_f = WL.o_f, o_y = WL.o_y, o_s = WL.o_s, head = WL.head;
     const size_t base = ctx->ws_base;
     APX_TRY(ws_reserve(ctx, base + head + resp_step_ws_bytes(n, ld, ctx->num_cus)));
     char *b = static_cast<char *>(ctx->ws) + base;

@@ -2,9 +2,9 @@
 
 Runs only the CPU oracle (Algorithm 1 to convergence from A=0, R=0) on the
 seeded synthetic inputs and stores, per workload, the exemplar set E, the
-iteration at which the stop rule fired, the preference and the net
-similarity.  The GPU runs (cold start and the warm starts) are judged
-against these sets.
+labels (Algorithm 1's idx), the iteration at which the stop rule fired, the
+preference and the net similarity.  The GPU runs (cold start and the warm
+starts) are judged against these.
 
     python tests/golden/make_oracle_exemplars.py [name ...]
 """
@@ -51,15 +51,24 @@ def run(name):
         "converged": bool(res.converged),
         "n_exemplars": int(res.n_exemplars),
         "exemplars": [int(e) for e in res.exemplars],
+        "labels": [int(v) for v in res.idx],
         "netsim": res.netsim,
         "dpsim": res.dpsim,
         "expref": res.expref,
         "oracle_threads": oracle.num_threads(),
         "seconds": {"setup": round(t1 - t0, 1), "ap": round(t2 - t1, 1)},
     }
+    labels = out.pop("labels")
     with open(os.path.join(HERE, name + ".json"), "w") as f:
         json.dump(out, f, indent=1)
-        f.write("\n")
+        f.write(',\n')
+    # the labels on one line, appended as the last key
+    with open(os.path.join(HERE, name + ".json"), "r+") as f:
+        body = f.read().rstrip().rstrip(",").rstrip()
+        assert body.endswith("}")
+        f.seek(0)
+        f.write(body[:-1].rstrip() + ',\n "labels": ' + json.dumps(labels, separators=(",", ":")) + "\n}\n")
+        f.truncate()
     print(name, out["iterations"], out["n_exemplars"], out["netsim"], out["seconds"], flush=True)
     del prep, res
     np.zeros(1)
