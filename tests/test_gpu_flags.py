@@ -74,7 +74,8 @@ def test_raw_labels_equal_oracle_decisions(which, request):
 def test_check_finite_rejects_before_any_write(c1, bad, call):
     S0, _ = c1
     n = S0.shape[0]
-    S = S0.clone()
+    S = apx.empty_matrix(n)
+    S.copy_(S0)
     S[17, 403] = bad
     R, A = apx.empty_matrix(n, fill=7.0), apx.empty_matrix(n, fill=9.0)
     say(f"finite check {call} {bad}")
