@@ -285,6 +285,21 @@ apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float
                       float damping, int32_t n_iter, int32_t *decision);
 
 /*
+ * ap_iterate_noalloc -- ap_iterate for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels, launch plan and results (bit for
+ * bit), with the column vectors and partials in a fixed scratch array
+ * compiled into the library (12 MiB per GPU, held until the process ends)
+ * instead of the context workspace.  It calls no allocating routine.
+ * Serves 2 <= n <= 8192; larger n gives APX_EINVAL.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other contexts or threads) race and give undefined results;
+ * calls ordered on one stream are safe.  Asynchronous.
+ */
+apx_status ap_iterate_noalloc(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                              float damping, int32_t n_iter, int32_t *decision);
+
+/*
  * ap_solve -- Algorithm 1 to its stop rule.  S holds the similarities with
  * the preferences on the diagonal.  warm selects the start (APX_COLD,
  * APX_WARM_A, APX_WARM_AR).  On exit R and A hold the messages of the stop

@@ -84,6 +84,7 @@ SIGNATURES = {
     "ap_similarity": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _I32, _P, ctypes.c_float,
                                      ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "ap_iterate": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, ctypes.c_float, _I32, _P]),
+    "ap_iterate_noalloc": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, ctypes.c_float, _I32, _P]),
     "ap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, ctypes.POINTER(apx_params), _P,
                                 ctypes.POINTER(apx_result)]),
     "ap_solve_batched": (ctypes.c_int, [_P, _I32, ctypes.POINTER(apx_instance), _I32,
@@ -232,6 +233,24 @@ def ap_iterate(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float
         dp = _P(decision.data_ptr())
     ctx = context(S.device)
     _check(ctx, lib().ap_iterate(ctx, Sp, n, ld, Rp, Ap, damping, n_iter, dp), "ap_iterate")
+
+
+def ap_iterate_noalloc(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float, n_iter: int,
+                       decision: torch.Tensor | None = None) -> None:
+    """ap_iterate on the library's fixed scratch array (no device allocation;
+    n <= 8192; calls overlapping on one GPU race)."""
+    Sp, n, ld = _mat(S, "S")
+    Rp, _, ldr = _mat(R, "R", n)
+    Ap, _, lda = _mat(A, "A", n)
+    if not (ld == ldr == lda):
+        raise ValueError("S, R and A must share one leading dimension")
+    dp = None
+    if decision is not None:
+        if not (decision.is_cuda and decision.dtype == torch.int32 and decision.numel() == n):
+            raise ValueError("decision must be an int32 CUDA tensor of n entries")
+        dp = _P(decision.data_ptr())
+    ctx = context(S.device)
+    _check(ctx, lib().ap_iterate_noalloc(ctx, Sp, n, ld, Rp, Ap, damping, n_iter, dp), "ap_iterate_noalloc")
 
 
 def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float = 0.5,

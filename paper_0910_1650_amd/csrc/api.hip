@@ -348,6 +348,45 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
 }  // namespace
 
 namespace apx {
+apx_status check_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, const float *R, const float *A,
+                         float damping, int32_t n_iter) {
+    if (!ctx) return APX_EINVAL;
+    if (n < 2) return set_err(ctx, APX_EINVAL, "ap_iterate needs n >= 2 (n = %lld)", (long long)n);
+    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
+    APX_TRY(check_matrix(ctx, S, "S", n, ld));
+    APX_TRY(check_matrix(ctx, R, "R", n, ld));
+    APX_TRY(check_matrix(ctx, A, "A", n, ld));
+    if (!(damping >= 0.0f && damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
+    if (n_iter < 1) return set_err(ctx, APX_EINVAL, "n_iter must be >= 1");
+    return APX_OK;
+}
+
+hipError_t iterate_passes(const PassPlan &pl, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                          float lam, int32_t n_iter, int32_t *decision, float *tcol, float *ccol, float *rdiag,
+                          float *partial, hipStream_t s) {
+    IterWs w{};
+    w.tcol = tcol;
+    w.ccol = ccol;
+    w.rdiag = rdiag;
+    w.partial = partial;
+    w.ldp = round4(n);
+    w.nparts = pl.grid;
+    // R_{t+1} from (R_t, S, A_t), in place, with its column vectors.
+    PassArgs pa = pass_args(S, R, R, A, n, ld, lam, w, nullptr, nullptr, nullptr);
+    hipError_t e = launch_row_pass(pl, PASS_R_ONLY, pa, s);
+    if (e == hipSuccess) e = launch_col_reduce(col_args(w, n, nullptr, 0), s);
+    for (int32_t it = 1; it < n_iter && e == hipSuccess; ++it) {
+        PassArgs pf = pass_args(S, R, R, A, n, ld, lam, w, nullptr, nullptr, nullptr);
+        e = launch_row_pass(pl, PASS_FULL, pf, s);
+        if (e == hipSuccess) e = launch_col_reduce(col_args(w, n, nullptr, 0), s);
+    }
+    if (e == hipSuccess) {
+        PassArgs pe = pass_args(S, R, R, A, n, ld, lam, w, decision, nullptr, nullptr);
+        e = launch_row_pass(pl, PASS_A_ONLY, pe, s);
+    }
+    return e;
+}
+
 size_t solve_ws_bytes(int64_t n, int64_t ld, int num_cus) {
     const PassPlan pl = plan_pass(n, num_cus);
     return iter_layout(n, ld, true, pl.grid).bytes;
@@ -396,6 +435,8 @@ apx_status apx_create(apx_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return APX_ENOMEM;
     }
+    // this device's fixed scratch array (ap_iterate_noalloc reports its absence)
+    (void)noalloc_init(ctx);
     const char *gv = getenv("APX_GRAPHS");
     if (gv && gv[0] == '0') ctx->graphs = false;
     const char *iv = getenv("APX_IMPLICIT_K");
@@ -545,31 +586,15 @@ apx_status apx_profile_read(apx_ctx *ctx, int64_t *launches, double *total_ms) {
 
 apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
                       float damping, int32_t n_iter, int32_t *decision) {
-    if (!ctx) return APX_EINVAL;
-    if (n < 2) return set_err(ctx, APX_EINVAL, "ap_iterate needs n >= 2 (n = %lld)", (long long)n);
-    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
-    APX_TRY(check_matrix(ctx, S, "S", n, ld));
-    APX_TRY(check_matrix(ctx, R, "R", n, ld));
-    APX_TRY(check_matrix(ctx, A, "A", n, ld));
-    if (!(damping >= 0.0f && damping < 1.0f)) return set_err(ctx, APX_EINVAL, "damping must be in [0,1)");
-    if (n_iter < 1) return set_err(ctx, APX_EINVAL, "n_iter must be >= 1");
+    APX_TRY(check_iterate(ctx, S, n, ld, R, A, damping, n_iter));
     DevGuard g(ctx->device);
     PassPlan pl{};
     APX_TRY(ctx_plan(ctx, n, &pl, nullptr));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, false, pl, w));
-    hipStream_t s = ctx->stream;
-    // R_{t+1} from (R_t, S, A_t), in place, with its column vectors.
-    PassArgs pa = pass_args(S, R, R, A, n, ld, damping, w, nullptr, nullptr, nullptr);
-    HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pa, s), "row pass (R)");
-    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
-    for (int32_t it = 1; it < n_iter; ++it) {
-        PassArgs pf = pass_args(S, R, R, A, n, ld, damping, w, nullptr, nullptr, nullptr);
-        HIP_TRY(launch_row_pass(pl, PASS_FULL, pf, s), "row pass");
-        HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0), s), "column reduce");
-    }
-    PassArgs pe = pass_args(S, R, R, A, n, ld, damping, w, decision, nullptr, nullptr);
-    HIP_TRY(launch_row_pass(pl, PASS_A_ONLY, pe, s), "row pass (A)");
+    HIP_TRY(iterate_passes(pl, S, n, ld, R, A, damping, n_iter, decision, w.tcol, w.ccol, w.rdiag, w.partial,
+                           ctx->stream),
+            "ap_iterate passes");
     return APX_OK;
 }
 

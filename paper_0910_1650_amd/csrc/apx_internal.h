@@ -247,6 +247,7 @@ struct apx_ctx {
     size_t ws_bytes = 0;
     bool ws_external = false; // ws belongs to the caller (apx_set_workspace): never grown
     int32_t *dflag = nullptr; // small device buffer of the context (finite checks)
+    void *scratch = nullptr;  // this device's fixed scratch array (ap_iterate_noalloc)
     size_t ws_base = 0;       // start of the slice handed to the running solver
     void *pinned = nullptr;   // small pinned host buffer for state read-back
     // hipGraph replay of the iteration loop: one captured chunk of
@@ -323,7 +324,17 @@ apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
 // Row-pass plan for n on this context: the default plan with the tuned
 // workgroup size and variant applied (tuning first if enabled and unseen);
 // *check_every (nullable) receives the tuned poll interval or 0.
-apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every);
+apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune = true);
+// ap_iterate's argument checks, and its launches (column vectors t, c,
+// r(k,k) and the partials [pl.grid][round4(n)] in caller-given memory).
+apx_status check_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, const float *R, const float *A,
+                         float damping, int32_t n_iter);
+hipError_t iterate_passes(const PassPlan &pl, const float *S, int64_t n, int64_t ld, float *R, float *A,
+                          float lam, int32_t n_iter, int32_t *decision, float *tcol, float *ccol, float *rdiag,
+                          float *partial, hipStream_t s);
+// Looks up this device's copy of the fixed scratch array of
+// ap_iterate_noalloc (noalloc.hip); called by apx_create with the device current.
+apx_status noalloc_init(apx_ctx *ctx);
 apx_status hip_err(apx_ctx *ctx, hipError_t e, const char *what);
 
 }  // namespace apx

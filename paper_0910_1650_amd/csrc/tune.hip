@@ -196,12 +196,12 @@ struct DevGuard {
 
 namespace apx {
 
-apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every) {
+apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune) {
     *pl = plan_pass(n, ctx->num_cus);
     if (check_every) *check_every = 0;
     TuneEntry *e = find_entry(ctx, n);
     // the tuner allocates a scratch problem: never with a caller-set workspace
-    if (!e && ctx->autotune && !ctx->ws_external) {
+    if (!e && may_tune && ctx->autotune && !ctx->ws_external) {
         TuneEntry t{};
         const apx_status st = measure(ctx, n, &t);
         if (st != APX_OK) return st;
