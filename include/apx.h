@@ -123,11 +123,11 @@ apx_status apx_set_workspace(apx_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* apx_set_implicit -- list capacity of the implicit responsibilities used by
  * ap_solve when R_0 = 0 (APX_COLD, APX_WARM_A): unrolling the damped Eq. (2)
- * gives R_t(i,k) = (1 - lambda^t) s(i,k) - beta_t(i) + gamma_t(i,k), where
- * gamma_t(i,.) is non-zero only on the columns that were row i's argmax of
- * a+s at an earlier iteration; each row keeps beta and up to list_capacity
- * (column, gamma) pairs, so an iteration reads S and A and writes A
- * (12 bytes per matrix element instead of 20).  When a row needs more
+ * gives R_t(i,k) = (1 - lambda^t) s(i,k) - beta_t(i) on every column k that
+ * was never row i's argmax of a+s; each row keeps beta and, for up to
+ * list_capacity columns that were, (column, r_t(i,k)) pairs updated by the
+ * damped Eq. (2), so an iteration reads S and A and writes A (12 bytes per
+ * matrix element instead of 20).  When a row needs more
  * entries, R is made explicit and the run continues with explicit R.
  * 0 = always explicit R; default 16 (the maximum); the environment variable
  * APX_IMPLICIT_K sets it at context creation.  Only problems with

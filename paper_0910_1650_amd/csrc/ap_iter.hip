@@ -863,11 +863,12 @@ hipError_t launch_t(int mode, const PassArgs &a, const PassPlan &pl, hipStream_t
 
 
 // ---- implicit responsibilities ---------------------------------------------
-// R_t(i,k) = alpha_t s(i,k) - beta_t(i) + gamma_t(i,k), see ImpArgs.  A pass
-// reads S and A and writes A (12 bytes per element instead of 20); R is
-// rebuilt in registers from the row's state.  alpha_t, alpha_{t+1} are read
-// from the run state, so the partials formed for R_{t+1} in pass t and the
-// values pass t+1 rebuilds use the same numbers.
+// R_t(i,k) = alpha_t s(i,k) - beta_t(i) off the row's list, and the stored
+// value r_t(i,k) (updated by the explicit damped Eq. (2)) on it; see
+// ImpArgs.  A pass reads S and A and writes A (12 bytes per element instead
+// of 20); R is rebuilt in registers from the row's state.  alpha_t,
+// alpha_{t+1} are read from the run state, so the partials formed for
+// R_{t+1} in pass t and the values pass t+1 rebuilds use the same numbers.
 
 template <int T, int J, int KIND, bool PREF>
 __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
@@ -978,7 +979,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
         float *Arow = p.A + i * ld;
         const rsrc_t a_rs = row_rsrc(Arow, ld);
         // state of R_t for this row; the listed columns this thread owns go
-        // to registers (local index 4*chunk + element, gamma, list slot)
+        // to registers (local index 4*chunk + element, stored r_t, list slot)
         const float beta = st_beta[sl];
         const int cnt = st_cnt[sl];
         uint32_t next_state = 0u;
@@ -1030,7 +1031,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) f4set(r, e, f4get(r, e) + own_g[o]);
+                        if (own_le[o] == 4 * j + e) f4set(r, e, own_g[o]);
             }
             if constexpr (DO_A) {
                 const float4 tv = ld4(p.tcol + c);
@@ -1088,10 +1089,14 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             }
         }
 
-        // State of R_{t+1}: beta' = lam beta + (1-lam) v1; every gamma decays
-        // by lam and column k1 gains d = (1-lam)(v1 - v2).
+        // State of R_{t+1}: beta' = lam beta + (1-lam) v1 for the columns off
+        // the list; on it (and for k1, which joins it) the damped Eq. (2),
+        // r' = (lam r + (1-lam) s) - (1-lam) (k = k1 ? v2 : v1), in the
+        // explicit pass's rounding.  Keeping r itself on the list, not an
+        // offset from alpha s - beta, avoids the cancellation of two large
+        // terms in rows whose argmax column has a large availability.
         const int k1 = t2.k1;
-        const float d = oml * (t2.v1 - t2.v2);
+        const float m_other = oml * t2.v1, m_self = oml * t2.v2;
         const float beta1 = lam * beta + oml * t2.v1;
         // A new column k1 overflows the row when the list is full or when the
         // thread owning k1 already keeps NOWN listed columns (every thread
@@ -1110,20 +1115,17 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
                 cnt_out[ii] = -1;
                 atomicOr(&p.st->imp_abort, 1);
             } else {
-                for (int qq = 0; qq < cnt; ++qq) {
-                    col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
-                    gam_out[(int64_t)ii * IMP_K + qq] = lam * st_gam[sl][qq] + (qq == pos1 ? d : 0.0f);
-                }
-                if (pos1 < 0) {
-                    col_out[(int64_t)ii * IMP_K + cnt] = k1;
-                    gam_out[(int64_t)ii * IMP_K + cnt] = d;
-                }
+                for (int qq = 0; qq < cnt; ++qq) col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
+                if (pos1 < 0) col_out[(int64_t)ii * IMP_K + cnt] = k1;
                 cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
             }
         }
-        float own_g1[NOWN];
+        // r_{t+1} of the listed columns (and of k1 when it joins), formed by
+        // their owners in the loop below and stored in the new list
+        float own_r1[NOWN];
 #pragma unroll
-        for (int o = 0; o < NOWN; ++o) own_g1[o] = lam * own_g[o] + (own_q[o] == pos1 ? d : 0.0f);
+        for (int o = 0; o < NOWN; ++o) own_r1[o] = 0.0f;
+        float k1_r1 = 0.0f;
         const bool k1_mine = pos1 < 0 && k1_owner == tid;
         const int k1_le = ((k1 >> 2) / T) * 4 + (k1 & 3);
         const bool wave_k1 = __any(k1_mine);
@@ -1146,14 +1148,22 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             if (wave_k1) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (k1_mine && k1_le == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + d);
+                    if (k1_mine && k1_le == 4 * j + e) {
+                        // r_t = alpha_t s - beta (k1 was off the list)
+                        const float s = f4get(sv, e);
+                        k1_r1 = (lam * (al * s - beta) + oml * s) - m_self;
+                        f4set(rv4, e, k1_r1);
+                    }
             }
             if (wave_own) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) f4set(rv4, e, f4get(rv4, e) + own_g1[o]);
+                        if (own_le[o] == 4 * j + e) {
+                            own_r1[o] = (lam * own_g[o] + oml * f4get(sv, e)) - (own_q[o] == pos1 ? m_self : m_other);
+                            f4set(rv4, e, own_r1[o]);
+                        }
             }
             float4 pos;
 #pragma unroll
@@ -1171,6 +1181,12 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             add4(acc, pos);
             lpart[j * T + tid] = acc;
         }
+        if (!ovf) {
+#pragma unroll
+            for (int o = 0; o < NOWN; ++o)
+                if (own_q[o] >= 0) gam_out[(int64_t)ii * IMP_K + own_q[o]] = own_r1[o];
+            if (k1_mine) gam_out[(int64_t)ii * IMP_K + cnt] = k1_r1;
+        }
         if (ovf) {
             // the overflowing row of R_{t+1}, written explicitly (same values)
 #pragma unroll
@@ -1185,10 +1201,10 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float rv = al1 * f4get(sv, e) - beta1;
-                    if (k1_mine && k1_le == 4 * j + e) rv = rv + d;
+                    if (k1_mine && k1_le == 4 * j + e) rv = k1_r1;
 #pragma unroll
                     for (int o = 0; o < NOWN; ++o)
-                        if (own_le[o] == 4 * j + e) rv = rv + own_g1[o];
+                        if (own_le[o] == 4 * j + e) rv = own_r1[o];
                     f4set(rn, e, rv);
                 }
                 store_chunk(Rx, x_rs, voff, j * T * 16, c, n, full, rn);
@@ -1580,7 +1596,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // The exemplar decision: column ii wins iff no column k < ii has
         // a+r >= D and no column k > ii has a+r > D, D = a(i,i) + r(i,i)
         // (lowest index on ties).  v > D is tested as v >= next float above D.
-        const float rdg = (al * sdg - beta) + (st_gdr[sl] == ii ? st_gd[sl] : 0.0f);
+        const float rdg = st_gdr[sl] == ii ? st_gd[sl] : al * sdg - beta;
         const float D = adg + rdg;
         const float Dn = __int_as_float(D >= 0.0f ? (D == 0.0f ? 1 : __float_as_int(D) + 1) : __float_as_int(D) - 1);
         bool fl = false;   // this thread saw a column that beats the diagonal
@@ -1594,7 +1610,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             nstate = fetch_state(i + 1);
             fetch_x(i + 1, nxt_c, nxt_v);
         }
-        // R-list entry tid (lanes of wavefront 0): column, gamma, s, acol_t
+        // R-list entry tid (lanes of wavefront 0): column, stored r_t, s, acol_t
         int rk = -1;
         float rg = 0.0f, rs = 0.0f, rav = 0.0f;
         if (tid < cnt) {
@@ -1734,7 +1750,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // exception list are merged by the list holder)
         const bool rl_diag = __ballot(rk == ii) != 0;     // meaningful in wavefront 0
         if (rk >= 0) {
-            const float r = (al * rs - beta) + rg;
+            const float r = rg;
             if (rk == ii) {
                 top2_merge(t2, adg + rs, ii, kNegInf);
             } else if (!((mask8[(size_t)xs * mw * 4 + (rk >> 2)] >> (rk & 3)) & 1u)) {
@@ -1755,7 +1771,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 if ((mb8[k >> 2] >> (4 + (k & 3))) & 1u) {
                     xrl[u] = true;
                     const int at = rl_find(sl, k);
-                    if (at >= 0) r = r + st_gam[sl][at];
+                    if (at >= 0) r = st_gam[sl][at];
                 }
                 const float an = lam * cur_v[u] + oml * fminf(0.0f, xtv[u] - fmaxf(0.0f, r));
                 merge(an + r, an + xsv[u], k);
@@ -1769,7 +1785,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             int ncnt = 0;
             float ngam = 0.0f;
             if (sw) {
-                // the count (lane 2K+1) and gamma (lane + K) of the state words
+                // the count (lane 2K+1) and stored r (lane + K) of the state words
                 ncnt = __builtin_amdgcn_readlane((int)nstate.v, 2 * IMP_K + 1);
                 ngam = __uint_as_float((uint32_t)__shfl((int)nstate.v, lane + IMP_K));
             }
@@ -1793,21 +1809,32 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             if (xovf) atomicOr(&p.st->imp_abort, 2);
         }
 
-        // State of R_{t+1}: beta' = lam beta + (1-lam) v1; every gamma decays
-        // by lam and column k1 gains d = (1-lam)(v1 - v2).  The list is held
-        // by wavefront 0, so its searches are ballots there.
+        // State of R_{t+1}: beta' = lam beta + (1-lam) v1 off the list; on
+        // it (and for k1 when it joins) the damped Eq. (2) in the explicit
+        // pass's rounding, r' = (lam r + (1-lam) s) - (1-lam) (k = k1 ? v2 :
+        // v1), stored as r itself (no cancellation of alpha s - beta against
+        // a large offset).  The list is held by wavefront 0, so its searches
+        // are ballots there.
         const int k1 = t2.k1;
-        const float d = oml * (t2.v1 - t2.v2);
+        const float m_other = oml * t2.v1, m_self = oml * t2.v2;
         const float beta1 = lam * beta + oml * t2.v1;
         const uint64_t bk1 = __ballot(rk >= 0 && rk == k1);
         const int pos1 = bk1 ? __builtin_ctzll(bk1) : -1;                  // wavefront 0
         const int k1_owner = (k1 >> 2) % T;
         const int k1_owner_has = __popcll(__ballot(rk >= 0 && ((rk >> 2) % T) == k1_owner));
         const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);   // wavefront 0
+        // r_{t+1} of this lane's list entry, and of k1 when it joins the list
+        // (its s: one load, rare once the lists settle)
+        const float rl1 = (lam * rg + oml * rs) - (tid == pos1 ? m_self : m_other);
+        float k1_r1 = 0.0f;
+        if (tid == 0 && pos1 < 0) {
+            const float s1 = p.S[i * ld + k1];
+            k1_r1 = (lam * (al * s1 - beta) + oml * s1) - m_self;
+        }
         if (wave == 0) {
             if (rk >= 0 && !ovf) {
                 col_out[(int64_t)ii * IMP_K + tid] = rk;
-                gam_out[(int64_t)ii * IMP_K + tid] = lam * rg + (tid == pos1 ? d : 0.0f);
+                gam_out[(int64_t)ii * IMP_K + tid] = rl1;
             }
             if (tid == 0) {
                 beta_out[ii] = beta1;
@@ -1817,7 +1844,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 } else {
                     if (pos1 < 0) {
                         col_out[(int64_t)ii * IMP_K + cnt] = k1;
-                        gam_out[(int64_t)ii * IMP_K + cnt] = d;
+                        gam_out[(int64_t)ii * IMP_K + cnt] = k1_r1;
                     }
                     cnt_out[ii] = cnt + (pos1 < 0 ? 1 : 0);
                 }
@@ -1838,14 +1865,14 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             // LDS partials: special columns and listed ones by their holders
             // (the reduction barrier orders the adds of consecutive rows)
             if (rk >= 0) {
-                const float r = (al1 * rs - beta1) + (lam * rg + (rk == k1 ? d : 0.0f));
+                const float r = rl1;
                 if (rk == ii) p.rdiag[ii] = r;
                 else if (r > 0.0f) lp[rk] = lp[rk] + r;
             }
             if (tid == 0) {
                 if (pos1 < 0) {
-                    // a new list column: its s (one load, rare once the lists settle)
-                    const float r = (al1 * p.S[i * ld + k1] - beta1) + d;
+                    // a new list column
+                    const float r = k1_r1;
                     if (k1 == ii) p.rdiag[ii] = r;
                     else if (r > 0.0f) lp[k1] = lp[k1] + r;
                 }
@@ -1908,17 +1935,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                         for (int e = 0; e < 4; ++e) {
                             const int k = c + e;
                             if (k >= n) break;
-                            float r = al1 * f4get(sv, e) - beta1;
+                            const float s = f4get(sv, e);
+                            float r = al1 * s - beta1;
                             bool listed = false;
                             if ((sp >> e) & 1u) {
                                 for (int qq = 0; qq < cnt; ++qq) {
                                     if (st_col[sl][qq] == k) {
-                                        r = r + (lam * st_gam[sl][qq] + (k == k1 ? d : 0.0f));
+                                        r = (lam * st_gam[sl][qq] + oml * s) - (k == k1 ? m_self : m_other);
                                         listed = true;
                                     }
                                 }
                             }
-                            if (!listed && k == k1) r = r + d;
+                            if (!listed && k == k1) r = (lam * (al * s - beta) + oml * s) - m_self;
                             if (k == ii) p.rdiag[ii] = r;
                             else if (r > 0.0f) P[k] = P[k] + r;
                         }
@@ -1932,15 +1960,16 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         if (wave == 0 && ovf) {
             float *Rx = Rx_base + i * ld;
             for (int k = lane; k < n; k += 64) {
-                float r = al1 * p.S[i * ld + k] - beta1;
+                const float s = p.S[i * ld + k];
+                float r = al1 * s - beta1;
                 bool listed = false;
                 for (int qq = 0; qq < cnt; ++qq) {
                     if (st_col[sl][qq] == k) {
-                        r = r + (lam * st_gam[sl][qq] + (k == k1 ? d : 0.0f));
+                        r = (lam * st_gam[sl][qq] + oml * s) - (k == k1 ? m_self : m_other);
                         listed = true;
                     }
                 }
-                if (!listed && k == k1) r = r + d;
+                if (!listed && k == k1) r = (lam * (al * s - beta) + oml * s) - m_self;
                 Rx[k] = r;
             }
         }
@@ -1960,7 +1989,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                     float r = al * s - beta;
                     if ((mb >> (4 + e)) & 1u) {
                         for (int qq = 0; qq < cnt; ++qq)
-                            if (st_col[sl][qq] == k) r = r + st_gam[sl][qq];
+                            if (st_col[sl][qq] == k) r = st_gam[sl][qq];
                     }
                     float a = acol_t[k];
                     if (k == ii) {
@@ -2029,8 +2058,8 @@ __global__ void k_ia_materialize(float *A, int64_t ld, int32_t n, const float *a
     }
 }
 
-// R(i,k) = alpha s(i,k) - beta(i) + gamma(i,k) for every row with a list;
-// the same expression (and rounding) as the passes use.
+// R(i,k) = alpha s(i,k) - beta(i) off the row's list and the stored value
+// on it, for every row with a list; the same values the passes use.
 __global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t n, const float *alpha,
                                   const char *state) {
 #pragma clang fp contract(off)
@@ -2062,7 +2091,7 @@ __global__ void k_imp_materialize(const float *S, float *R, int64_t ld, int32_t 
         __syncthreads();
         if (threadIdx.x < c) {
             const int64_t k = col[i * IMP_K + threadIdx.x];
-            rrow[k] = (al * srow[k] - b) + gam[i * IMP_K + threadIdx.x];
+            rrow[k] = gam[i * IMP_K + threadIdx.x];
         }
         __syncthreads();
     }

@@ -117,12 +117,14 @@ hipError_t launch_copy_rows(float *dst, const float *src, int64_t rows, int64_t 
                             hipStream_t s);
 
 // Implicit responsibilities (ap_iter.hip).  With R_0 = 0 the damped Eq. (2)
-// unrolls to R_t(i,k) = alpha_t s(i,k) - beta_t(i) + gamma_t(i,k) with
-// alpha_t = 1 - lambda^t, beta_{t+1} = lambda beta_t + (1-lambda) v1_t,
-// gamma_{t+1}(i,k) = lambda gamma_t(i,k) + (1-lambda)(v1_t - v2_t)[k = k1_t],
-// where gamma_t(i,.) is non-zero only on the columns that were row i's
-// argmax of a+s at an earlier iteration: a short list per row.  State for
-// R_t lives in parity t & 1 of the state arrays.
+// unrolls to R_t(i,k) = alpha_t s(i,k) - beta_t(i) with alpha_t = 1 -
+// lambda^t, beta_{t+1} = lambda beta_t + (1-lambda) v1_t, on every column k
+// that was never row i's argmax k1 of a+s; the columns that were (a short
+// list per row) keep r_t(i,k) itself, updated by the damped Eq. (2)
+// r_{t+1} = (lambda r_t + (1-lambda) s) - (1-lambda)(k = k1_t ? v2_t : v1_t).
+// (Keeping an offset gamma = r - (alpha s - beta) instead would cancel two
+// large terms in rows whose argmax column has a large availability.)  State
+// for R_t lives in parity t & 1 of the state arrays.
 constexpr int IMP_K = 16;            // list capacity per row
 enum ImpKind : int { IMP_FULL = 0, IMP_PRO_COLD = 1, IMP_PRO_WARM = 2 };
 
@@ -175,7 +177,7 @@ __host__ __device__ inline XLayout x_layout(int64_t n) {
 }
 // Byte layout of one parity of the implicit-R state for n rows: beta (n
 // floats), list length (n ints, -1 after an overflow), columns (n x IMP_K
-// ints), gammas (n x IMP_K floats).
+// ints), the listed columns' r values (n x IMP_K floats, field `gam`).
 struct ImpLayout {
     int64_t beta, cnt, col, gam, stride;
 };
