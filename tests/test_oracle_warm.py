@@ -262,3 +262,70 @@ def test_a0_from_exact_targets_is_the_fixed_point_availability():
     assert np.max(np.abs(A0[off] - ref.A[off])) <= 1e-6 * rng
     assert np.max(np.abs(np.diag(A0) - np.diag(ref.A))) <= 1e-6 * rng
     assert np.all(A0[~np.eye(n, dtype=bool)] <= 0) and np.all(np.diag(A0) >= 0)
+
+
+# ---------------------------------------------------------------------------
+# The straight-through gradient of the bfloat16 network, pinned against
+# central differences of a surrogate written here: the forward pass with
+# every bfloat16 rounding replaced by a fixed offset, the rounding error it
+# makes at the expansion point.  At that point the surrogate equals the
+# rounded network; its derivative treats each rounding as the identity,
+# which is the gradient the backward pass defines.  A slip in which operand
+# of a product the backward pass takes rounded (or unrounded) changes the
+# derivative by the rounding error times the other factor, which these
+# differences resolve.
+# ---------------------------------------------------------------------------
+def _st_surrogate(theta0, X):
+    rnd = warm.bf16_round
+    p0 = warm.unpack(theta0)
+    off = {k: rnd(p0[k]) - p0[k] for k in ("W1", "W2", "W3")}
+    x = rnd(X)
+    z1_0 = x @ rnd(p0["W1"]) + p0["b1"]
+    g1 = warm.gelu(z1_0)
+    o1 = rnd(g1) - g1
+    z2_0 = rnd(g1) @ rnd(p0["W2"]) + p0["b2"]
+    g2 = warm.gelu(z2_0)
+    o2 = rnd(g2) - g2
+
+    def f(theta, T, w):
+        p = warm.unpack(theta)
+        z1 = x @ (p["W1"] + off["W1"]) + p["b1"]
+        h1 = warm.gelu(z1) + o1
+        z2 = h1 @ (p["W2"] + off["W2"]) + p["b2"]
+        h2 = warm.gelu(z2) + o2
+        y = h2 @ (p["W3"] + off["W3"]) + p["b3"]
+        return float(np.sum(w[:, None] * warm.huber(y - T)))
+    return f
+
+
+def test_bf16_backward_is_the_straight_through_gradient():
+    theta, X, T, w = _fd_setup(seed=11, count=32)
+    # weights large enough that their rounding errors are far above the FD error
+    theta = theta * 4.0
+    L, g, _ = warm.backward(theta, X, T, w, bf16=True)
+    f = _st_surrogate(theta, X)
+    assert f(theta, T, w) == pytest.approx(warm.loss(theta, X, T, w, bf16=True), rel=1e-13)
+    assert L == pytest.approx(f(theta, T, w), rel=1e-13)
+    rng = np.random.default_rng(12)
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in warm.SHAPES])
+    dirs = [rng.normal(size=theta.size) for _ in range(3)]
+    for t in range(6):
+        d = np.zeros(theta.size)
+        d[offs[t]:offs[t + 1]] = rng.normal(size=offs[t + 1] - offs[t])
+        dirs.append(d)
+    h = 1e-6
+    for d in dirs:
+        d = d / np.linalg.norm(d)
+        fd = (f(theta + h * d, T, w) - f(theta - h * d, T, w)) / (2 * h)
+        assert abs(fd - g @ d) <= 1e-6 * abs(g @ d) + 1e-9
+
+
+def test_bf16_backward_differs_from_the_unrounded_gradient():
+    """The same check distinguishes the rounded network: the FP64 network's
+    gradient misses the surrogate's differences by far more than their error."""
+    theta, X, T, w = _fd_setup(seed=11, count=32)
+    theta = theta * 4.0
+    _, g64, _ = warm.backward(theta, X, T, w, bf16=False)
+    _, g16, _ = warm.backward(theta, X, T, w, bf16=True)
+    rel = np.abs(g64 - g16).max() / np.abs(g16).max()
+    assert rel > 1e-4
