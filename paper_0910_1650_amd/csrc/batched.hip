@@ -1,13 +1,19 @@
-// batched.hip -- many independent AP instances of uneven size in one launch
-// per half-iteration (Algorithm 1 run on each instance; the sub-problems of
+// batched.hip -- many independent AP instances of uneven size in ONE
+// persistent launch (Algorithm 1 run on each instance; the sub-problems of
 // partition AP, Algorithm 2 Step 2, are such a batch).
 //
-// Every launch walks a ragged work table: a work item is a contiguous block
-// of rows of one instance.  A full row pass and a column reduce per iteration
-// cover every active instance; each instance keeps its own stop-rule state,
-// and a frozen (stopped) instance's work items exit at once.  All instances
-// share one iteration counter, so the parity of t picks the responsibility
-// buffer for all of them.
+// The launch is a fixed grid of workgroups that are all resident at once (a
+// cooperative launch).  The host cuts the grid into teams over a ragged
+// table: an instance gets a team of g workgroups in proportion to its n^2
+// (member r owns a contiguous block of rows and the same block of columns
+// for the column sums), or, when there are more instances than workgroups,
+// one-workgroup teams each solve a queue of instances in turn.  A team runs
+// its instance from the prologue to the instance's own stop rule on the
+// device: per iteration a row pass (A_t, decisions, R_{t+1}, column
+// partials), a team barrier, the column sums of the member's columns in
+// FP64 in a fixed order and the stop rule (member 0), a team barrier.  The
+// host waits for the one launch; no iteration is driven from the host.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -25,7 +31,7 @@ struct InstDesc {
     float *A;
     int64_t ld;
     int32_t n;
-    int32_t nparts;       // work items (= partial rows) of this instance
+    int32_t nparts;       // team size (= partial rows) of this instance
     float *partial;       // [nparts][ldp]
     int64_t ldp;
     float *tcol, *ccol, *rdiag;
@@ -37,17 +43,6 @@ struct InstDesc {
     double *sums;         // [dpsim, expref]
     int32_t *nex_out;
     int32_t pad;
-};
-
-struct WorkItem {
-    int32_t inst;
-    int32_t row0, row1;
-    int32_t part;         // partial row of this item
-};
-
-struct ColBlock {
-    int32_t inst;
-    int32_t col0;
 };
 
 __device__ __forceinline__ float f4get(const float4 &v, int e) {
@@ -73,36 +68,34 @@ __device__ __forceinline__ void argmax_merge(float &v, int &k, float ov, int ok)
     k = take ? ok : k;
 }
 
-// Batched row pass: same arithmetic as the single-instance pass (Eqs. (2)-(4)
-// with damping, decision, column partials), one work item per workgroup.
-// MODE: PASS_FULL, PASS_R_ONLY, PASS_R_COLD (also writes A_0 = 0).
+// Rows [row0, row1) of one instance: same arithmetic as the single-instance
+// pass (Eqs. (2)-(4) with damping, decision, column partials into partial
+// row `part`).  MODE: PASS_FULL, PASS_R_ONLY, PASS_R_COLD (also writes
+// A_0 = 0).  sh_f / sh_i: the workgroup's reduction slots.
 template <int J, int MODE>
-__global__ __launch_bounds__(BT) void k_batch_row_pass(const InstDesc *descs, const WorkItem *items,
-                                                       float lam, int32_t t) {
+__device__ __forceinline__ void rows_pass(const InstDesc *dp, int row0, int row1, int part, float lam, int32_t t,
+                                          float (*sh_f)[BT / 64][3], int (*sh_i)[BT / 64][2]) {
 #pragma clang fp contract(off)
+    const InstDesc d = *dp;
     constexpr bool DO_A = (MODE == PASS_FULL);
     constexpr bool LD_RA = (MODE != PASS_R_COLD);
     constexpr int NW = BT / 64;
-    const WorkItem wi = items[blockIdx.x];
-    const InstDesc d = descs[wi.inst];
-    if (d.st->frozen) return;
-    __shared__ float sh_f[2][NW][3];
-    __shared__ int sh_i[2][NW][2];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = d.n;
     const int64_t ld = d.ld;
     const float oml = 1.0f - lam;
-    const float *Rin = d.R[t & 1];
-    float *Rout = d.R[(t + 1) & 1];
+    // (selects, not an index: an indexed member would put d in scratch)
+    const float *Rin = (t & 1) ? d.R[1] : d.R[0];
+    float *Rout = (t & 1) ? d.R[0] : d.R[1];
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
-    float4 part[J];
+    float4 part4[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) part[j] = z4;
+    for (int j = 0; j < J; ++j) part4[j] = z4;
     int my_nex = 0, my_changed = 0;
 
-    for (int i = wi.row0; i < wi.row1; ++i) {
+    for (int i = row0; i < row1; ++i) {
         const float *Srow = d.S + (int64_t)i * ld;
         const float *Rrow = Rin + (int64_t)i * ld;
         float *Arow = d.A + (int64_t)i * ld;
@@ -206,7 +199,7 @@ __global__ __launch_bounds__(BT) void k_batch_row_pass(const InstDesc *descs, co
                 f4set(rn, e, v);
                 if (k < n) {
                     if (k == i) d.rdiag[i] = v;
-                    else f4set(part[j], e, f4get(part[j], e) + fmaxf(0.0f, v));
+                    else f4set(part4[j], e, f4get(part4[j], e) + fmaxf(0.0f, v));
                 }
             }
             if (full) {
@@ -218,11 +211,11 @@ __global__ __launch_bounds__(BT) void k_batch_row_pass(const InstDesc *descs, co
             }
         }
     }
-    float *P = d.partial + (int64_t)wi.part * d.ldp;
+    float *P = d.partial + (int64_t)part * d.ldp;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int c = (j * BT + tid) * 4;
-        if (c < n) *reinterpret_cast<float4 *>(P + c) = part[j];
+        if (c < n) *reinterpret_cast<float4 *>(P + c) = part4[j];
     }
     if constexpr (DO_A) {
         if (tid == 0) {
@@ -232,36 +225,161 @@ __global__ __launch_bounds__(BT) void k_batch_row_pass(const InstDesc *descs, co
     }
 }
 
-// Column sums per instance (FP64, fixed order over the instance's work items)
-// and, for the block holding column 0, the stop rule of that instance.
-__global__ __launch_bounds__(256) void k_batch_col_reduce(const InstDesc *descs, const ColBlock *blocks,
-                                                          int bookkeep) {
-    const ColBlock cb = blocks[blockIdx.x];
-    const InstDesc d = descs[cb.inst];
-    if (d.st->frozen) return;
-    const int k = cb.col0 + threadIdx.x;
-    if (k < d.n) {
+// Column sums of columns [c0, c1) of one instance over its nparts partial
+// rows, in FP64: 16 columns at a time, 16 slices of the partial rows per
+// column, slices combined in a fixed order (deterministic).
+__device__ __forceinline__ void col_sums(const InstDesc *dp, int c0, int c1, double (*red)[16]) {
+#pragma clang fp contract(off)
+    const InstDesc d = *dp;
+    const int cx = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    for (int cb = c0; cb < c1; cb += 16) {
+        const int k = cb + cx;
         double c = 0.0;
-        for (int g = 0; g < d.nparts; ++g) c += (double)d.partial[(int64_t)g * d.ldp + k];
-        d.tcol[k] = (float)((double)d.rdiag[k] + c);
-        d.ccol[k] = (float)c;
-    }
-    if (bookkeep && cb.col0 == 0 && threadIdx.x == 0) {
-        ApState *st = d.st;
-        const int t = st->iter + 1;
-        const int same = (t > 1) && (st->changed == 0);
-        const int run = same ? st->run + 1 : 1;
-        st->iter = t;
-        st->run = run;
-        st->last_nex = st->nex;
-        if (st->conv_iter > 0 && run >= st->conv_iter && st->nex > 0) {
-            st->converged = 1;
-            st->frozen = 1;
-        } else if (t >= st->max_iter) {
-            st->frozen = 1;
+        if (k < c1) {
+            int g = sl;
+            for (; g + 3 * 16 < d.nparts; g += 4 * 16) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = d.partial[(int64_t)(g + u * 16) * d.ldp + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c += (double)v[u];
+            }
+            for (; g < d.nparts; g += 16) c += (double)d.partial[(int64_t)g * d.ldp + k];
         }
-        st->nex = 0;
-        st->changed = 0;
+        red[sl][cx] = c;
+        __syncthreads();
+        if (sl == 0 && k < c1) {
+            double tot = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) tot += red[q][cx];
+            d.tcol[k] = (float)((double)d.rdiag[k] + tot);
+            d.ccol[k] = (float)tot;
+        }
+        __syncthreads();
+    }
+}
+
+// The stop rule of one instance after the pass of iteration st->iter + 1
+// (the exemplar-set rule and the iteration cap).
+__device__ __forceinline__ void bookkeep(ApState *st) {
+    const int t = st->iter + 1;
+    const int same = (t > 1) && (st->changed == 0);
+    const int run = same ? st->run + 1 : 1;
+    st->iter = t;
+    st->run = run;
+    st->last_nex = st->nex;
+    if (st->conv_iter > 0 && run >= st->conv_iter && st->nex > 0) {
+        st->converged = 1;
+        st->frozen = 1;
+    } else if (t >= st->max_iter) {
+        st->frozen = 1;
+    }
+    st->nex = 0;
+    st->changed = 0;
+}
+
+// Barrier of a team of g workgroups (g > 1): arrival counter and generation
+// word; the last to arrive resets the counter and publishes the next
+// generation.  Writes before the barrier are released at device scope and
+// acquired after it.  The wait is bounded: after about kSpinLimit polls
+// (seconds; a legitimate wait is one member's row pass, well under a
+// millisecond) the fail flag is raised and the workgroup gives up, so a
+// broken team cannot hang the device; the host reports the failure.
+struct TeamBar {
+    uint32_t count;
+    uint32_t gen;
+    uint32_t pad[62];    // one 256-byte line per team
+};
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Returns false (in every thread) when the team has failed.
+__device__ __forceinline__ bool team_sync(TeamBar *bar, int g, uint32_t &gen, int32_t *fail, int *ok_sh) {
+    if (g == 1) {
+        __syncthreads();
+        return true;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t target = gen + 1u;
+        if (atomicAdd(&bar->count, 1u) == (uint32_t)g - 1u) {
+            atomicExch(&bar->count, 0u);
+            __threadfence();
+            atomicExch(&bar->gen, target);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                __builtin_amdgcn_s_sleep(4);
+                if (++spins > kSpinLimit) {
+                    atomicOr(fail, 1);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        gen = target;
+        *ok_sh = __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    }
+    __syncthreads();
+    return *ok_sh != 0;
+}
+
+// One task: instance `inst`, member `rank` of a team of g workgroups (team
+// barrier `bar`, -1 for a team of one).
+struct Task {
+    int32_t inst, rank, g, bar;
+};
+
+struct PersistArgs {
+    const InstDesc *descs;
+    const Task *tasks;
+    const int32_t *lane;      // workgroup b runs tasks [lane[b], lane[b+1]) in order
+    TeamBar *bars;
+    int32_t *fail;
+    float lam;
+    int32_t warm;
+};
+
+// The whole batched solve in one launch: every workgroup runs its tasks in
+// turn; a task is Algorithm 1 on one instance, from the prologue (R_1) to
+// the instance's own stop rule, in lockstep with the rest of its team.
+// The shortest rows keep four workgroups per compute unit (128 registers);
+// longer rows take the registers their chunks need (the occupancy query
+// sets the grid).
+template <int J>
+__global__ __launch_bounds__(BT, J <= 1 ? 4 : 1) void k_batch_persist(PersistArgs a) {
+    __shared__ float sh_f[2][BT / 64][3];
+    __shared__ int sh_i[2][BT / 64][2];
+    __shared__ double red[16][16];
+    __shared__ int ok_sh, frozen_sh;
+    const int b = blockIdx.x;
+    for (int q = a.lane[b]; q < a.lane[b + 1]; ++q) {
+        const Task tk = a.tasks[q];
+        const InstDesc *d = a.descs + tk.inst;
+        ApState *st = d->st;
+        TeamBar *bar = tk.bar >= 0 ? a.bars + tk.bar : nullptr;
+        uint32_t gen = 0u;
+        const int n = d->n;
+        const int row0 = (int)((int64_t)tk.rank * n / tk.g);
+        const int row1 = (int)((int64_t)(tk.rank + 1) * n / tk.g);
+        // t = 0: R_1 from R_0 (zero, or given) and A_0 (zero: written here)
+        if (a.warm == APX_COLD) rows_pass<J, PASS_R_COLD>(d, row0, row1, tk.rank, a.lam, 0, sh_f, sh_i);
+        else rows_pass<J, PASS_R_ONLY>(d, row0, row1, tk.rank, a.lam, 0, sh_f, sh_i);
+        if (!team_sync(bar, tk.g, gen, a.fail, &ok_sh)) return;
+        col_sums(d, row0, row1, red);
+        if (!team_sync(bar, tk.g, gen, a.fail, &ok_sh)) return;
+        for (int32_t t = 1;; ++t) {
+            rows_pass<J, PASS_FULL>(d, row0, row1, tk.rank, a.lam, t, sh_f, sh_i);
+            if (!team_sync(bar, tk.g, gen, a.fail, &ok_sh)) return;
+            col_sums(d, row0, row1, red);
+            if (tk.rank == 0 && threadIdx.x == 0) bookkeep(st);
+            if (!team_sync(bar, tk.g, gen, a.fail, &ok_sh)) return;
+            if (threadIdx.x == 0) frozen_sh = __hip_atomic_load(&st->frozen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int fz = frozen_sh;
+            __syncthreads();
+            if (fz) break;
+        }
     }
 }
 
@@ -379,32 +497,36 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc *descs) 
 }
 
 template <int J>
-hipError_t launch_batch_pass(int mode, const InstDesc *descs, const WorkItem *items, int nitems,
-                             float lam, int32_t t, hipStream_t s) {
-    switch (mode) {
-    case PASS_FULL: k_batch_row_pass<J, PASS_FULL><<<nitems, BT, 0, s>>>(descs, items, lam, t); break;
-    case PASS_R_ONLY: k_batch_row_pass<J, PASS_R_ONLY><<<nitems, BT, 0, s>>>(descs, items, lam, t); break;
-    default: k_batch_row_pass<J, PASS_R_COLD><<<nitems, BT, 0, s>>>(descs, items, lam, t); break;
-    }
-    return hipGetLastError();
+hipError_t launch_persist(const PersistArgs &a, int grid, hipStream_t s) {
+    void *args[] = {const_cast<PersistArgs *>(&a)};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_batch_persist<J>), dim3(grid), dim3(BT),
+                                      args, 0, s);
 }
 
-hipError_t batch_pass(int J, int mode, const InstDesc *descs, const WorkItem *items, int nitems,
-                      float lam, int32_t t, hipStream_t s) {
+template <int J>
+int persist_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_persist<J>, BT, 0) != hipSuccess) nb = 0;
+    return nb;
+}
+
+#define APX_BATCH_J(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+
+hipError_t persist_launch(int J, const PersistArgs &a, int grid, hipStream_t s) {
     switch (J) {
-    case 1: return launch_batch_pass<1>(mode, descs, items, nitems, lam, t, s);
-    case 2: return launch_batch_pass<2>(mode, descs, items, nitems, lam, t, s);
-    case 3: return launch_batch_pass<3>(mode, descs, items, nitems, lam, t, s);
-    case 4: return launch_batch_pass<4>(mode, descs, items, nitems, lam, t, s);
-    case 5: return launch_batch_pass<5>(mode, descs, items, nitems, lam, t, s);
-    case 6: return launch_batch_pass<6>(mode, descs, items, nitems, lam, t, s);
-    case 7: return launch_batch_pass<7>(mode, descs, items, nitems, lam, t, s);
-    case 8: return launch_batch_pass<8>(mode, descs, items, nitems, lam, t, s);
-    case 9: return launch_batch_pass<9>(mode, descs, items, nitems, lam, t, s);
-    case 10: return launch_batch_pass<10>(mode, descs, items, nitems, lam, t, s);
-    case 11: return launch_batch_pass<11>(mode, descs, items, nitems, lam, t, s);
-    case 12: return launch_batch_pass<12>(mode, descs, items, nitems, lam, t, s);
+#define APX_CASE(j) case j: return launch_persist<j>(a, grid, s);
+        APX_BATCH_J(APX_CASE)
+#undef APX_CASE
     default: return hipErrorInvalidValue;
+    }
+}
+
+int occupancy_of(int J) {
+    switch (J) {
+#define APX_CASE(j) case j: return persist_occupancy<j>();
+        APX_BATCH_J(APX_CASE)
+#undef APX_CASE
+    default: return 0;
     }
 }
 
@@ -412,46 +534,105 @@ hipError_t batch_pass(int J, int mode, const InstDesc *descs, const WorkItem *it
 
 namespace {
 
+// Workgroups per compute unit of the persistent launch (at most; fewer when
+// the kernel's occupancy is lower), and the least work per team member.
+constexpr int kMaxWpc = 4;
+constexpr double kMinMemberElems = 131072.0;
+
 struct BatchPlan {
-    int J;
-    std::vector<WorkItem> items;
-    std::vector<int32_t> nparts;
-    std::vector<ColBlock> cblocks;
+    int J, wpc, G;
+    std::vector<Task> tasks;
+    std::vector<int32_t> lane;     // G + 1 entries
+    std::vector<int32_t> team;     // team size per instance
+    int nbars;
     // workspace offsets (relative to the plan's base)
     std::vector<size_t> o_r2, o_part, o_t, o_c, o_d, o_e, o_dec, o_ex;
-    size_t o_st, o_sum, o_nex, o_desc, o_items, o_cb, bytes;
+    size_t o_st, o_sum, o_nex, o_desc, o_tasks, o_lane, o_bars, o_fail, bytes;
 };
 
-BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus) {
+// Teams: with no more instances than workgroups, each instance gets its own
+// team, sized in proportion to its n^2 (at least one workgroup, at most one
+// per row, and no member with fewer than kMinMemberElems elements per
+// iteration unless the team is one workgroup), scaled so the teams fill
+// the grid; all instances then run at once.  With more instances than
+// workgroups, every team is one workgroup and the instances are dealt to
+// the workgroups largest first, each to the least loaded one.
+BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc) {
     BatchPlan P;
-    int64_t max_n = 0, total = 0;
-    for (int j = 0; j < count; ++j) {
-        max_n = spec[j].n > max_n ? spec[j].n : max_n;
-        total += spec[j].n * spec[j].n;
-    }
+    int64_t max_n = 0;
+    for (int j = 0; j < count; ++j) max_n = spec[j].n > max_n ? spec[j].n : max_n;
     P.J = (int)((max_n + 4 * BT - 1) / (4 * BT));
-    // Work items: about 4 per CU in total, at least one per instance, rows
-    // split so that items carry similar element counts.
-    const int64_t target = total / (4LL * num_cus) + 1;
-    P.nparts.resize(count);
+    P.wpc = wpc;
+    P.G = num_cus * wpc;
+    const int G = P.G;
+    P.team.assign(count, 1);
+    P.lane.assign(G + 1, 0);
+    std::vector<double> cost(count);
+    double tot = 0.0;
     for (int j = 0; j < count; ++j) {
-        const int64_t n = spec[j].n;
-        int64_t rows = target / (n > 0 ? n : 1);
-        if (rows < 1) rows = 1;
-        if (rows > n) rows = n;
-        int32_t p = 0;
-        for (int64_t r = 0; r < n; r += rows, ++p)
-            P.items.push_back(WorkItem{j, (int32_t)r, (int32_t)(r + rows < n ? r + rows : n), p});
-        P.nparts[j] = p;
-        for (int64_t c = 0; c < n; c += 256) P.cblocks.push_back(ColBlock{j, (int32_t)c});
+        cost[j] = (double)spec[j].n * (double)spec[j].n;
+        tot += cost[j];
     }
+    std::vector<std::vector<Task>> per(G);
+    P.nbars = 0;
+    if (count <= G) {
+        auto gmax = [&](int j) -> int64_t {
+            int64_t m = (int64_t)(cost[j] / kMinMemberElems);
+            if (m < 1) m = 1;
+            return m < spec[j].n ? m : spec[j].n;
+        };
+        auto sizes = [&](double x, std::vector<int32_t> &g) -> int64_t {
+            int64_t sum = 0;
+            for (int j = 0; j < count; ++j) {
+                int64_t v = (int64_t)(x * cost[j] / tot);
+                const int64_t m = gmax(j);
+                v = v < 1 ? 1 : (v > m ? m : v);
+                g[j] = (int32_t)v;
+                sum += v;
+            }
+            return sum;
+        };
+        std::vector<int32_t> g(count);
+        double lo = 0.0, hi = (double)G;
+        while (sizes(hi, g) <= G && hi < 1e12) hi *= 2.0;
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (sizes(mid, g) <= G) lo = mid;
+            else hi = mid;
+        }
+        sizes(lo, g);
+        int b = 0;
+        for (int j = 0; j < count; ++j) {
+            P.team[j] = g[j];
+            const int bar = g[j] > 1 ? P.nbars++ : -1;
+            for (int r = 0; r < g[j]; ++r) per[b++].push_back(Task{j, r, g[j], bar});
+        }
+    } else {
+        std::vector<int> order(count);
+        for (int j = 0; j < count; ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        std::vector<double> load(G, 0.0);
+        for (int j : order) {
+            int best = 0;
+            for (int b = 1; b < G; ++b)
+                if (load[b] < load[best]) best = b;
+            load[best] += cost[j];
+            per[best].push_back(Task{j, 0, 1, -1});
+        }
+    }
+    for (int b = 0; b < G; ++b) {
+        P.lane[b] = (int32_t)P.tasks.size();
+        P.tasks.insert(P.tasks.end(), per[b].begin(), per[b].end());
+    }
+    P.lane[G] = (int32_t)P.tasks.size();
+
     WsLayout L;
     P.o_r2.resize(count); P.o_part.resize(count); P.o_t.resize(count); P.o_c.resize(count);
     P.o_d.resize(count); P.o_e.resize(count); P.o_dec.resize(count); P.o_ex.resize(count);
     for (int j = 0; j < count; ++j) {
         const int64_t n = spec[j].n, ldp = (n + 3) & ~int64_t(3);
         P.o_r2[j] = L.take(sizeof(float) * (size_t)n * (size_t)spec[j].ld);
-        P.o_part[j] = L.take(sizeof(float) * (size_t)ldp * P.nparts[j]);
+        P.o_part[j] = L.take(sizeof(float) * (size_t)ldp * (size_t)P.team[j]);
         P.o_t[j] = L.take(sizeof(float) * ldp);
         P.o_c[j] = L.take(sizeof(float) * ldp);
         P.o_d[j] = L.take(sizeof(float) * ldp);
@@ -463,8 +644,10 @@ BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus) {
     P.o_sum = L.take(sizeof(double) * 2 * count);
     P.o_nex = L.take(sizeof(int32_t) * count);
     P.o_desc = L.take(sizeof(InstDesc) * count);
-    P.o_items = L.take(sizeof(WorkItem) * P.items.size());
-    P.o_cb = L.take(sizeof(ColBlock) * P.cblocks.size());
+    P.o_tasks = L.take(sizeof(Task) * (P.tasks.size() > 0 ? P.tasks.size() : 1));
+    P.o_lane = L.take(sizeof(int32_t) * (size_t)(G + 1));
+    P.o_bars = L.take(sizeof(TeamBar) * (size_t)(P.nbars > 0 ? P.nbars : 1));
+    P.o_fail = L.take(sizeof(int32_t));
     P.bytes = L.off;
     return P;
 }
@@ -472,16 +655,24 @@ BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus) {
 }  // namespace
 
 size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus) {
-    return make_plan(count, spec, num_cus).bytes;
+    // an upper bound: the plan at the largest workgroups per CU
+    return make_plan(count, spec, num_cus, kMaxWpc).bytes;
 }
 
 // Host driver shared by ap_solve_batched and pap_solve (Step 2): the
-// workspace slice starts at ctx->ws_base.
+// workspace slice starts at ctx->ws_base.  Tables, initial state, one
+// persistent cooperative launch, then R_T and the labels.
 apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int32_t warm,
                          const apx_params *params, apx_result *res) {
     hipStream_t s = ctx->stream;
-    BatchPlan P = make_plan(count, spec, ctx->num_cus);
-    if (P.J > 12) return set_err(ctx, APX_ENOTIMPL, "batched instances are limited to n <= %d", 12 * 4 * BT);
+    int64_t max_n = 0;
+    for (int j = 0; j < count; ++j) max_n = spec[j].n > max_n ? spec[j].n : max_n;
+    const int J = (int)((max_n + 4 * BT - 1) / (4 * BT));
+    if (J > 12) return set_err(ctx, APX_ENOTIMPL, "batched instances are limited to n <= %d", 12 * 4 * BT);
+    int wpc = occupancy_of(J);
+    if (wpc < 1) return set_err(ctx, APX_EDEVICE, "no occupancy for the batched kernel");
+    wpc = wpc < kMaxWpc ? wpc : kMaxWpc;
+    BatchPlan P = make_plan(count, spec, ctx->num_cus, wpc);
     apx_status st = ws_reserve(ctx, ctx->ws_base + P.bytes);
     if (st != APX_OK) return st;
     char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
@@ -490,7 +681,6 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
     double *dsum = reinterpret_cast<double *>(b + P.o_sum);
     int32_t *dnex = reinterpret_cast<int32_t *>(b + P.o_nex);
     std::vector<InstDesc> descs(count);
-    int64_t max_n = 0;
     for (int j = 0; j < count; ++j) {
         InstDesc &d = descs[j];
         std::memset(&d, 0, sizeof d);
@@ -500,7 +690,7 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
         d.A = spec[j].A;
         d.ld = spec[j].ld;
         d.n = (int32_t)spec[j].n;
-        d.nparts = P.nparts[j];
+        d.nparts = P.team[j];
         d.partial = reinterpret_cast<float *>(b + P.o_part[j]);
         d.ldp = (spec[j].n + 3) & ~int64_t(3);
         d.tcol = reinterpret_cast<float *>(b + P.o_t[j]);
@@ -513,63 +703,48 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
         d.ex = reinterpret_cast<int32_t *>(b + P.o_ex[j]);
         d.sums = dsum + 2 * j;
         d.nex_out = dnex + j;
-        max_n = spec[j].n > max_n ? spec[j].n : max_n;
     }
     InstDesc *ddesc = reinterpret_cast<InstDesc *>(b + P.o_desc);
-    WorkItem *ditems = reinterpret_cast<WorkItem *>(b + P.o_items);
-    ColBlock *dcb = reinterpret_cast<ColBlock *>(b + P.o_cb);
+    Task *dtasks = reinterpret_cast<Task *>(b + P.o_tasks);
+    int32_t *dlane = reinterpret_cast<int32_t *>(b + P.o_lane);
+    TeamBar *dbars = reinterpret_cast<TeamBar *>(b + P.o_bars);
+    int32_t *dfail = reinterpret_cast<int32_t *>(b + P.o_fail);
     hipError_t e;
     if ((e = hipMemcpyAsync(ddesc, descs.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(ditems, P.items.data(), sizeof(WorkItem) * P.items.size(), hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(dcb, P.cblocks.data(), sizeof(ColBlock) * P.cblocks.size(), hipMemcpyHostToDevice, s)) ||
+        (!P.tasks.empty() &&
+         (e = hipMemcpyAsync(dtasks, P.tasks.data(), sizeof(Task) * P.tasks.size(), hipMemcpyHostToDevice, s))) ||
+        (e = hipMemcpyAsync(dlane, P.lane.data(), sizeof(int32_t) * P.lane.size(), hipMemcpyHostToDevice, s)) ||
         (e = hipStreamSynchronize(s)))
         return hip_err(ctx, e, "batch tables");
 
-    const float lam = params->damping;
-    const int J = P.J, nitems = (int)P.items.size(), ncb = (int)P.cblocks.size();
     const dim3 zgrid((unsigned)(max_n < 2048 ? max_n : 2048), (unsigned)count);
     k_batch_init<<<count, 256, 0, s>>>(ddesc, count, params->max_iter, params->conv_iter);
     if ((e = hipGetLastError())) return hip_err(ctx, e, "batch init");
-    if (warm == APX_COLD) {
-        if ((e = batch_pass(J, PASS_R_COLD, ddesc, ditems, nitems, lam, 0, s))) return hip_err(ctx, e, "prologue");
-    } else {
-        if (warm == APX_WARM_A) {
-            k_batch_zero<<<zgrid, 256, 0, s>>>(ddesc, 1);
-            if ((e = hipGetLastError())) return hip_err(ctx, e, "R_0");
-        }
-        if ((e = batch_pass(J, PASS_R_ONLY, ddesc, ditems, nitems, lam, 0, s))) return hip_err(ctx, e, "prologue");
+    // team barriers and the fail flag start at zero (a fill kernel, not a memset)
+    if ((e = launch_fill_u8(reinterpret_cast<uint8_t *>(dbars), sizeof(TeamBar) * (P.nbars > 0 ? P.nbars : 1), 0, s)) ||
+        (e = launch_fill_u8(reinterpret_cast<uint8_t *>(dfail), sizeof(int32_t), 0, s)))
+        return hip_err(ctx, e, "batch barriers");
+    if (warm == APX_WARM_A) {
+        k_batch_zero<<<zgrid, 256, 0, s>>>(ddesc, 1);
+        if ((e = hipGetLastError())) return hip_err(ctx, e, "R_0");
     }
-    k_batch_col_reduce<<<ncb, 256, 0, s>>>(ddesc, dcb, 0);
-    if ((e = hipGetLastError())) return hip_err(ctx, e, "column reduce");
-
-    const int chunk = params->check_every > 0 ? params->check_every : 16;
-    std::vector<ApState> hst(count);
-    int32_t t = 1;
-    for (;;) {
-        int32_t stop_at = t + chunk;
-        if (stop_at > params->max_iter + 1) stop_at = params->max_iter + 1;
-        for (; t < stop_at; ++t) {
-            if ((e = batch_pass(J, PASS_FULL, ddesc, ditems, nitems, lam, t, s))) return hip_err(ctx, e, "row pass");
-            k_batch_col_reduce<<<ncb, 256, 0, s>>>(ddesc, dcb, 1);
-            if ((e = hipGetLastError())) return hip_err(ctx, e, "column reduce");
-        }
-        if ((e = hipMemcpyAsync(hst.data(), dst, sizeof(ApState) * count, hipMemcpyDeviceToHost, s)) ||
-            (e = hipStreamSynchronize(s)))
-            return hip_err(ctx, e, "state");
-        bool all = true;
-        for (int j = 0; j < count; ++j) all = all && hst[j].frozen;
-        if (all || t > params->max_iter) break;
-    }
+    PersistArgs pa{ddesc, dtasks, dlane, dbars, dfail, params->damping, warm};
+    if ((e = persist_launch(J, pa, P.G, s))) return hip_err(ctx, e, "persistent batch launch");
     k_batch_fix_r<<<zgrid, 256, 0, s>>>(ddesc);
     if ((e = hipGetLastError())) return hip_err(ctx, e, "copy R");
     k_batch_finalize<<<count, 1024, 0, s>>>(ddesc);
     if ((e = hipGetLastError())) return hip_err(ctx, e, "finalize");
+    std::vector<ApState> hst(count);
     std::vector<double> sums(2 * (size_t)count);
     std::vector<int32_t> nex(count);
-    if ((e = hipMemcpyAsync(sums.data(), dsum, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s)) ||
+    int32_t hfail = 0;
+    if ((e = hipMemcpyAsync(hst.data(), dst, sizeof(ApState) * count, hipMemcpyDeviceToHost, s)) ||
+        (e = hipMemcpyAsync(sums.data(), dsum, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s)) ||
         (e = hipMemcpyAsync(nex.data(), dnex, sizeof(int32_t) * count, hipMemcpyDeviceToHost, s)) ||
+        (e = hipMemcpyAsync(&hfail, dfail, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
         (e = hipStreamSynchronize(s)))
         return hip_err(ctx, e, "results");
+    if (hfail) return set_err(ctx, APX_EDEVICE, "batched launch: a team barrier timed out");
     for (int j = 0; j < count; ++j) {
         apx_result &r = res[j];
         std::memset(&r, 0, sizeof r);

@@ -124,3 +124,46 @@ def test_pap_rejects_bad_partition():
         apx.pap_solve(S, apx.empty_matrix(50), apx.empty_matrix(50), 2, perm=np.zeros(50, dtype=np.int64))
     with pytest.raises(apx.ApxError):
         apx.pap_solve(S, apx.empty_matrix(50), apx.empty_matrix(50), 2, offsets=[0, 60, 50])
+
+
+def test_more_instances_than_workgroups():
+    """1300 small instances (more than the persistent grid holds): one-
+    workgroup teams each solve a queue of instances; every instance equals
+    its own oracle run."""
+    rng = np.random.default_rng(5)
+    Ss = []
+    for j in range(1300):
+        n = int(rng.integers(12, 48))
+        pts = synth.gaussian_2d(n=n, k=3, seed=7000 + j)
+        Ss.append(inst_S(pts, 7000 + j))
+    print("batched: 1300 instances", flush=True)
+    idxs, res = apx.ap_solve_batched([dev(S) for S in Ss], damping=0.9, max_iter=500, conv_iter=15)
+    for j, (S, idx, r) in enumerate(zip(Ss, idxs, res)):
+        ref = oracle.ap(S, 0.9, 500, 15)
+        assert r.iterations == ref.iterations and r.converged == ref.converged, j
+        assert np.array_equal(idx.cpu().numpy(), ref.idx), j
+
+
+def test_one_large_instance_runs_as_a_team():
+    """A batch whose instances are far from equal: one large instance takes a
+    team of many workgroups (device barriers between its passes) next to
+    small ones; messages after a fixed count and the converged exemplars
+    against the oracle."""
+    sizes = [6000, 300, 450]
+    Ss = [inst_S(synth.gaussian_2d(n=n, k=6, seed=7900 + n), 7900 + n) for n in sizes]
+    print("batched: team instance", sizes, flush=True)
+    Rs = [apx.empty_matrix(n) for n in sizes]
+    As = [apx.empty_matrix(n) for n in sizes]
+    apx.ap_solve_batched([dev(S) for S in Ss], Rs, As, damping=0.9, max_iter=60, conv_iter=0)
+    for S, R, A in zip(Ss, Rs, As):
+        ref = oracle.ap(S, 0.9, 60, 0)
+        rng = S.max() - S.min()
+        assert np.max(np.abs(R.cpu().numpy() - ref.R)) <= 1e-4 * rng
+        assert np.max(np.abs(A.cpu().numpy() - ref.A)) <= 1e-4 * rng
+    idxs, res = apx.ap_solve_batched([dev(S) for S in Ss], damping=0.9, max_iter=1000, conv_iter=15)
+    idxs2, res2 = apx.ap_solve_batched([dev(S) for S in Ss], damping=0.9, max_iter=1000, conv_iter=15)
+    for S, idx, r, idx2, r2 in zip(Ss, idxs, res, idxs2, res2):
+        ref = oracle.ap(S, 0.9, 1000, 15)
+        assert r.iterations == ref.iterations
+        assert np.array_equal(idx.cpu().numpy(), ref.idx)
+        assert torch.equal(idx, idx2) and r.netsim == r2.netsim
