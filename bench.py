@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-warm-compare", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (PAP at N=40000, the 512-instance batch, LAP)")
     ap.add_argument("--counter-run", action="store_true",
                     help="sequence for rocprofv3 --pmc runs: one ap_solve at N as a step runs it "
                          "(to the stop rule), then a plain 1.6 GB device copy (the calibration "
@@ -140,6 +142,136 @@ def time_to_exemplars(apx, S, n, pts_seed):
     if ref is not None:
         out["oracle"] = {"iterations": ref["iterations"], "n_exemplars": ref["n_exemplars"],
                          "netsim": ref["netsim"]}
+    return out
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) * 1e3
+
+
+def workload_extras(apx) -> dict:
+    """The other workloads of the path, each timed once outside the timed
+    region (inputs resident in HBM before each clock starts):
+
+    * pap_c3: Algorithm 2 on 40000 points on a union of 20 random 5-D
+      subspaces of R^100, 8 random parts of 3000-7000 points; the parts'
+      sub-problems alone (one persistent batched launch) with their HBM rate
+      (20 B per element and iteration of the explicit form those passes run,
+      summed over the parts' own iteration counts), the whole pap_solve, and
+      cold-start AP on the same S.
+    * batch_512: 512 independent 2-D mixtures, n in [100, 2000], 2-20
+      components, damping 0.5, at most 200 iterations: one ap_solve_batched
+      call; instance-iterations per second and the same HBM rate.
+    * lap_c4: Algorithm 3 (Steps 1-2) on 200000 points in 128-D, 10000
+      landmarks: the landmark similarity and AP, then the assignment of every
+      point; the whole lap_solve and the assignment's FP32 rate."""
+    import numpy as np
+    import torch
+
+    import synth
+    out = {}
+    # ---- PAP, N = 40000
+    n, seed = 40000, 3001
+    pts = synth.subspaces(n=n, d=100, n_sub=20, dim=5, noise=0.05, seed=seed)
+    X = torch.from_numpy(pts.X).cuda()
+    S, _ = apx.ap_similarity(X, pref="median", noise_seed=seed, noise_rel=1e-12)
+    perm, offsets = synth.random_partition(n, 8, 3000, 7000, seed=seed)
+    sizes = np.diff(offsets)
+    blocks = []
+    pt = torch.from_numpy(perm).cuda()
+    for j in range(8):
+        m = pt[offsets[j]:offsets[j + 1]]
+        Sj = apx.empty_matrix(int(sizes[j]))
+        Sj.copy_(S[m][:, m])
+        blocks.append(Sj)
+    (idxs, subres), ms_sub = _timed(lambda: apx.ap_solve_batched(blocks, damping=0.9, max_iter=2000,
+                                                                    conv_iter=15))
+    sub_bytes = sum(20 * int(sizes[j]) ** 2 * subres[j].iterations for j in range(8))
+    del blocks, idxs
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    (idx, res, subs), ms_pap = _timed(lambda: apx.pap_solve(S, R, A, 8, perm, offsets, damping=0.9,
+                                                            max_iter=2000, conv_iter=15))
+    (idx_c, res_c), ms_cold = _timed(lambda: apx.ap_solve(S, R, A, 0.9, 2000, 15))
+    sub_gbs = sub_bytes / (ms_sub * 1e-3) / 1e9
+    out["pap_c3"] = {
+        "workload": "40000 points, union of 20 random 5-D subspaces of R^100 (noise 0.05), "
+                    "8 random parts of 3000-7000 points, damping 0.9",
+        "part_sizes": [int(x) for x in sizes],
+        "parts_ms": round(ms_sub, 2), "parts_iterations": [r.iterations for r in subres],
+        "parts_GBps": round(sub_gbs, 1), "parts_frac": round(sub_gbs / HBM_PEAK_GBS, 4),
+        "parts_bytes_basis": "20 B per element and iteration (explicit form), each part's own iteration count",
+        "pap_ms": round(ms_pap, 2), "pap_step4_iterations": res.iterations,
+        "pap_netsim": res.netsim, "pap_n_exemplars": res.n_exemplars,
+        "cold_ms": round(ms_cold, 2), "cold_iterations": res_c.iterations,
+        "cold_netsim": res_c.netsim, "cold_n_exemplars": res_c.n_exemplars,
+        "same_exemplars": bool(torch.equal(idx, idx_c)),
+    }
+    del S, R, A, X, idx, idx_c
+    torch.cuda.empty_cache()
+    print("extras: pap done", file=sys.stderr, flush=True)
+
+    # ---- 512 independent instances
+    insts = synth.batch_instances(count=512, seed0=3101)
+    Ss = []
+    for p_ in insts:
+        Xj = torch.from_numpy(p_.X).cuda()
+        Sj, _ = apx.ap_similarity(Xj, pref="median", noise_seed=p_.seed, noise_rel=1e-12)
+        Ss.append(Sj)
+    Rs = [apx.empty_matrix(S_.shape[0]) for S_ in Ss]
+    As = [apx.empty_matrix(S_.shape[0]) for S_ in Ss]
+    apx.ap_solve_batched(Ss, Rs, As, damping=0.5, max_iter=200, conv_iter=15)      # warm-up
+    (idxs, rs), ms_b = _timed(lambda: apx.ap_solve_batched(Ss, Rs, As, damping=0.5, max_iter=200,
+                                                           conv_iter=15))
+    it_sum = sum(r.iterations for r in rs)
+    b_bytes = sum(20 * S_.shape[0] ** 2 * r.iterations for S_, r in zip(Ss, rs))
+    b_gbs = b_bytes / (ms_b * 1e-3) / 1e9
+    out["batch_512"] = {
+        "workload": "512 independent 2-D Gaussian mixtures, n in [100, 2000], 2-20 components, "
+                    "median preference, damping 0.5, at most 200 iterations, one launch",
+        "sum_n2": int(sum(S_.shape[0] ** 2 for S_ in Ss)),
+        "ms": round(ms_b, 2), "instance_iterations": it_sum,
+        "instance_iterations_per_s": round(it_sum / (ms_b * 1e-3), 1),
+        "converged": int(sum(r.converged for r in rs)),
+        "GBps": round(b_gbs, 1), "frac": round(b_gbs / HBM_PEAK_GBS, 4),
+        "bytes_basis": "20 B per element and iteration (explicit form), each instance's own count",
+    }
+    del Ss, Rs, As, idxs
+    torch.cuda.empty_cache()
+    print("extras: batch done", file=sys.stderr, flush=True)
+
+    # ---- LAP, N = 200000
+    n, d, L, seed = 200000, 128, 10000, 4001
+    pts = synth.image_features(n=n, d=d, k=20, seed=seed)
+    M = synth.landmarks(n, L, seed)
+    X = torch.from_numpy(pts.X).cuda()
+    apx.lap_solve(X, L, landmarks=M, seed=seed, damping=0.9)                        # warm-up
+    (idx, res, ex), ms_lap = _timed(lambda: apx.lap_solve(X, L, landmarks=M, seed=seed, damping=0.9))
+    XM = X[torch.from_numpy(M).cuda()].contiguous()
+
+    def landmark_part():
+        SL, _ = apx.ap_similarity(XM, pref="median", noise_seed=seed, noise_rel=1e-12)
+        RL, AL = apx.empty_matrix(L), apx.empty_matrix(L)
+        return apx.ap_solve(SL, RL, AL, 0.9, 2000, 15)
+    landmark_part()
+    (_, rl), ms_land = _timed(landmark_part)
+    ms_assign = max(ms_lap - ms_land, 1e-3)
+    flops = 2.0 * n * res.n_exemplars * d
+    out["lap_c4"] = {
+        "workload": "200000 points in 128-D (20-component mixture, clipped to [-3,3]), 10000 landmarks, "
+                    "damping 0.9",
+        "ms": round(ms_lap, 2), "landmark_ms": round(ms_land, 2), "landmark_iterations": rl.iterations,
+        "n_exemplars": res.n_exemplars, "assign_ms": round(ms_assign, 2),
+        "assign_TFLOPs": round(flops / (ms_assign * 1e-3) / 1e12, 2),
+        "assign_frac_fp32": round(flops / (ms_assign * 1e-3) / 157.3e12, 4),
+        "assign_basis": "2 n |E| d FP32 flops of the distances over the assignment time "
+                        "(lap_solve minus the landmark similarity and AP)",
+    }
+    print("extras: lap done", file=sys.stderr, flush=True)
     return out
 
 
@@ -307,6 +439,9 @@ def main():
                      "bytes_per_launch": per_launch,
                      "traffic_unit": "GB per launch (HBM read + write, counter-measured)"},
     }
+    if not args.no_extras:
+        print("other workloads: PAP N=40000, 512 instances, LAP N=200000 ...", file=sys.stderr, flush=True)
+        out["workloads"] = workload_extras(apx)
     if not args.no_warm_compare:
         print("time to oracle exemplars: cold / PAP / learned ...", file=sys.stderr, flush=True)
         out["time_to_exemplars"] = time_to_exemplars(apx, S, n, SEED)
