@@ -69,6 +69,10 @@ def lib():
     L.apo_finalize.restype = _i64
     L.apo_assign_nearest.argtypes = [_i64, _i64, _f32p, _i64, _i64, _i64p, _i32p,
                                      ctypes.POINTER(_dbl)]
+    L.apo_nearest_of.argtypes = [_i64, _f32p, _i64, _i64, _i64p, _i64, _i64p, _i32p, _f64p]
+    L.apo_pair_dist.argtypes = [_i64, _f32p, _i64, _i64, _i64p, _i64p, _f64p]
+    L.apo_medoid.argtypes = [_i64, _f32p, _i64, _i64, _i64p]
+    L.apo_medoid.restype = _i64
     L.apo_resp_rows.argtypes = [_i64, _f64p, _f64p, _f64p, _dbl, _i64p, _i64, _f64p]
     L.apo_column_sums.argtypes = [_i64, _f64p, _f64p]
     L.apo_avail_rows.argtypes = [_i64, _f64p, _f64p, _f64p, _dbl, _i64p, _i64, _f64p]
@@ -327,6 +331,37 @@ def lap(X: np.ndarray, landmarks: np.ndarray, seed: int = 0, lam: float = 0.9,
     lib().apo_assign_nearest(n, d, X, d, ex.size, ex, idx, ctypes.byref(dp))
     expref = float(prep.pref) * ex.size
     return LAPResult(res, ex, idx, dp.value, expref, dp.value + expref, prep.pref)
+
+
+def nearest_of(X: np.ndarray, query: np.ndarray, cand: np.ndarray):
+    """For every query point (global indices), the nearest candidate point
+    (ascending global indices) by FP64 squared distance, lowest index on
+    ties: (labels int32, distances float64)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    q = np.ascontiguousarray(query, dtype=np.int64)
+    c = np.ascontiguousarray(cand, dtype=np.int64)
+    idx = np.empty(q.size, dtype=np.int32)
+    dist = np.empty(q.size, dtype=np.float64)
+    lib().apo_nearest_of(X.shape[1], X, X.shape[1], q.size, q, c.size, c, idx, dist)
+    return idx, dist
+
+
+def pair_dist(X: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """FP64 squared distances between points a[i] and b[i] (global indices)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    b = np.ascontiguousarray(b, dtype=np.int64)
+    out = np.empty(a.size)
+    lib().apo_pair_dist(X.shape[1], X, X.shape[1], a.size, a, b, out)
+    return out
+
+
+def medoid(X: np.ndarray, members: np.ndarray) -> int:
+    """The member of least summed FP64 squared distance to all members
+    (members ascending global indices; lowest index on ties)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    mem = np.ascontiguousarray(members, dtype=np.int64)
+    return int(lib().apo_medoid(X.shape[1], X, X.shape[1], mem.size, mem))
 
 
 def sqdist(x: np.ndarray, y: np.ndarray) -> float:

@@ -299,6 +299,53 @@ int64_t apo_finalize(int64_t n, const double *S, const int32_t *dec, int32_t *id
 /* index on ties); exemplars label themselves.  Returns the sum of           */
 /* -||x_i - x_idx(i)||^2 over non-exemplars in *dpsim.                       */
 /* ------------------------------------------------------------------------ */
+/* Nearest of the nex candidate points ex (ascending global indices) for each
+ * of the m query points q (global indices), FP64 squared distance, lowest
+ * candidate on ties: idx[i] = the candidate's global index, dist[i] its
+ * distance (Algorithm 3, Step 2 and the reassignment of Step 4). */
+void apo_nearest_of(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *q, int64_t nex,
+                    const int64_t *ex, int32_t *idx, double *dist)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double best = INFINITY; int64_t bk = nex > 0 ? ex[0] : -1;
+        for (int64_t j = 0; j < nex; ++j) {
+            double dd = apo_sqdist(d, X + q[i] * ldx, X + ex[j] * ldx);
+            if (dd < best) { best = dd; bk = ex[j]; }
+        }
+        idx[i] = (int32_t)bk; dist[i] = best;
+    }
+}
+
+/* The medoid of a set of m points (global indices, ascending): the member
+ * whose summed FP64 squared distance to all members (summed in member
+ * order) is least; the lowest index on ties. */
+int64_t apo_medoid(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *members)
+{
+    double *tot = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    if (!tot) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < m; ++q) {
+        double t = 0.0;
+        for (int64_t i = 0; i < m; ++i) t += apo_sqdist(d, X + members[i] * ldx, X + members[q] * ldx);
+        tot[q] = t;
+    }
+    int64_t best = m > 0 ? members[0] : -1;
+    double bt = INFINITY;
+    for (int64_t q = 0; q < m; ++q)
+        if (tot[q] < bt) { bt = tot[q]; best = members[q]; }
+    free(tot);
+    return best;
+}
+
+/* FP64 squared distances of m point pairs (a[i], b[i]), global indices. */
+void apo_pair_dist(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *a, const int64_t *b,
+                   double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) out[i] = apo_sqdist(d, X + a[i] * ldx, X + b[i] * ldx);
+}
+
 void apo_assign_nearest(int64_t n, int64_t d, const float *X, int64_t ldx, int64_t nex,
                         const int64_t *ex /* ascending global indices */, int32_t *idx,
                         double *dpsim)

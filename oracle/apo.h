@@ -43,6 +43,16 @@ void apo_decisions(int64_t n, const double *A, const double *R, int32_t *dec);
 int64_t apo_finalize(int64_t n, const double *S, const int32_t *dec, int32_t *idx,
                      double *dpsim, double *expref, double *netsim);
 
+/* Nearest candidate (FP64 squared distance, lowest index on ties) for m
+ * query points; dist receives the distances. */
+void apo_nearest_of(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *q, int64_t nex,
+                    const int64_t *ex, int32_t *idx, double *dist);
+/* Medoid of m points (ascending global indices): least summed FP64 squared
+ * distance to the members, lowest index on ties. */
+int64_t apo_medoid(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *members);
+/* FP64 squared distances of m point pairs (a[i], b[i]). */
+void apo_pair_dist(int64_t d, const float *X, int64_t ldx, int64_t m, const int64_t *a, const int64_t *b,
+                   double *out);
 /* Nearest-exemplar assignment in FP64 (Algorithm 3, Step 2). */
 void apo_assign_nearest(int64_t n, int64_t d, const float *X, int64_t ldx, int64_t nex,
                         const int64_t *ex, int32_t *idx, double *dpsim);
