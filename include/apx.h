@@ -93,7 +93,9 @@ enum {
     APX_OP_LAP = 5,           /* lap_solve: n points in d dimensions, count landmarks  */
     APX_OP_FEATURES = 6,      /* apx_features: n points                                */
     APX_OP_MLP_BACKWARD = 7,  /* apx_mlp_backward: count points                        */
-    APX_OP_WARMSTART = 8      /* ap_warmstart: n x n, ld                               */
+    APX_OP_WARMSTART = 8,     /* ap_warmstart: n x n, ld                               */
+    APX_OP_LAP_FULL = 9       /* lap_full_solve: n points in d dimensions, count
+                                 landmarks, m0 = ld                                    */
 };
 
 /*
@@ -378,6 +380,54 @@ apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t
                      int64_t n_landmarks, const int64_t *landmarks, uint64_t seed, double noise_rel,
                      int32_t pref_mode, float pref_scalar, const apx_params *params, int32_t *idx,
                      apx_result *res, int64_t *exemplars_out);
+
+/* What the full landmark method did at its top level. */
+typedef struct {
+    int32_t levels;          /* recursion levels run (1: Step 3 needed no recursion) */
+    int32_t step1_centres;   /* |C1|: centres of the landmark AP (Step 1) */
+    int64_t assigned;        /* points Step 2 assigned below their class's max_distance */
+    int64_t unassigned;      /* m: points left for Step 3 */
+    int32_t merged_centres;  /* |C1| plus Step 3's centres */
+    int32_t step3_mode;      /* 0: nothing left, 1: AP on the m points, 2: the method on them */
+    int32_t refined_centres; /* centres after Step 4 (the exemplars) */
+    int32_t pad;
+    double preference;       /* p of the landmark AP, used by every later AP and by expref */
+} apx_lap_stats;
+
+/*
+ * lap_full_solve -- landmark affinity propagation, Section 4, Algorithm 3,
+ * Steps 1-4 (lap_solve is Steps 1-2 without the threshold).
+ *   Step 1: AP on the landmarks (given, or sampled as in lap_solve from
+ *           `seed`): centres C1 and each landmark's class; preference p from
+ *           pref_mode (APX_PREF_MEDIAN: the median of the landmark
+ *           similarities; APX_PREF_SCALAR: pref_scalar).
+ *   Step 2: max_distance(c) = the largest squared Euclidean distance of a
+ *           landmark of class c to c; every other point goes to its nearest
+ *           centre c (exact, lowest index on ties) when its distance is
+ *           strictly below max_distance(c); the m others stay unassigned.
+ *   Step 3: m <= m0: AP on the m points; m > m0: the whole method on them,
+ *           with min(n_landmarks, m0) landmarks drawn uniformly from them (a
+ *           partial Fisher-Yates shuffle driven by the SplitMix64 stream
+ *           seeded with seed + 3 per level); their centres join C1.
+ *   Step 4: every point goes to its nearest merged centre, and each class's
+ *           centre becomes its medoid (least summed FP64 squared distance to
+ *           the class, lowest index on ties).
+ * Finally every point goes to its nearest refined centre; the refined
+ * centres are the exemplars (they label themselves).  Every AP after the
+ * first uses p; tie noise noise_rel with seed + 3l (Step 1), + 1 (Step 3)
+ * at recursion level l.  X: device n x d (ldx), d <= 300, all finite
+ * (else APX_EINVAL).  idx: device, n labels.  res: the landmark AP's
+ * iterations and convergence, |E|, dpsim = -sum of FP64 squared distances
+ * of non-exemplars to their exemplar, expref = |E| p, netsim.  stats (host,
+ * nullable): see apx_lap_stats.  exemplars_out (host, nullable, capacity
+ * n) receives the exemplars ascending.  params->flags:
+ * APX_MSG_THRESHOLD applies to every AP; APX_RAW_LABELS is rejected.
+ * Synchronises.
+ */
+apx_status lap_full_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx, int64_t n_landmarks,
+                          const int64_t *landmarks, uint64_t seed, double noise_rel, int32_t pref_mode,
+                          float pref_scalar, int64_t m0, const apx_params *params, int32_t *idx,
+                          apx_result *res, apx_lap_stats *stats, int64_t *exemplars_out);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start.  The paper starts Algorithm 1 from a(i,k) = 0 (Eq. (1))

@@ -25,7 +25,7 @@ APX_COLD, APX_WARM_A, APX_WARM_AR = range(3)
 APX_MLP_FEATURES, APX_MLP_PARAMS = 16, 18946
 APX_RAW_LABELS, APX_CHECK_FINITE, APX_MSG_THRESHOLD = 1, 2, 4
 (APX_OP_SIMILARITY, APX_OP_ITERATE, APX_OP_SOLVE, APX_OP_SOLVE_BATCHED, APX_OP_PAP, APX_OP_LAP,
- APX_OP_FEATURES, APX_OP_MLP_BACKWARD, APX_OP_WARMSTART) = range(9)
+ APX_OP_FEATURES, APX_OP_MLP_BACKWARD, APX_OP_WARMSTART, APX_OP_LAP_FULL) = range(10)
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTIMPL"}
 
 
@@ -46,6 +46,14 @@ class apx_result(ctypes.Structure):
                 ("n_exemplars", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("dpsim", ctypes.c_double), ("expref", ctypes.c_double),
                 ("netsim", ctypes.c_double)]
+
+
+class apx_lap_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("step1_centres", ctypes.c_int32),
+                ("assigned", ctypes.c_int64), ("unassigned", ctypes.c_int64),
+                ("merged_centres", ctypes.c_int32), ("step3_mode", ctypes.c_int32),
+                ("refined_centres", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("preference", ctypes.c_double)]
 
 
 class apx_instance(ctypes.Structure):
@@ -94,6 +102,9 @@ SIGNATURES = {
     "lap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
                                  _I32, ctypes.c_float, ctypes.POINTER(apx_params), _P,
                                  ctypes.POINTER(apx_result), _P]),
+    "lap_full_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
+                                      _I32, ctypes.c_float, _I64, ctypes.POINTER(apx_params), _P,
+                                      ctypes.POINTER(apx_result), ctypes.POINTER(apx_lap_stats), _P]),
     "apx_features": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P]),
     "apx_mlp_forward": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
     "apx_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P, _P]),
@@ -459,6 +470,34 @@ def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, 
                                 _P(ex.ctypes.data)), "lap_solve")
     r = _res(res)
     return idx, r, ex[: r.n_exemplars].copy()
+
+
+def lap_full_solve(X: torch.Tensor, n_landmarks: int, m0: int = 20000, landmarks=None, seed: int = 0,
+                   noise_rel: float = 1e-12, damping: float = 0.9, max_iter: int = 2000, conv_iter: int = 15,
+                   check_every: int = 0, pref: str | float = "median", flags: int = 0, msg_tol: float = 0.0):
+    """Landmark AP, Algorithm 3 Steps 1-4; returns (idx, Result, exemplar
+    indices, stats dict)."""
+    import numpy as np
+    if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
+        raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
+    n, d = X.shape
+    lm = None if landmarks is None else np.ascontiguousarray(landmarks, dtype=np.int64)
+    if lm is not None and lm.size != n_landmarks:
+        raise ValueError(f"landmarks has {lm.size} entries, expected {n_landmarks}")
+    idx = torch.empty(n, dtype=torch.int32, device=X.device)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, msg_tol)
+    res = apx_result()
+    st = apx_lap_stats()
+    ex = np.zeros(n, dtype=np.int64)
+    mode, scal = (APX_PREF_MEDIAN, 0.0) if isinstance(pref, str) else (APX_PREF_SCALAR, float(pref))
+    ctx = context(X.device)
+    _check(ctx, lib().lap_full_solve(ctx, _P(X.data_ptr()), n, d, X.stride(0), n_landmarks,
+                                     None if lm is None else _P(lm.ctypes.data), seed, noise_rel, mode, scal,
+                                     m0, ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res),
+                                     ctypes.byref(st), _P(ex.ctypes.data)), "lap_full_solve")
+    r = _res(res)
+    stats = {f: getattr(st, f) for f, _ in apx_lap_stats._fields_ if f != "pad"}
+    return idx, r, ex[: r.n_exemplars].copy(), stats
 
 
 # --------------------------------------------------------------------------

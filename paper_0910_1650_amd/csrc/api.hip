@@ -519,6 +519,9 @@ size_t apx_workspace_size(const apx_ctx *ctx, int32_t op, int64_t n, int64_t ld,
         return count >= 1 ? mlp_backward_ws_bytes(count) : 0;
     case APX_OP_WARMSTART:
         return (n >= 2 && ld >= n) ? warmstart_ws_bytes(n, ld, cus) : 0;
+    case APX_OP_LAP_FULL:
+        return (n >= 2 && d >= 1 && count >= 2 && count <= n && ld >= 2) ? lap_full_ws_bytes(n, d, count, ld, cus)
+                                                                          : 0;
     default:
         return 0;
     }

@@ -305,6 +305,7 @@ size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus);
 size_t similarity_ws_bytes(int64_t n);
 size_t pap_ws_bytes(int64_t n, int64_t ld, int32_t k, const int64_t *sizes, int num_cus);
 size_t lap_ws_bytes(int64_t n, int64_t d, int64_t L, int num_cus);
+size_t lap_full_ws_bytes(int64_t n, int64_t d, int64_t L, int64_t m0, int num_cus);
 size_t features_ws_bytes(int64_t n);
 size_t mlp_backward_ws_bytes(int64_t count);
 size_t warmstart_ws_bytes(int64_t n, int64_t ld, int num_cus);
