@@ -271,7 +271,29 @@ def workload_extras(apx) -> dict:
         "assign_basis": "2 n |E| d FP32 flops of the distances over the assignment time "
                         "(lap_solve minus the landmark similarity and AP)",
     }
+    (idxf, rf, exf, stf), ms_full = _timed(lambda: apx.lap_full_solve(X, L, m0=20000, landmarks=M, seed=seed,
+                                                                       damping=0.9))
+    out["lap_full_c4"] = {
+        "workload": "the same 200000 points and landmarks, Algorithm 3 Steps 1-4 with m0 = 20000",
+        "ms": round(ms_full, 2), "n_exemplars": rf.n_exemplars, "netsim": rf.netsim,
+        "netsim_steps_1_2": res.netsim, "stats": stf,
+    }
+    from paper_0910_1650_amd import experiments as ex
+    out["lap_reseed_c4"] = {
+        "workload": "the same points: LAP (Steps 1-2), then twice more with the landmarks re-seeded "
+                    "from the previous run's exemplars plus a fresh uniform sample",
+        "rounds": ex.lap_reseed(X, L, seed=seed, rounds=3),
+    }
     print("extras: lap done", file=sys.stderr, flush=True)
+    del X
+    torch.cuda.empty_cache()
+    # Table 2's protocol and the 2-D size sweep
+    out["size_sweep_2d"] = {
+        "workload": "2-D 10-component mixtures, N = 100..3000 step 100, 10 seeded runs each, "
+                    "AP against PAP with k = 4 (contiguous split), damping 0.9",
+        "rows": ex.size_sweep(),
+    }
+    print("extras: size sweep done", file=sys.stderr, flush=True)
     return out
 
 
@@ -442,6 +464,12 @@ def main():
     if not args.no_extras:
         print("other workloads: PAP N=40000, 512 instances, LAP N=200000 ...", file=sys.stderr, flush=True)
         out["workloads"] = workload_extras(apx)
+        from paper_0910_1650_amd import experiments as ex
+        out["workloads"]["pap_k_sweep"] = {
+            "workload": f"the benchmark matrix (N={n}): AP, then PAP with the paper's contiguous split "
+                        f"for k = 2, 4, 8, 16 (Table 2's protocol)",
+            "rows": ex.pap_k_sweep(S, truth=pts.labels),
+        }
     if not args.no_warm_compare:
         print("time to oracle exemplars: cold / PAP / learned ...", file=sys.stderr, flush=True)
         out["time_to_exemplars"] = time_to_exemplars(apx, S, n, SEED)

@@ -381,6 +381,20 @@ apx_status lap_solve(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t
                      int32_t pref_mode, float pref_scalar, const apx_params *params, int32_t *idx,
                      apx_result *res, int64_t *exemplars_out);
 
+/*
+ * apx_lap_landmarks -- a landmark set for Step 1 of Algorithm 3 that keeps
+ * given points, e.g. a previous run's exemplars (re-seeding the landmarks;
+ * the paper's closing section names a better choice of landmarks as future
+ * work), and fills the rest with a uniform sample without replacement of
+ * the other points: a partial Fisher-Yates shuffle of their positions (in
+ * ascending index order) driven by the SplitMix64 stream seeded with `seed`.
+ * keep: host, n_keep distinct indices in [0, n) (n_keep <= n_landmarks);
+ * out: host, n_landmarks entries, ascending.  Host only (no device work, no
+ * context); EINVAL on bad arguments.
+ */
+apx_status apx_lap_landmarks(int64_t n, int64_t n_landmarks, const int64_t *keep, int64_t n_keep, uint64_t seed,
+                             int64_t *out);
+
 /* What the full landmark method did at its top level. */
 typedef struct {
     int32_t levels;          /* recursion levels run (1: Step 3 needed no recursion) */

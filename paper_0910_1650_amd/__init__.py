@@ -105,6 +105,7 @@ SIGNATURES = {
     "lap_full_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I64, _P, ctypes.c_uint64, ctypes.c_double,
                                       _I32, ctypes.c_float, _I64, ctypes.POINTER(apx_params), _P,
                                       ctypes.POINTER(apx_result), ctypes.POINTER(apx_lap_stats), _P]),
+    "apx_lap_landmarks": (ctypes.c_int, [_I64, _I64, _P, _I64, ctypes.c_uint64, _P]),
     "apx_features": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P]),
     "apx_mlp_forward": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
     "apx_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P, _P]),
@@ -470,6 +471,19 @@ def lap_solve(X: torch.Tensor, n_landmarks: int, landmarks=None, seed: int = 0, 
                                 _P(ex.ctypes.data)), "lap_solve")
     r = _res(res)
     return idx, r, ex[: r.n_exemplars].copy()
+
+
+def apx_lap_landmarks(n: int, n_landmarks: int, keep=None, seed: int = 0):
+    """Landmark set keeping `keep` (e.g. previous exemplars) plus a uniform
+    sample of the other points (host only); ascending int64 array."""
+    import numpy as np
+    kp = np.zeros(0, dtype=np.int64) if keep is None else np.ascontiguousarray(keep, dtype=np.int64)
+    out = np.zeros(n_landmarks, dtype=np.int64)
+    st = lib().apx_lap_landmarks(n, n_landmarks, _P(kp.ctypes.data) if kp.size else None, kp.size, seed,
+                                 _P(out.ctypes.data))
+    if st != APX_OK:
+        raise ApxError(st, "apx_lap_landmarks: bad arguments")
+    return out
 
 
 def lap_full_solve(X: torch.Tensor, n_landmarks: int, m0: int = 20000, landmarks=None, seed: int = 0,

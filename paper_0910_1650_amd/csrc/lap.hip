@@ -943,3 +943,27 @@ extern "C" apx_status lap_full_solve(apx_ctx *ctx, const float *X, int64_t n, in
     }
     return APX_OK;
 }
+
+// Landmark set for Step 1 of Algorithm 3 from given points (a previous run's
+// exemplars, say) plus a uniform sample of the others (host only).
+extern "C" apx_status apx_lap_landmarks(int64_t n, int64_t n_landmarks, const int64_t *keep, int64_t n_keep,
+                                        uint64_t seed, int64_t *out) {
+    if (n < 1 || n_landmarks < 1 || n_landmarks > n || n_keep < 0 || n_keep > n_landmarks || !out ||
+        (n_keep > 0 && !keep))
+        return APX_EINVAL;
+    std::vector<char> kept(n, 0);
+    for (int64_t i = 0; i < n_keep; ++i) {
+        if (keep[i] < 0 || keep[i] >= n || kept[keep[i]]) return APX_EINVAL;
+        kept[keep[i]] = 1;
+    }
+    std::vector<int64_t> rest;
+    rest.reserve(n - n_keep);
+    for (int64_t i = 0; i < n; ++i)
+        if (!kept[i]) rest.push_back(i);
+    const std::vector<int64_t> pos = sample_positions((int64_t)rest.size(), n_landmarks - n_keep, seed);
+    std::vector<int64_t> M(keep, keep + n_keep);
+    for (int64_t p : pos) M.push_back(rest[p]);
+    std::sort(M.begin(), M.end());
+    std::memcpy(out, M.data(), sizeof(int64_t) * (size_t)n_landmarks);
+    return APX_OK;
+}
