@@ -14,6 +14,7 @@
 // FP64 in a fixed order and the stop rule (member 0), a team barrier.  The
 // host waits for the one launch; no iteration is driven from the host.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -535,9 +536,19 @@ int occupancy_of(int J) {
 namespace {
 
 // Workgroups per compute unit of the persistent launch (at most; fewer when
-// the kernel's occupancy is lower), and the least work per team member.
+// the kernel's occupancy is lower), and the fewest rows a team member
+// takes (a row costs a few microseconds of latency; two team barriers per
+// iteration cost about as much as a few rows).  APX_BATCH_WPC and
+// APX_BATCH_MIN_ROWS override them (tuning runs).
 constexpr int kMaxWpc = 4;
-constexpr double kMinMemberElems = 131072.0;
+constexpr int kMinMemberRows = 8;
+
+int env_int(const char *name, int dflt, int lo, int hi) {
+    const char *v = getenv(name);
+    if (!v || !v[0]) return dflt;
+    const int x = atoi(v);
+    return x < lo ? lo : (x > hi ? hi : x);
+}
 
 struct BatchPlan {
     int J, wpc, G;
@@ -551,9 +562,9 @@ struct BatchPlan {
 };
 
 // Teams: with no more instances than workgroups, each instance gets its own
-// team, sized in proportion to its n^2 (at least one workgroup, at most one
-// per row, and no member with fewer than kMinMemberElems elements per
-// iteration unless the team is one workgroup), scaled so the teams fill
+// team, sized in proportion to its n^2 (at least one workgroup, and no
+// member with fewer than kMinMemberRows rows unless the team is one
+// workgroup), scaled so the teams fill
 // the grid; all instances then run at once.  With more instances than
 // workgroups, every team is one workgroup and the instances are dealt to
 // the workgroups largest first, each to the least loaded one.
@@ -575,11 +586,11 @@ BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc) 
     }
     std::vector<std::vector<Task>> per(G);
     P.nbars = 0;
+    const int min_rows = env_int("APX_BATCH_MIN_ROWS", kMinMemberRows, 1, 1 << 20);
     if (count <= G) {
         auto gmax = [&](int j) -> int64_t {
-            int64_t m = (int64_t)(cost[j] / kMinMemberElems);
-            if (m < 1) m = 1;
-            return m < spec[j].n ? m : spec[j].n;
+            const int64_t m = spec[j].n / min_rows;
+            return m < 1 ? 1 : m;
         };
         auto sizes = [&](double x, std::vector<int32_t> &g) -> int64_t {
             int64_t sum = 0;
@@ -671,7 +682,8 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
     if (J > 12) return set_err(ctx, APX_ENOTIMPL, "batched instances are limited to n <= %d", 12 * 4 * BT);
     int wpc = occupancy_of(J);
     if (wpc < 1) return set_err(ctx, APX_EDEVICE, "no occupancy for the batched kernel");
-    wpc = wpc < kMaxWpc ? wpc : kMaxWpc;
+    const int cap = env_int("APX_BATCH_WPC", kMaxWpc, 1, kMaxWpc);
+    wpc = wpc < cap ? wpc : cap;
     BatchPlan P = make_plan(count, spec, ctx->num_cus, wpc);
     apx_status st = ws_reserve(ctx, ctx->ws_base + P.bytes);
     if (st != APX_OK) return st;
