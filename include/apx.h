@@ -161,6 +161,16 @@ apx_status apx_set_implicit_a(apx_ctx *ctx, int32_t list_capacity, int64_t min_n
 apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *explicit_iters,
                                int32_t *implicit_a_iters);
 
+/* apx_last_fallback -- why the last ap_solve on this context left an
+ * implicit form and continued with explicit messages (0: it did not): an OR
+ * of APX_FALLBACK_R_LIST (a row's list of ever-argmax columns was full),
+ * APX_FALLBACK_R_OWNER (a new list column would have given one thread of the
+ * implicit-R pass more listed columns than it keeps in registers) and
+ * APX_FALLBACK_A_LIST (a row's list of ever-positive responsibilities was
+ * full).  Diagnostic only; results do not depend on it. */
+enum { APX_FALLBACK_R_LIST = 1, APX_FALLBACK_A_LIST = 2, APX_FALLBACK_R_OWNER = 4 };
+apx_status apx_last_fallback(apx_ctx *ctx, int32_t *reasons);
+
 /* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP
  * graph (enable = 1, the default; the environment variable APX_GRAPHS=0
  * turns it off at context creation) or launch every kernel from the host

@@ -80,6 +80,7 @@ SIGNATURES = {
     "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
     "apx_set_implicit_a": (ctypes.c_int, [_P, _I32, _I64]),
     "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "apx_last_fallback": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     "apx_autotune": (ctypes.c_int, [_P, _I64]),
     "apx_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_tune_set": (ctypes.c_int, [_P, _I64, _I32, _I32, _I32]),
@@ -336,6 +337,17 @@ def apx_last_solve_info(device=None) -> tuple[int, int, int]:
     _check(ctx, lib().apx_last_solve_info(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "apx_last_solve_info")
     return a.value, b.value, c.value
+
+
+APX_FALLBACK_R_LIST, APX_FALLBACK_A_LIST, APX_FALLBACK_R_OWNER = 1, 2, 4
+
+
+def apx_last_fallback(device=None) -> int:
+    """Why the last ap_solve left an implicit form (OR of APX_FALLBACK_*; 0: it did not)."""
+    ctx = context(device)
+    a = _I32()
+    _check(ctx, lib().apx_last_fallback(ctx, ctypes.byref(a)), "apx_last_fallback")
+    return a.value
 
 
 def apx_set_graphs(enable: bool, device=None) -> None:

@@ -1113,7 +1113,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
             beta_out[ii] = beta1;
             if (ovf) {
                 cnt_out[ii] = -1;
-                atomicOr(&p.st->imp_abort, 1);
+                atomicOr(&p.st->imp_abort, cnt >= p.kmax ? 1 : 4);
             } else {
                 for (int qq = 0; qq < cnt; ++qq) col_out[(int64_t)ii * IMP_K + qq] = st_col[sl][qq];
                 if (pos1 < 0) col_out[(int64_t)ii * IMP_K + cnt] = k1;
@@ -1365,7 +1365,7 @@ template <int T, int J, bool GP>
 __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
 #pragma clang fp contract(off)
     constexpr int NW = T / 64;
-    constexpr int NOWN = 2;                      // overflow rule shared with k_row_imp
+    constexpr int NOWN = 2;                      // listed columns per owner in k_row_imp
     constexpr int EPT = (IMP_KA + T - 1) / T;    // exception-list entries per thread
     static_assert(IMP_K <= 64, "R-list holders are lanes of wavefront 0");
 
@@ -1822,7 +1822,13 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const int pos1 = bk1 ? __builtin_ctzll(bk1) : -1;                  // wavefront 0
         const int k1_owner = (k1 >> 2) % T;
         const int k1_owner_has = __popcll(__ballot(rk >= 0 && ((rk >> 2) % T) == k1_owner));
-        const bool ovf = pos1 < 0 && (cnt >= p.kmax || k1_owner_has >= NOWN);   // wavefront 0
+        // Only a full list overflows here: listed columns are handled by
+        // their holders, not their owners.  A list that the implicit-R pass
+        // could not take over (an owner with more than NOWN listed columns)
+        // is noted in the run state, so that a fallback from implicit A
+        // makes R explicit too.
+        const bool ovf = pos1 < 0 && cnt >= p.kmax;                        // wavefront 0
+        if (tid == 0 && pos1 < 0 && !ovf && k1_owner_has >= NOWN) atomicOr(&p.st->imp_owner, 1);
         // r_{t+1} of this lane's list entry, and of k1 when it joins the list
         // (its s: one load, rare once the lists settle)
         const float rl1 = (lam * rg + oml * rs) - (tid == pos1 ? m_self : m_other);

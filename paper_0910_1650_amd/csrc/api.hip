@@ -566,6 +566,12 @@ apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *e
     return APX_OK;
 }
 
+apx_status apx_last_fallback(apx_ctx *ctx, int32_t *reasons) {
+    if (!ctx || !reasons) return APX_EINVAL;
+    *reasons = ctx->last_fallback;
+    return APX_OK;
+}
+
 apx_status apx_set_graphs(apx_ctx *ctx, int enable) {
     if (!ctx) return APX_EINVAL;
     ctx->graphs = enable != 0;
@@ -660,6 +666,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
     int32_t ia_until = imp_a ? INT32_MAX : 0;       // last iteration run with implicit A
+    int32_t fallback = 0;                           // imp_abort bits of the fallbacks
     if (implicit) {
         // parity 0 holds R_0 = 0: beta = 0 and empty lists
         const ImpLayout il = imp_layout(n);
@@ -768,13 +775,18 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             // vectors are rebuilt and the run continues with explicit messages.
             const int32_t ta = hst->iter;
             const int po = (ta + 1) & 1;
+            fallback |= hst->imp_abort;
+            // implicit R cannot continue without implicit A when a row list
+            // breaks the implicit-R pass's owner rule
+            const bool r_too = (hst->imp_abort & 5) || (imp_a && implicit && hst->imp_owner);
+            if (imp_a && implicit && hst->imp_owner && !(hst->imp_abort & 5)) fallback |= APX_FALLBACK_R_OWNER;
             if (imp_a) {
                 HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[ta & 1], w.adiag[ta & 1],
                                               w.xst + (ta & 1) * w.xstride, s), "materialize A");
                 imp_a = false;
                 ia_until = ta;
             }
-            if (hst->imp_abort & 1) {
+            if (r_too) {
                 // alpha_{t_a+1} is the run state's current alpha after the reduce of pass t_a
                 HIP_TRY(launch_imp_materialize(S, buf[po], ld, (int32_t)n, &w.st->imp_al,
                                                w.imp + po * w.imp_stride, s), "materialize R");
@@ -794,6 +806,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     ctx->last_imp_iters = imp_until < T ? imp_until : T;
     ctx->last_exp_iters = T - ctx->last_imp_iters;
     ctx->last_ia_iters = ia_until < T ? ia_until : T;
+    ctx->last_fallback = fallback;
     if (imp_a) {
         HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[T & 1], w.adiag[T & 1],
                                       w.xst + (T & 1) * w.xstride, s), "materialize A");

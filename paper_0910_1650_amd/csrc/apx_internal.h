@@ -25,7 +25,7 @@ struct ApState {
     int32_t max_iter;
     int32_t conv_iter;
     int32_t last_nex;   // |E| of the last completed iteration
-    int32_t imp_abort;  // bit 0: an implicit-R row list overflowed; bit 1: an implicit-A list did
+    int32_t imp_abort;  // bit 0: an implicit-R row list was full; bit 2: its owner rule; bit 1: an implicit-A list was full
     float imp_lam;      // damping of the run
     float imp_al;       // alpha_t for the next full pass t (1 - lambda^t)
     float imp_al1;      // alpha_{t+1}
@@ -37,7 +37,8 @@ struct ApState {
     uint32_t d_r;       // max |r_t - r_{t-1}| (from pass t-1)
     int32_t msg_on;     // 1: stop once both changes are <= msg_tol (t >= 2)
     float msg_tol;
-    int32_t pad[3];
+    int32_t imp_owner;  // 1: an implicit-A pass let a thread own more listed R columns than k_row_imp keeps
+    int32_t pad[2];
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -267,6 +268,7 @@ struct apx_ctx {
     int implicit_a = apx::IMP_KA;     // implicit-A exception list capacity (0 = explicit A)
     int64_t implicit_a_min_n = 4096;  // smaller cold starts run explicit (faster there)
     int32_t last_ia_iters = 0;        // iterations of the last ap_solve run with implicit A
+    int32_t last_fallback = 0;        // why the last ap_solve left an implicit form (imp_abort bits)
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
     std::vector<apx::TuneEntry> tune;
