@@ -1256,10 +1256,14 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
 // and each thread zeroes its own bytes of row i-1's slot after it, two
 // barriers before the slot is set again.
 // GP: the partials accumulate in the workgroup's global partial row (rows too
-// long for LDS); the reduction barrier orders LDS only, so there every
-// column's partial is formed by the column owner.
+// long for LDS), added by the same threads; the reduction barrier orders LDS
+// only, so a wavefront that added to them releases its stores before the
+// next row's barrier (a wait for its outstanding memory operations, which
+// by then are the next row's S, needed by the scan anyway) and every
+// wavefront acquires after it.
 constexpr int NXS = 4;
 constexpr int kMaxDynLdsIa = 160 * 1024 - 4 * 1024;
+
 
 __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) << 3) + (k & 3)); }
 
@@ -1640,7 +1644,16 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         float smax = kNegInf;   // largest s of the thread's columns that phase 2 leaves to it
         int l1 = -1;
         uint32_t fch = 0;       // chunks holding a first positive responsibility
-        bool has_sp = false;    // the thread owns a special column (GP phase 2)
+        // longer rows: acol_t chunks stream from L2, one chunk ahead of use
+        // (a load waited on at once per chunk serialises J latencies); at
+        // J > 7 the extra registers spill and loading at use is faster
+        constexpr int APF = (ACV || J > 7) ? 0 : 1;
+        float4 avq[APF + 1];
+        if constexpr (!ACV) {
+#pragma unroll
+            for (int j = 0; j < APF && j < J; ++j)
+                if (j < J - 1 || last_in) avq[j] = ld4(acol_t + c0 + j * T * 4);
+        }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (!(j < J - 1 || last_in)) continue;
@@ -1648,15 +1661,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             const int c = c0 + j * T * 4;
             const float4 sv = s4[j];
             float4 av;
-            if constexpr (ACV) av = acv[j];
-            else av = ld4(acol_t + c);
+            if constexpr (ACV) {
+                av = acv[j];
+            } else {
+                if (j + APF < J && (j + APF < J - 1 || last_in))
+                    avq[(j + APF) % (APF + 1)] = ld4(acol_t + c0 + (j + APF) * T * 4);
+                av = avq[j % (APF + 1)];
+            }
             // out-of-range columns of the last chunk count as listed
             const uint32_t mb = mb8[j * T + tid] | (full ? 0u : oob_bits);
-            has_sp = has_sp || (mb8[j * T + tid] >> 4) != 0u;
             // columns of this chunk below the diagonal beat it with a tie
             // (the diagonal's own chunk is finished after the scan)
             const float dth = c + 3 < ii ? D : Dn;
-            bool fr = false;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float s = f4get(sv, e);
@@ -1664,7 +1680,6 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 // listed in either list (or out of range): one mask test
                 const bool lst = (mb & (0x11u << e)) != 0u;
                 const bool pos = r > 0.0f;
-                if constexpr (GP) fr = fr || (pos && !lst);
                 // ordinary with r <= 0: A is the column value
                 const bool ord = !(lst || pos);
                 const float a = ord ? f4get(av, e) : kNegInf;
@@ -1677,15 +1692,12 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 // largest s of the ordinary columns (positive r included):
                 // r = al s - beta is monotone in s, so it tells whether the
                 // thread holds a first positive, and bounds phase 2's values
-                if constexpr (GP) smax = max3f(smax, (full || c + e < n) ? s : kNegInf);
-                else smax = max3f(smax, lst ? kNegInf : s);
+                smax = max3f(smax, lst ? kNegInf : s);
             }
-            if constexpr (GP) fch |= fr ? (1u << j) : 0u;
         }
         // a first positive somewhere in the thread's ordinary columns: every
         // chunk is searched (rare once the lists settle)
-        if constexpr (!GP)
-            fch = (al * smax - beta > 0.0f) ? ((1u << J) - 1u) & (last_in ? ~0u : ~(1u << (J - 1))) : 0u;
+        fch = (al * smax - beta > 0.0f) ? ((1u << J) - 1u) & (last_in ? ~0u : ~(1u << (J - 1))) : 0u;
         Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
         auto merge = [&](float v, float w, int k) {
             fl = fl || (k < ii ? v >= D : v > D);
@@ -1796,6 +1808,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         __builtin_amdgcn_sched_barrier(0);
 
         wg_top2<NW>(t2, sh_v[i & 1], sh_i[i & 1], lane, wave);
+        // the previous row's additions to global partials are visible
+        if constexpr (GP) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "global");
         if (tid == 0) {
             const uint8_t ef = (uint8_t)(dec_fail[xs] == 0);
             if (ef_prev != ef) my_changed = 1;
@@ -1866,99 +1880,78 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
 
         // ---- column partials of max(0, R_{t+1}), one addition per row and
-        // column, in row order.
-        if constexpr (!GP) {
-            // LDS partials: special columns and listed ones by their holders
-            // (the reduction barrier orders the adds of consecutive rows)
-            if (rk >= 0) {
-                const float r = rl1;
-                if (rk == ii) p.rdiag[ii] = r;
-                else if (r > 0.0f) lp[rk] = lp[rk] + r;
+        // column, in row order: special columns and listed ones by their
+        // holders, the rest by their owners.  The reduction barrier orders
+        // the additions of consecutive rows (LDS partials); with global
+        // partials a wavefront that added makes its stores visible before
+        // the next row's barrier (release below, acquire after the reduction).
+        bool added = false;
+        auto padd = [&](int k, float r) {
+            if constexpr (GP) P[k] = P[k] + r;
+            else lp[k] = lp[k] + r;
+            added = true;
+        };
+        if (rk >= 0) {
+            const float r = rl1;
+            if (rk == ii) p.rdiag[ii] = r;
+            else if (r > 0.0f) padd(rk, r);
+        }
+        if (tid == 0) {
+            if (pos1 < 0) {
+                // a new list column
+                const float r = k1_r1;
+                if (k1 == ii) p.rdiag[ii] = r;
+                else if (r > 0.0f) padd(k1, r);
             }
-            if (tid == 0) {
-                if (pos1 < 0) {
-                    // a new list column
-                    const float r = k1_r1;
-                    if (k1 == ii) p.rdiag[ii] = r;
-                    else if (r > 0.0f) lp[k1] = lp[k1] + r;
-                }
-                if (!rl_diag && !(pos1 < 0 && k1 == ii)) p.rdiag[ii] = al1 * sdg - beta1;
-            }
+            if (!rl_diag && !(pos1 < 0 && k1 == ii)) p.rdiag[ii] = al1 * sdg - beta1;
+        }
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const int k = cur_c[u];
-                if ((unsigned)k < (unsigned)n && !xrl[u] && k != k1) {
-                    const float r = al1 * xsv[u] - beta1;
-                    if (r > 0.0f) lp[k] = lp[k] + r;
-                }
+        for (int u = 0; u < EPT; ++u) {
+            const int k = cur_c[u];
+            if ((unsigned)k < (unsigned)n && !xrl[u] && k != k1) {
+                const float r = al1 * xsv[u] - beta1;
+                if (r > 0.0f) padd(k, r);
             }
-            // ordinary elements: a positive value needs al1 s - beta1 > 0,
-            // which is monotone in s, so only threads whose largest ordinary
-            // s passes reread their chunks (from L2)
-            const bool hot = al1 * smax - beta1 > 0.0f;
-            if (__any(hot)) {
-                if (hot) {
-                    const float *srow = p.S + i * ld;
+        }
+        // ordinary elements: a positive value needs al1 s - beta1 > 0,
+        // which is monotone in s, so only threads whose largest ordinary
+        // s passes reread their chunks (from L2)
+        const bool hot = al1 * smax - beta1 > 0.0f;
+        if (__any(hot)) {
+            if (hot) {
+                const float *srow = p.S + i * ld;
 #pragma unroll 1
-                    for (int j = 0; j < J; ++j) {
-                        if (!(j < J - 1 || last_in)) continue;
-                        const int c = c0 + j * T * 4;
-                        const float4 sv = ld4(srow + c);
-                        const uint32_t mb = mb8[j * T + tid];
-                        if (mb == 0u && (k1 >> 2) != (c >> 2) && c + 3 < n) {
-                            // no listed column and not k1's chunk: no other
-                            // thread adds to these columns in this row
-                            float4 a4 = lpart[c >> 2];
-                            a4.x = (al1 * sv.x - beta1 > 0.0f) ? a4.x + (al1 * sv.x - beta1) : a4.x;
-                            a4.y = (al1 * sv.y - beta1 > 0.0f) ? a4.y + (al1 * sv.y - beta1) : a4.y;
-                            a4.z = (al1 * sv.z - beta1 > 0.0f) ? a4.z + (al1 * sv.z - beta1) : a4.z;
-                            a4.w = (al1 * sv.w - beta1 > 0.0f) ? a4.w + (al1 * sv.w - beta1) : a4.w;
-                            lpart[c >> 2] = a4;
-                            continue;
-                        }
-                        const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
-                        for (int e = 0; e < 4; ++e) {
-                            const int k = c + e;
-                            const float r = al1 * f4get(sv, e) - beta1;
-                            if (k < n && !((ex >> e) & 1u) && k != k1 && r > 0.0f) lp[k] = lp[k] + r;
-                        }
+                for (int j = 0; j < J; ++j) {
+                    if (!(j < J - 1 || last_in)) continue;
+                    const int c = c0 + j * T * 4;
+                    const float4 sv = ld4(srow + c);
+                    const uint32_t mb = mb8[j * T + tid];
+                    if (mb == 0u && (k1 >> 2) != (c >> 2) && c + 3 < n) {
+                        // no listed column and not k1's chunk: no other
+                        // thread adds to these columns in this row
+                        float4 a4;
+                        if constexpr (GP) a4 = ld4(P + c);
+                        else a4 = lpart[c >> 2];
+                        a4.x = (al1 * sv.x - beta1 > 0.0f) ? a4.x + (al1 * sv.x - beta1) : a4.x;
+                        a4.y = (al1 * sv.y - beta1 > 0.0f) ? a4.y + (al1 * sv.y - beta1) : a4.y;
+                        a4.z = (al1 * sv.z - beta1 > 0.0f) ? a4.z + (al1 * sv.z - beta1) : a4.z;
+                        a4.w = (al1 * sv.w - beta1 > 0.0f) ? a4.w + (al1 * sv.w - beta1) : a4.w;
+                        if constexpr (GP) st4(P + c, a4);
+                        else lpart[c >> 2] = a4;
+                        added = true;
+                        continue;
+                    }
+                    const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = c + e;
+                        const float r = al1 * f4get(sv, e) - beta1;
+                        if (k < n && !((ex >> e) & 1u) && k != k1 && r > 0.0f) padd(k, r);
                     }
                 }
             }
-        } else {
-            // global partials: every column by its owner (no ordering between
-            // threads is needed), rereading S
-            const bool hot = al1 * smax - beta1 > 0.0f || has_sp || k1_owner == tid;
-            if (__any(hot)) {
-                if (hot) {
-                    const float *srow = p.S + i * ld;
-#pragma unroll 1
-                    for (int j = 0; j < J; ++j) {
-                        if (!(j < J - 1 || last_in)) continue;
-                        const int c = c0 + j * T * 4;
-                        const float4 sv = ld4(srow + c);
-                        const uint32_t sp = mb8[j * T + tid] >> 4;
-                        for (int e = 0; e < 4; ++e) {
-                            const int k = c + e;
-                            if (k >= n) break;
-                            const float s = f4get(sv, e);
-                            float r = al1 * s - beta1;
-                            bool listed = false;
-                            if ((sp >> e) & 1u) {
-                                for (int qq = 0; qq < cnt; ++qq) {
-                                    if (st_col[sl][qq] == k) {
-                                        r = (lam * st_gam[sl][qq] + oml * s) - (k == k1 ? m_self : m_other);
-                                        listed = true;
-                                    }
-                                }
-                            }
-                            if (!listed && k == k1) r = (lam * (al * s - beta) + oml * s) - m_self;
-                            if (k == ii) p.rdiag[ii] = r;
-                            else if (r > 0.0f) P[k] = P[k] + r;
-                        }
-                    }
-                }
-            }
+        }
+        if constexpr (GP) {
+            if (__any(added)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "global");
         }
 
         // Overflowing rows (at most once per run), written explicitly with
