@@ -67,7 +67,15 @@ enum {
 enum {
     APX_COLD = 0,     /* A_0 = 0 (Eq. (1)) and R_0 = 0; A, R are outputs only */
     APX_WARM_A = 1,   /* A holds A_0 on entry (e.g. PAP's A'); R_0 = 0 */
-    APX_WARM_AR = 2   /* A and R hold A_0 and R_0 on entry */
+    APX_WARM_AR = 2,  /* A and R hold A_0 and R_0 on entry */
+    APX_WARM_COLUMNS = 3  /* A holds a column-structured A_0 (every off-diagonal
+                             element of a column equal, as apx_warm_a0 and
+                             ap_warmstart write it) and R_0 is the undamped
+                             Eq. (2) step from it, which the solve forms itself
+                             (R is not read); R_1 = R_0, since damping a
+                             message towards itself leaves it unchanged.  Runs
+                             with implicit R (alpha_t = 1) and implicit A from
+                             A_0's column vectors where cold starts do */
 };
 
 typedef struct apx_ctx apx_ctx;
@@ -167,8 +175,10 @@ apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *e
  * APX_FALLBACK_R_OWNER (a new list column would have given one thread of the
  * implicit-R pass more listed columns than it keeps in registers) and
  * APX_FALLBACK_A_LIST (a row's list of ever-positive responsibilities was
- * full).  Diagnostic only; results do not depend on it. */
-enum { APX_FALLBACK_R_LIST = 1, APX_FALLBACK_A_LIST = 2, APX_FALLBACK_R_OWNER = 4 };
+ * full).  APX_NOTE_R_OWNER (no fallback by itself) says that the implicit-A
+ * pass let a row list break that owner rule, so a fallback of A would have
+ * made R explicit too.  Diagnostic only; results do not depend on it. */
+enum { APX_FALLBACK_R_LIST = 1, APX_FALLBACK_A_LIST = 2, APX_FALLBACK_R_OWNER = 4, APX_NOTE_R_OWNER = 8 };
 apx_status apx_last_fallback(apx_ctx *ctx, int32_t *reasons);
 
 /* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libapx.so")
 
 APX_OK, APX_EINVAL, APX_ENOMEM, APX_EDEVICE, APX_ENOTIMPL = range(5)
 APX_PREF_MEDIAN, APX_PREF_SCALAR, APX_PREF_VECTOR = range(3)
-APX_COLD, APX_WARM_A, APX_WARM_AR = range(3)
+APX_COLD, APX_WARM_A, APX_WARM_AR, APX_WARM_COLUMNS = range(4)
 APX_MLP_FEATURES, APX_MLP_PARAMS = 16, 18946
 APX_RAW_LABELS, APX_CHECK_FINITE, APX_MSG_THRESHOLD = 1, 2, 4
 (APX_OP_SIMILARITY, APX_OP_ITERATE, APX_OP_SOLVE, APX_OP_SOLVE_BATCHED, APX_OP_PAP, APX_OP_LAP,
@@ -339,7 +339,7 @@ def apx_last_solve_info(device=None) -> tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
-APX_FALLBACK_R_LIST, APX_FALLBACK_A_LIST, APX_FALLBACK_R_OWNER = 1, 2, 4
+APX_FALLBACK_R_LIST, APX_FALLBACK_A_LIST, APX_FALLBACK_R_OWNER, APX_NOTE_R_OWNER = 1, 2, 4, 8
 
 
 def apx_last_fallback(device=None) -> int:
@@ -611,7 +611,8 @@ def apx_warm_a0(Y: torch.Tensor, sigma: torch.Tensor, A: torch.Tensor) -> torch.
 
 def ap_warmstart(S: torch.Tensor, theta: torch.Tensor, R: torch.Tensor, A: torch.Tensor,
                  sigma: torch.Tensor | None = None):
-    """Predicted (R_0, A_0) for ap_solve(..., warm=APX_WARM_AR); returns sigma."""
+    """Predicted (R_0, A_0) for ap_solve(..., warm=APX_WARM_AR), or A_0 alone for
+    warm=APX_WARM_COLUMNS (column-structured; the solve forms R_0); returns sigma."""
     Sp, n, ld = _mat(S, "S")
     Rp, _, ldr = _mat(R, "R", n)
     Ap, _, lda = _mat(A, "A", n)

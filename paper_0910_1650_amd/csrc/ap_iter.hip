@@ -616,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
         // alphas of the implicit-R passes t+1 and t+2 (the pass just run was t)
         st->imp_al_prev = st->imp_al;
         st->imp_al = st->imp_al1;
-        st->imp_al1 = imp_alpha(st->imp_lam, t + 2);
+        st->imp_al1 = st->imp_alpha_one ? 1.0f : imp_alpha(st->imp_lam, t + 2);
         const int run = same ? st->run + 1 : 1;
         st->iter = t;
         st->run = run;
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
 }
 
 __global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, int msg_on,
-                             float msg_tol) {
+                             float msg_tol, int alpha_one) {
     if (threadIdx.x == 0) {
         ApState s{};
         s.max_iter = max_iter;
@@ -650,11 +650,21 @@ __global__ void k_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, f
         s.msg_on = msg_on;
         s.msg_tol = msg_tol;
         s.imp_lam = lam;
-        s.imp_al = imp_alpha(lam, 1);
-        s.imp_al1 = imp_alpha(lam, 2);
+        s.imp_alpha_one = alpha_one;
+        s.imp_al = alpha_one ? 1.0f : imp_alpha(lam, 1);
+        s.imp_al1 = alpha_one ? 1.0f : imp_alpha(lam, 2);
         s.imp_al_prev = 0.0f;
         *st = s;
     }
+}
+
+// Column vectors of a column-structured A_0 (n >= 2): acol[k] = a_0(r,k)
+// with r = 0 (r = 1 for k = 0), adiag[k] = a_0(k,k).
+__global__ void k_extract_cols(const float *A, int64_t ld, int32_t n, float *acol, float *adiag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    acol[k] = A[(k == 0 ? ld : 0) + k];
+    adiag[k] = A[(int64_t)k * ld + k];
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
@@ -2249,8 +2259,14 @@ hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s,
-                             int msg_on, float msg_tol) {
-    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter, lam, msg_on, msg_tol);
+                             int msg_on, float msg_tol, int alpha_one) {
+    k_state_init<<<1, 64, 0, s>>>(st, max_iter, conv_iter, lam, msg_on, msg_tol, alpha_one);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_cols(const float *A, int64_t ld, int32_t n, float *acol, float *adiag, hipStream_t s) {
+    const int g = (n + 255) / 256;
+    k_extract_cols<<<g > 0 ? g : 1, 256, 0, s>>>(A, ld, n, acol, adiag);
     return hipGetLastError();
 }
 

@@ -616,7 +616,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     APX_TRY(check_matrix(ctx, R, "R", n, ld));
     APX_TRY(check_matrix(ctx, A, "A", n, ld));
     if (!params || !res || !idx) return set_err(ctx, APX_EINVAL, "params, idx and res must be non-null");
-    if (warm < APX_COLD || warm > APX_WARM_AR) return set_err(ctx, APX_EINVAL, "bad warm mode %d", warm);
+    if (warm < APX_COLD || warm > APX_WARM_COLUMNS) return set_err(ctx, APX_EINVAL, "bad warm mode %d", warm);
     APX_TRY(check_params(ctx, params));
     const float lam = params->damping;
     const bool raw_labels = (params->flags & APX_RAW_LABELS) != 0;
@@ -649,8 +649,9 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
+    const bool cols = warm == APX_WARM_COLUMNS;
     HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, lam, s, msg_rule ? 1 : 0,
-                              params->msg_tol), "state init");
+                              params->msg_tol, cols ? 1 : 0), "state init");
     HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
 
     // R_t lives in buf[t & 1]; buf[0] is the caller's R.  With R_0 = 0 (cold
@@ -661,7 +662,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     PassPlan ipl{}, apl{};
     // the message-change rule needs both messages in memory: explicit form
     const bool r_ok = !msg_rule && ctx->implicit_k > 0 && warm != APX_WARM_AR && imp_plan(n, ctx->num_cus, &ipl);
-    bool imp_a = r_ok && warm == APX_COLD && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
+    bool imp_a = r_ok && (warm == APX_COLD || cols) && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
                  ia_plan(n, ctx->num_cus, &apl);
     bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
@@ -673,12 +674,16 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         HIP_TRY(launch_fill_f32_rows(reinterpret_cast<float *>(w.imp + il.beta), 1, n, n, 0.0f, s),
                 "implicit state");
         HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.imp + il.cnt), 4 * n, 0, s), "implicit state");
-        const ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, true, ctx->implicit_k);
+        // R_1: the damped step from R_0 = 0 and A_0; with A_0 column-structured
+        // the undamped step (damping 0, alpha_1 = 1 in the run state), which
+        // is R_0 itself
+        const ImpArgs ia = imp_args(S, A, n, ld, cols ? 0.0f : lam, w, buf, true, ctx->implicit_k);
         HIP_TRY(launch_row_imp(ipl, warm == APX_COLD ? IMP_PRO_COLD : IMP_PRO_WARM, ia, s), "prologue");
         if (imp_a) {
-            // A_0 = 0: both column vectors zero, every exception list empty
+            // A_0 = 0 (or A_0's column vectors): every exception list empty
             HIP_TRY(launch_fill_f32_rows(w.acol[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
             HIP_TRY(launch_fill_f32_rows(w.adiag[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
+            if (cols) HIP_TRY(launch_extract_cols(A, ld, (int32_t)n, w.acol[0], w.adiag[0], s), "implicit A");
             HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.xst + x_layout(n).cnt), 4 * n, 0, s),
                     "implicit A");
         } else if (warm == APX_COLD) {
@@ -690,6 +695,12 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             // R_1 from R_0 = A_0 = 0, then A_0 = 0 in memory (Eq. (1)).
             HIP_TRY(launch_row_pass(pl, PASS_R_COLD, pr, s), "prologue");
             HIP_TRY(launch_fill_f32_rows(A, n, n, ld, 0.0f, s), "A_0");
+        } else if (cols) {
+            // R_1 = R_0: the undamped step from A_0 (damping 0 on R = 0)
+            HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R_0");
+            PassArgs pu = pr;
+            pu.lam = 0.0f;
+            HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pu, s), "prologue");
         } else {
             if (warm == APX_WARM_A) HIP_TRY(launch_fill_f32_rows(R, n, n, ld, 0.0f, s), "R_0");
             HIP_TRY(launch_row_pass(pl, PASS_R_ONLY, pr, s), "prologue");
@@ -806,7 +817,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     ctx->last_imp_iters = imp_until < T ? imp_until : T;
     ctx->last_exp_iters = T - ctx->last_imp_iters;
     ctx->last_ia_iters = ia_until < T ? ia_until : T;
-    ctx->last_fallback = fallback;
+    ctx->last_fallback = fallback | (hst->imp_owner ? APX_NOTE_R_OWNER : 0);
     if (imp_a) {
         HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[T & 1], w.adiag[T & 1],
                                       w.xst + (T & 1) * w.xstride, s), "materialize A");

@@ -38,7 +38,8 @@ struct ApState {
     int32_t msg_on;     // 1: stop once both changes are <= msg_tol (t >= 2)
     float msg_tol;
     int32_t imp_owner;  // 1: an implicit-A pass let a thread own more listed R columns than k_row_imp keeps
-    int32_t pad[2];
+    int32_t imp_alpha_one;  // 1: alpha_t = 1 for every t (R_0 is the undamped Eq. (2) step, not 0)
+    int32_t pad[1];
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -104,7 +105,9 @@ PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds);
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s);
 hipError_t launch_col_reduce(const ColArgs &a, hipStream_t s);
 hipError_t launch_state_init(ApState *st, int32_t max_iter, int32_t conv_iter, float lam, hipStream_t s,
-                             int msg_on = 0, float msg_tol = 0.0f);
+                             int msg_on = 0, float msg_tol = 0.0f, int alpha_one = 0);
+// acol[k] = A(r,k) for one r != k, adiag[k] = A(k,k) (column-structured A_0)
+hipError_t launch_extract_cols(const float *A, int64_t ld, int32_t n, float *acol, float *adiag, hipStream_t s);
 // flag |= 1 if any of the n x n entries of M (leading dimension ld) is NaN or
 // infinite; flag |= 1 likewise for the rows x cols entries of X (ldx).
 hipError_t launch_check_finite(const float *M, int64_t rows, int64_t cols, int64_t ld, int32_t *flag,

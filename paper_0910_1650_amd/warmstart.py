@@ -29,7 +29,7 @@ import time
 import numpy as np
 import torch
 
-from . import (APX_MLP_PARAMS, APX_WARM_AR, ap_similarity, ap_solve, ap_warmstart, apx_features,
+from . import (APX_MLP_PARAMS, APX_WARM_COLUMNS, ap_similarity, ap_solve, ap_warmstart, apx_features,
                apx_mlp_adam, apx_mlp_backward, apx_targets, empty_matrix, pap_solve)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -158,7 +158,7 @@ def solve_warm(S, theta, damping=0.9, max_iter=2000, conv_iter=15):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ap_warmstart(S, theta, R, A)
-    idx, res = ap_solve(S, R, A, damping, max_iter, conv_iter, warm=APX_WARM_AR)
+    idx, res = ap_solve(S, R, A, damping, max_iter, conv_iter, warm=APX_WARM_COLUMNS)
     total = res.iterations
     fell_back = degenerate(res, n)
     if fell_back:

@@ -17,6 +17,10 @@
 * A_0: bit-exact (FP32 products).
 * ap_warmstart end to end, and the warm-started solve's exemplar set against
   the oracle's warm-started run from its own A_0.
+* The column-structured start (APX_WARM_COLUMNS: implicit R with alpha = 1
+  and, from 4096 points, implicit A from A_0's column vectors) against the
+  oracle's run from the same A_0 and its undamped Eq. (2) step R_0: stop
+  iteration, exemplar set, labels and net similarity.
 """
 import numpy as np
 import pytest
@@ -226,4 +230,40 @@ def test_warmstart_end_to_end_and_solve():
     say(f"  warm iterations gpu {res.iterations} oracle {ref.iterations}; |E| {res.n_exemplars}")
     assert res.converged and ref.converged
     assert np.array_equal(np.flatnonzero(idx.cpu().numpy() == np.arange(n)), ref.exemplars)
+    assert abs(res.netsim - ref.netsim) <= n * 1e-6 * rng
+
+
+@pytest.mark.parametrize("n", [1500, 6000])
+def test_warm_columns_solve(n):
+    seed = 910 + n
+    say(f"warm columns n={n}")
+    pts = synth.gaussian_mixture(n=n, d=16, k=15, seed=seed)
+    S = oracle.prepare(oracle.similarity(pts.X), "median", seed=seed).S.astype(np.float32).astype(np.float64)
+    theta = synth.mlp_params(901, bias_std=0.3)
+    Sd = dev(S)
+    R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+    apx.ap_warmstart(Sd, t32(theta), R, A)
+    A0 = host(A)
+    # column-structured: every off-diagonal element equals its column's value
+    off = A0.copy()
+    np.fill_diagonal(off, np.nan)
+    assert np.all(np.nanmax(off, axis=0) == np.nanmin(off, axis=0))
+    R.fill_(float("nan"))                        # R is not read
+    idx, res = apx.ap_solve(Sd, R, A, 0.9, 2000, 15, warm=apx.APX_WARM_COLUMNS)
+    imp, exp, ia = apx.apx_last_solve_info()
+    why = apx.apx_last_fallback()
+    say(f"  gpu iterations {res.iterations} (implicit R {imp}, explicit {exp}, implicit A {ia}, fallback {why})")
+    if n >= 4096:
+        # implicit R throughout; implicit A until a row collects more
+        # ever-positive responsibilities than its list holds (this random
+        # network's A_0 makes many positive in the first step)
+        assert imp == res.iterations and exp == 0 and ia >= 1
+        assert why & ~(apx.APX_FALLBACK_A_LIST | apx.APX_NOTE_R_OWNER) == 0
+    R0 = oracle.resp_rows(S, A0, np.zeros_like(S), 0.0, np.arange(n))
+    ref = oracle.ap(S, 0.9, 2000, 15, A0=A0, R0=R0)
+    say(f"  oracle iterations {ref.iterations}; |E| gpu {res.n_exemplars} oracle {ref.exemplars.size}")
+    rng = S.max() - S.min()
+    assert res.converged and ref.converged
+    assert res.iterations == ref.iterations
+    assert np.array_equal(idx.cpu().numpy(), ref.idx)
     assert abs(res.netsim - ref.netsim) <= n * 1e-6 * rng
