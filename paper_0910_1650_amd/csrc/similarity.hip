@@ -4,8 +4,8 @@
 //
 // The Gram part runs on FP32 matrix cores (v_mfma_f32_32x32x2f32, FP32
 // accumulate).  Only tiles on or above the block diagonal are computed; each
-// result is written at (i,k) and mirrored to (k,i), so S is exactly
-// symmetric.  The preference is the median of the n(n-1) off-diagonal
+// result is written at (i,k) and mirrored to (k,i) from the accumulators,
+// so S is exactly symmetric.  The preference is the median of the n(n-1) off-diagonal
 // entries, found exactly by a three-pass radix select over the upper
 // triangle (which holds every off-diagonal value twice by symmetry).
 #include <cmath>
@@ -50,6 +50,14 @@ struct SimArgs {
     uint32_t *minmax;     // [0] = min key, [1] = max key of off-diagonal entries
 };
 
+// One 128 x 128 tile per workgroup.  X rows are staged through LDS one K
+// chunk at a time, the next chunk's global loads in flight during the
+// current chunk's MFMAs; the epilogue writes S straight from the
+// accumulators (no LDS tile, so four workgroups fit a CU): lane l of
+// block (x, y) holds column c = l mod 32 and rows 8g + 4(l / 32) + q
+// (g, q = 0..3), written directly (one float per row, 128-byte row
+// segments per half wavefront) and mirrored (the four rows q are
+// consecutive columns of S's row c: one float4).
 __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
     // Decode the upper-triangle tile (bi <= bj) from the linear block index.
     const int64_t T = a.tiles_per_side;
@@ -61,11 +69,9 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
     const int64_t bj = bi + t;
     const int64_t row0 = bi * BM, col0 = bj * BM;
 
-    __shared__ float smem[BM * (BM + 1)];          // 66 KB: staging, then the C tile
-    __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
     constexpr int LDA = BM + 1;                     // padded: conflict-free transposed stores
-    float *As = smem;                               // [KB][LDA]
-    float *Bs = smem + KB * LDA;                    // [KB][LDA]
+    __shared__ float As[KB * LDA], Bs[KB * LDA];    // 33 KB of staging
+    __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     for (int e = tid; e < BM; e += NT) {
@@ -81,11 +87,10 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.0f;
 
-    for (int64_t k0 = 0; k0 < a.d; k0 += KB) {
-        // Stage X[row0 .. +BM, k0 .. +KB] and X[col0 .. +BM, k0 .. +KB], k-major:
-        // every load of the chunk in flight first, then the LDS stores.
-        constexpr int SU = BM * KB / NT;
-        float va[SU], vb[SU];
+    // X[row0 .. +BM, k0 .. +KB] and X[col0 .. +BM, k0 .. +KB] into registers
+    constexpr int SU = BM * KB / NT;
+    float va[SU], vb[SU];
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int e = tid + u * NT;
@@ -95,6 +100,10 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             va[u] = (ra < a.n && kg < a.d) ? a.X[ra * a.ldx + kg] : 0.0f;
             vb[u] = (rb < a.n && kg < a.d) ? a.X[rb * a.ldx + kg] : 0.0f;
         }
+    };
+    fetch(0);
+    for (int64_t k0 = 0; k0 < a.d; k0 += KB) {
+        // staged k-major; the previous chunk's MFMAs are done (barrier below)
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int e = tid + u * NT;
@@ -103,6 +112,7 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             Bs[kk * LDA + m] = vb[u];
         }
         __syncthreads();
+        if (k0 + KB < a.d) fetch(k0 + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 2) {
             const int kr = kk + (lane >> 5);
@@ -120,70 +130,61 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
         __syncthreads();
     }
 
-    // Gram tile to LDS: C[m][c] with a padded stride.
-    constexpr int LDC = BM + 1;
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    const bool diag_tile = (bi == bj);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 2; ++y) {
+            const int c = wn * 64 + y * 32 + (lane & 31);   // tile column
+            const int64_t k = col0 + c;
+            const float ncc = nc[c];
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int m = wm * 64 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int c = wn * 64 + y * 32 + (lane & 31);
-                smem[m * LDC + c] = acc[x][y][v];
-            }
-    __syncthreads();
-
-    uint32_t kmin = 0xffffffffu, kmax = 0u;
-    const bool diag_tile = (bi == bj);
-    // Direct tile, four columns per store: rows row0+m, columns col0+c.  On a
-    // diagonal tile the value at (m,c) is taken from the upper entry
-    // min/max(m,c) so it is symmetric.  The diagonal element itself gets a
-    // value too; the preference pass overwrites it.
-    for (int e = tid; e < BM * BM / 4; e += NT) {
-        const int m = e / (BM / 4), c = (e % (BM / 4)) * 4;
-        const int64_t i = row0 + m, k = col0 + c;
-        if (i >= a.n || k >= a.n) continue;
-        float v[4];
+            for (int g = 0; g < 4; ++g) {
+                const int mb = wm * 64 + x * 32 + 8 * g + 4 * (lane >> 5);   // first of four rows
+                const int64_t ib = row0 + mb;
+                float v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float g = smem[m * LDC + c + q];
-            if (diag_tile && m > c + q) g = smem[(c + q) * LDC + m];
-            v[q] = 2.0f * g - (nr[m] + nc[c + q]);
-            if (k + q < a.n && i != k + q && (!diag_tile || m < c + q)) {
-                const uint32_t key = fkey(v[q]);
-                kmin = min(kmin, key);
-                kmax = max(kmax, key);
-            }
-        }
-        float *dst = a.S + i * a.ld + k;
-        if (k + 3 < a.n) {
-            *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
+                for (int q = 0; q < 4; ++q) v[q] = 2.0f * acc[x][y][4 * g + q] - (nr[mb + q] + ncc);
+                if (k >= a.n) continue;
+                if (!diag_tile) {
+                    // every (i, k) here has i < k: direct, mirror, bounds
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (k + q < a.n) dst[q] = v[q];
-        }
-    }
-    if (!diag_tile) {
-        // Mirror, four rows per store: S[col0+c][row0+m..m+3] = s(row0+m.., col0+c).
-        for (int e = tid; e < BM * BM / 4; e += NT) {
-            const int c = e / (BM / 4), m = (e % (BM / 4)) * 4;
-            const int64_t i = row0 + m, k = col0 + c;
-            if (i >= a.n || k >= a.n) continue;
-            float v[4];
+                    for (int q = 0; q < 4; ++q) {
+                        if (ib + q < a.n) {
+                            a.S[(ib + q) * a.ld + k] = v[q];
+                            const uint32_t key = fkey(v[q]);
+                            kmin = min(kmin, key);
+                            kmax = max(kmax, key);
+                        }
+                    }
+                    float *dst = a.S + k * a.ld + ib;
+                    if (ib + 3 < a.n) {
+                        *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = 2.0f * smem[(m + q) * LDC + c] - (nr[m + q] + nc[c]);
-            float *dst = a.S + k * a.ld + i;
-            if (i + 3 < a.n) {
-                *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-            } else {
+                        for (int q = 0; q < 4; ++q)
+                            if (ib + q < a.n) dst[q] = v[q];
+                    }
+                } else {
+                    // diagonal tile: the upper entries (m < c) are written at
+                    // (m, c) and (c, m), so S is symmetric; the diagonal gets
+                    // a value that the preference pass overwrites
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i + q < a.n) dst[q] = v[q];
+                    for (int q = 0; q < 4; ++q) {
+                        const int m = mb + q;
+                        if (ib + q >= a.n || m > c) continue;
+                        a.S[(ib + q) * a.ld + k] = v[q];
+                        if (m < c) {
+                            a.S[k * a.ld + ib + q] = v[q];
+                            const uint32_t key = fkey(v[q]);
+                            kmin = min(kmin, key);
+                            kmax = max(kmax, key);
+                        }
+                    }
+                }
             }
         }
-    }
     // Block min/max of the upper off-diagonal entries: wavefronts, then the
     // tile, then one atomic per bound, skipped when it cannot change the value
     // (all tiles update the same two words).
@@ -426,6 +427,67 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
     }
 }
 
+// Median mode, last select pass fused with the tie noise: every row is read
+// once; upper-triangle entries are counted for the last digit (their values
+// before noise), every off-diagonal entry gets its noise, and the diagonal
+// is left for k_pref_diag once the median is known.  The noise scale needs
+// only the off-diagonal range (the median lies inside it).
+__global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned long long *hist) {
+    extern __shared__ uint32_t hsh[];
+    constexpr int pass = 2;
+    int shift, bits;
+    uint32_t hmask;
+    sel_digit(pass, shift, bits, hmask);
+    const uint32_t nb = 1u << bits;
+    for (uint32_t b = threadIdx.x; b < 2 * nb; b += blockDim.x) hsh[b] = 0u;
+    __syncthreads();
+    const uint32_t p0 = a.sel->prefix[0], p1 = a.sel->prefix[1];
+    const bool same = p0 == p1;
+    uint32_t *const h0 = hsh;
+    uint32_t *const h1 = hsh + nb;
+    const double scale = a.noise_rel * ((double)keyf(a.minmax[1]) - (double)keyf(a.minmax[0]));
+    for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+        float *row = a.S + i * a.ld;
+        auto one = [&](int64_t k, float v) -> float {
+            if (k > i) {
+                const uint32_t key = fkey(v);
+                const uint32_t dig = (key >> shift) & (nb - 1u);
+                if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
+                if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
+            }
+            return k == i ? v : (float)((double)v + scale * noise_u(a.seed, a.n, i, k));
+        };
+        for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.n; k += 4 * (int64_t)blockDim.x) {
+            if (k + 3 < a.n) {
+                float4 v = *reinterpret_cast<const float4 *>(row + k);
+                v.x = one(k, v.x);
+                v.y = one(k + 1, v.y);
+                v.z = one(k + 2, v.z);
+                v.w = one(k + 3, v.w);
+                *reinterpret_cast<float4 *>(row + k) = v;
+            } else {
+                for (int64_t q = k; q < a.n; ++q) row[q] = one(q, row[q]);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const uint32_t c0 = h0[b], c1 = same ? c0 : h1[b];
+        if (c0) atomicAdd(&hist[b], (unsigned long long)c0);
+        if (c1) atomicAdd(&hist[SEL_BINS + b], (unsigned long long)c1);
+    }
+}
+
+// The diagonal after the fused pass: s(i,i) = p (+ its noise).
+__global__ void k_pref_diag(PrefArgs a, const double *range) {
+    const double pm = median_of(a);
+    const double scale = a.noise_rel * (*range);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double base = pref_of(a, i, pm);
+        a.S[i * a.ld + i] = a.noise_rel > 0.0 ? (float)(base + scale * noise_u(a.seed, a.n, i, i)) : (float)base;
+    }
+}
+
 }  // namespace
 }  // namespace apx
 
@@ -509,22 +571,34 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     const int64_t ntiles = sa.tiles_per_side * (sa.tiles_per_side + 1) / 2;
     k_sim_gemm<<<(unsigned)ntiles, NT, 0, s>>>(sa);
     HIP_TRY(hipGetLastError(), "similarity gemm");
+    PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1]};
     if (pref_mode == APX_PREF_MEDIAN) {
+        // three digit passes over the upper triangle; with noise the last
+        // one also adds the noise to every off-diagonal entry
         const int g = (int)(n - 1 < 2048 ? n - 1 : 2048);
         for (int pass = 0; pass < 3; ++pass) {
             const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
-            k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist);
+            if (pass == 2 && noise_rel > 0.0) {
+                const int gn = (int)(n < 8192 ? n : 8192);
+                k_sel_hist_noise<<<gn, 256, lds, s>>>(pa, hist);
+            } else {
+                k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist);
+            }
             HIP_TRY(hipGetLastError(), "select histogram");
             k_sel_pick<<<1, 256, 0, s>>>(sel, pass, hist);
             HIP_TRY(hipGetLastError(), "select pick");
         }
+        k_pref_range<<<1, 256, 0, s>>>(pa, &dvals[0]);
+        HIP_TRY(hipGetLastError(), "preference range");
+        k_pref_diag<<<(unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), 256, 0, s>>>(pa, &dvals[0]);
+        HIP_TRY(hipGetLastError(), "preference");
+    } else {
+        k_pref_range<<<1, 256, 0, s>>>(pa, &dvals[0]);
+        HIP_TRY(hipGetLastError(), "preference range");
+        const int g = (int)(n < 8192 ? n : 8192);
+        k_pref_noise<<<g, 256, 0, s>>>(pa, &dvals[0]);
+        HIP_TRY(hipGetLastError(), "preference/noise");
     }
-    PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1]};
-    k_pref_range<<<1, 256, 0, s>>>(pa, &dvals[0]);
-    HIP_TRY(hipGetLastError(), "preference range");
-    const int g = (int)(n < 8192 ? n : 8192);
-    k_pref_noise<<<g, 256, 0, s>>>(pa, &dvals[0]);
-    HIP_TRY(hipGetLastError(), "preference/noise");
     // The bounds of the off-diagonal keys tell whether a similarity overflowed
     // (a key at or beyond the one of +inf or -inf: infinities and NaNs).
     double *h = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 1024);
