@@ -213,6 +213,38 @@ apx_status apx_tune_set(apx_ctx *ctx, int64_t n, int32_t threads, int32_t lds, i
  * variant that actually runs at this n. */
 apx_status apx_tune_get(apx_ctx *ctx, int64_t n, int32_t *threads, int32_t *lds, int32_t *check_every,
                         double *ms_per_iter);
+/*
+ * Message forms of a cold (or column-structured warm) ap_solve:
+ * APX_FORM_EXPLICIT (R and A in memory, 20 bytes per element and iteration),
+ * APX_FORM_IMPLICIT_R (R kept implicitly, 12 bytes) and APX_FORM_IMPLICIT_RA
+ * (R and A implicit, 4 bytes).  Without a tuned form the solve picks by size
+ * (apx_set_implicit, apx_set_implicit_a).  The forms agree to rounding, not
+ * bit for bit, so a tuned form can change results at the rounding level.
+ */
+enum { APX_FORM_DEFAULT = 0, APX_FORM_EXPLICIT = 1, APX_FORM_IMPLICIT_R = 2, APX_FORM_IMPLICIT_RA = 3 };
+/* apx_autotune_form -- time the three forms on a synthetic problem of n
+ * points (a 16-D Gaussian mixture built on the device: S, R and A of n x n
+ * are allocated and freed; a few short solves per form) and keep the
+ * fastest per iteration for the bucket of n.  form (nullable) receives the
+ * pick, ms (nullable, 3 doubles) the measured ms per iteration of each. */
+apx_status apx_autotune_form(apx_ctx *ctx, int64_t n, int32_t *form, double *ms);
+/* apx_tune_set_form -- set the form of the bucket of n by hand
+ * (APX_FORM_DEFAULT clears it). */
+apx_status apx_tune_set_form(apx_ctx *ctx, int64_t n, int32_t form);
+/* apx_tune_get_form -- the form recorded for n (APX_FORM_DEFAULT if none)
+ * and, if ms is non-null, the 3 measured ms per iteration (0 if not timed). */
+apx_status apx_tune_get_form(apx_ctx *ctx, int64_t n, int32_t *form, double *ms);
+/* apx_autotune_batched -- time the plans of the persistent batched launch
+ * (ap_solve_batched, pap_solve's Step 2) for a batch of `count` instances of
+ * sizes[j] points (host) on scratch instances of those sizes (allocated and
+ * freed: 3 n x n matrices each), over workgroups per compute unit 1..4 and
+ * 2, 8 or 32 rows at least per team member, and keep the fastest for
+ * batches of that shape (the bit lengths of count and of the largest n).
+ * Outputs (nullable): the pick and its time for 12 iterations.  Plans group
+ * the column partial sums differently, so a tuned plan changes results at
+ * the rounding level. */
+apx_status apx_autotune_batched(apx_ctx *ctx, int32_t count, const int64_t *sizes, int32_t *wpc,
+                                int32_t *min_rows, double *ms);
 /* apx_tune_clear -- forget every entry (back to the default plans). */
 apx_status apx_tune_clear(apx_ctx *ctx);
 /* apx_tune_save / apx_tune_load -- the context's entries as JSON (path: host
@@ -348,9 +380,11 @@ typedef struct {
 
 /*
  * ap_solve_batched -- Algorithm 1 on `count` independent instances of uneven
- * size (inst: host array) in one launch per half-iteration: a ragged table of
- * row blocks covers every instance, each instance keeps its own stop rule and
- * stops independently.  Per instance the arithmetic is that of ap_solve;
+ * size (inst: host array) in one persistent cooperative launch: each
+ * instance gets a team of workgroups (sized in proportion to its n^2; with
+ * more instances than workgroups, instances are dealt to single workgroups
+ * largest first), teams meet at device-side barriers, and each instance
+ * keeps its own stop rule and stops independently.  Per instance the arithmetic is that of ap_solve;
  * only the grouping of the FP32 column partial sums differs (rows are split
  * into blocks differently), so results agree with ap_solve to rounding.
  * The results are deterministic.  res (host, count).  Instances need

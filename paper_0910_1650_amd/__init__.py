@@ -87,6 +87,11 @@ SIGNATURES = {
     "apx_tune_get": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                     ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
     "apx_tune_clear": (ctypes.c_int, [_P]),
+    "apx_autotune_form": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
+    "apx_tune_set_form": (ctypes.c_int, [_P, _I64, _I32]),
+    "apx_autotune_batched": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                            ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
+    "apx_tune_get_form": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
     "apx_tune_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "apx_tune_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "apx_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
@@ -380,6 +385,42 @@ def apx_tune_get(n: int, device=None) -> dict:
     _check(ctx, lib().apx_tune_get(ctx, n, ctypes.byref(t), ctypes.byref(l), ctypes.byref(c),
                                    ctypes.byref(ms)), "apx_tune_get")
     return dict(threads=t.value, lds=bool(l.value), check_every=c.value, ms_per_iter=ms.value)
+
+
+APX_FORM_DEFAULT, APX_FORM_EXPLICIT, APX_FORM_IMPLICIT_R, APX_FORM_IMPLICIT_RA = range(4)
+
+
+def apx_autotune_form(n: int, device=None) -> dict:
+    """Time the three message forms at n (synthetic problem) and keep the fastest."""
+    ctx = context(device)
+    f = _I32()
+    ms = (ctypes.c_double * 3)()
+    _check(ctx, lib().apx_autotune_form(ctx, n, ctypes.byref(f), ms), "apx_autotune_form")
+    return dict(form=f.value, ms=list(ms))
+
+
+def apx_autotune_batched(sizes, device=None) -> dict:
+    """Time the batched launch plans for a batch of these sizes and keep the fastest."""
+    ctx = context(device)
+    arr = (_I64 * len(sizes))(*[int(x) for x in sizes])
+    w, m = _I32(), _I32()
+    ms = ctypes.c_double()
+    _check(ctx, lib().apx_autotune_batched(ctx, len(sizes), arr, ctypes.byref(w), ctypes.byref(m), ctypes.byref(ms)),
+           "apx_autotune_batched")
+    return dict(wpc=w.value, min_rows=m.value, ms=ms.value)
+
+
+def apx_tune_set_form(n: int, form: int, device=None) -> None:
+    ctx = context(device)
+    _check(ctx, lib().apx_tune_set_form(ctx, n, form), "apx_tune_set_form")
+
+
+def apx_tune_get_form(n: int, device=None) -> dict:
+    ctx = context(device)
+    f = _I32()
+    ms = (ctypes.c_double * 3)()
+    _check(ctx, lib().apx_tune_get_form(ctx, n, ctypes.byref(f), ms), "apx_tune_get_form")
+    return dict(form=f.value, ms=list(ms))
 
 
 def apx_tune_clear(device=None) -> None:

@@ -645,8 +645,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     }
 
     PassPlan pl{};
-    int tuned_chunk = 0;
-    APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk));
+    int tuned_chunk = 0, tuned_form = 0;
+    APX_TRY(ctx_plan(ctx, n, &pl, &tuned_chunk, true, &tuned_form));
     IterWs w{};
     APX_TRY(iter_ws(ctx, n, ld, true, pl, w));
     const bool cols = warm == APX_WARM_COLUMNS;
@@ -665,6 +665,17 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     bool imp_a = r_ok && (warm == APX_COLD || cols) && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
                  ia_plan(n, ctx->num_cus, &apl);
     bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
+    // a tuned (or, while the tuner times forms, forced) message form replaces
+    // the size thresholds where the start allows it
+    if (tuned_form == APX_FORM_EXPLICIT) {
+        imp_a = implicit = false;
+    } else if (tuned_form == APX_FORM_IMPLICIT_R) {
+        imp_a = false;
+        implicit = r_ok;
+    } else if (tuned_form == APX_FORM_IMPLICIT_RA) {
+        imp_a = r_ok && (warm == APX_COLD || cols) && ctx->implicit_a > 0 && ia_plan(n, ctx->num_cus, &apl);
+        implicit = r_ok;
+    }
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
     int32_t ia_until = imp_a ? INT32_MAX : 0;       // last iteration run with implicit A
     int32_t fallback = 0;                           // imp_abort bits of the fallbacks

@@ -238,8 +238,21 @@ struct TuneEntry {
     int lds;            // 1: LDS-resident variant
     int check_every;    // host poll interval of the stop flag
     double ms_per_iter; // measured (row pass + column reduce)
+    // message form of cold starts (apx_autotune_form): 0 = size thresholds,
+    // APX_FORM_EXPLICIT / _IMPLICIT_R / _IMPLICIT_RA; measured ms per
+    // iteration of each form (0 = not measured)
+    int form = 0;
+    double form_ms[3] = {0.0, 0.0, 0.0};
 };
 int64_t tune_bucket(int64_t n);
+// Tuned plan of the persistent batched launch for batches of one shape
+// (bit lengths of the instance count and of the largest n).
+struct BatchTune {
+    int32_t count_bits, n_bits;
+    int32_t wpc;        // workgroups per compute unit
+    int32_t min_rows;   // fewest rows per team member
+    double ms;          // measured time of the timed iterations
+};
 
 }  // namespace apx
 
@@ -274,6 +287,9 @@ struct apx_ctx {
     int32_t last_fallback = 0;        // why the last ap_solve left an implicit form (imp_abort bits)
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
+    int force_form = 0;               // form timing in progress: the form every solve uses
+    std::vector<apx::BatchTune> btune;  // tuned batched plans (apx_autotune_batched)
+    int force_bwpc = 0, force_bmin = 0;   // batched plan timing in progress
     std::vector<apx::TuneEntry> tune;
     // benchmark timing of full row passes (apx_profile)
     bool prof = false;
@@ -332,7 +348,8 @@ apx_status set_err(apx_ctx *ctx, apx_status st, const char *fmt, ...);
 // Row-pass plan for n on this context: the default plan with the tuned
 // workgroup size and variant applied (tuning first if enabled and unseen);
 // *check_every (nullable) receives the tuned poll interval or 0.
-apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune = true);
+apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune = true,
+                    int *form = nullptr);
 // ap_iterate's argument checks, and its launches (column vectors t, c,
 // r(k,k) and the partials [pl.grid][round4(n)] in caller-given memory).
 apx_status check_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, const float *R, const float *A,

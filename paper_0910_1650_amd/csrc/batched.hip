@@ -14,6 +14,7 @@
 // FP64 in a fixed order and the stop rule (member 0), a team barrier.  The
 // host waits for the one launch; no iteration is driven from the host.
 #include <algorithm>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -543,6 +544,22 @@ namespace {
 constexpr int kMaxWpc = 4;
 constexpr int kMinMemberRows = 8;
 
+int bit_length(int64_t v) {
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+const BatchTune *find_batch_tune(const apx_ctx *ctx, int32_t count, int64_t max_n) {
+    const int cb = bit_length(count), nb = bit_length(max_n);
+    for (const BatchTune &t : ctx->btune)
+        if (t.count_bits == cb && t.n_bits == nb) return &t;
+    return nullptr;
+}
+
 int env_int(const char *name, int dflt, int lo, int hi) {
     const char *v = getenv(name);
     if (!v || !v[0]) return dflt;
@@ -568,7 +585,7 @@ struct BatchPlan {
 // the grid; all instances then run at once.  With more instances than
 // workgroups, every team is one workgroup and the instances are dealt to
 // the workgroups largest first, each to the least loaded one.
-BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc) {
+BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc, int min_rows) {
     BatchPlan P;
     int64_t max_n = 0;
     for (int j = 0; j < count; ++j) max_n = spec[j].n > max_n ? spec[j].n : max_n;
@@ -586,7 +603,6 @@ BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc) 
     }
     std::vector<std::vector<Task>> per(G);
     P.nbars = 0;
-    const int min_rows = env_int("APX_BATCH_MIN_ROWS", kMinMemberRows, 1, 1 << 20);
     if (count <= G) {
         auto gmax = [&](int j) -> int64_t {
             const int64_t m = spec[j].n / min_rows;
@@ -666,8 +682,9 @@ BatchPlan make_plan(int32_t count, const BatchSpec *spec, int num_cus, int wpc) 
 }  // namespace
 
 size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus) {
-    // an upper bound: the plan at the largest workgroups per CU
-    return make_plan(count, spec, num_cus, kMaxWpc).bytes;
+    // an upper bound: the plan at the largest workgroups per CU and the
+    // largest teams (one row per member at least)
+    return make_plan(count, spec, num_cus, kMaxWpc, 1).bytes;
 }
 
 // Host driver shared by ap_solve_batched and pap_solve (Step 2): the
@@ -682,9 +699,21 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
     if (J > 12) return set_err(ctx, APX_ENOTIMPL, "batched instances are limited to n <= %d", 12 * 4 * BT);
     int wpc = occupancy_of(J);
     if (wpc < 1) return set_err(ctx, APX_EDEVICE, "no occupancy for the batched kernel");
-    const int cap = env_int("APX_BATCH_WPC", kMaxWpc, 1, kMaxWpc);
+    // plan: tuned for this batch shape if known (apx_autotune_batched), the
+    // environment (APX_BATCH_WPC, APX_BATCH_MIN_ROWS) over that, the tuner's
+    // candidate while it times
+    int cap = kMaxWpc, min_rows = kMinMemberRows;
+    const BatchTune *bt = find_batch_tune(ctx, count, max_n);
+    if (bt) {
+        cap = bt->wpc;
+        min_rows = bt->min_rows;
+    }
+    cap = env_int("APX_BATCH_WPC", cap, 1, kMaxWpc);
+    min_rows = env_int("APX_BATCH_MIN_ROWS", min_rows, 1, 1 << 20);
+    if (ctx->force_bwpc) cap = ctx->force_bwpc;
+    if (ctx->force_bmin) min_rows = ctx->force_bmin;
     wpc = wpc < cap ? wpc : cap;
-    BatchPlan P = make_plan(count, spec, ctx->num_cus, wpc);
+    BatchPlan P = make_plan(count, spec, ctx->num_cus, wpc, min_rows);
     apx_status st = ws_reserve(ctx, ctx->ws_base + P.bytes);
     if (st != APX_OK) return st;
     char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
@@ -776,3 +805,115 @@ apx_status batched_solve(apx_ctx *ctx, int32_t count, const BatchSpec *spec, int
 }
 
 }  // namespace apx
+
+// ---- tuning of the batched plan --------------------------------------------
+using namespace apx;
+
+namespace {
+
+// Deterministic finite scratch similarities in [-1, 0) (a small integer hash
+// per element, the diagonal at -1/2): the batch timing runs a fixed number
+// of iterations, so only the shapes matter.
+__global__ void k_btune_fill(float *S, int64_t n, int64_t ld, uint32_t salt) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+            const uint32_t h = ((uint32_t)i * 2654435761u) ^ ((uint32_t)k * 40503u) ^ (salt * 97u);
+            S[i * ld + k] = i == k ? -0.5f : -(float)((h >> 7) & 1023u) / 1024.0f - 1.0f / 2048.0f;
+        }
+}
+
+}  // namespace
+
+extern "C" apx_status apx_autotune_batched(apx_ctx *ctx, int32_t count, const int64_t *sizes, int32_t *wpc_out,
+                                           int32_t *min_rows_out, double *ms_out) {
+    if (!ctx) return APX_EINVAL;
+    if (count < 1 || !sizes) return set_err(ctx, APX_EINVAL, "need count >= 1 and sizes");
+    int64_t max_n = 0, total = 0;
+    std::vector<int64_t> lds(count), offs(count);
+    for (int j = 0; j < count; ++j) {
+        const int64_t n = sizes[j];
+        if (n < 2 || n > 12 * 4 * BT) return set_err(ctx, APX_EINVAL, "instance %d: need 2 <= n <= %d", j, 12 * 4 * BT);
+        max_n = n > max_n ? n : max_n;
+        lds[j] = (n + 3) & ~int64_t(3);
+        offs[j] = total;
+        total += n * lds[j];
+    }
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != ctx->device) (void)hipSetDevice(ctx->device);
+    hipStream_t s = ctx->stream;
+    // S, R, A of every instance in one buffer, labels in another
+    float *buf = nullptr;
+    int32_t *lab = nullptr;
+    struct Free {
+        float **b;
+        int32_t **l;
+        ~Free() {
+            if (*b) (void)hipFree(*b);
+            if (*l) (void)hipFree(*l);
+        }
+    } fr{&buf, &lab};
+    hipError_t e;
+    if ((e = hipMalloc(&buf, sizeof(float) * 3 * (size_t)total)) ||
+        (e = hipMalloc(&lab, sizeof(int32_t) * (size_t)count * (size_t)max_n)))
+        return hip_err(ctx, e, "batch tuning scratch");
+    std::vector<BatchSpec> spec(count);
+    for (int j = 0; j < count; ++j) {
+        float *Sj = buf + offs[j];
+        spec[j] = BatchSpec{sizes[j], lds[j], Sj, buf + total + offs[j], buf + 2 * total + offs[j], lab + (size_t)j * max_n};
+        const int g = (int)(sizes[j] < 1024 ? sizes[j] : 1024);
+        k_btune_fill<<<g, 256, 0, s>>>(Sj, sizes[j], lds[j], (uint32_t)j);
+    }
+    if ((e = hipGetLastError())) return hip_err(ctx, e, "batch tuning fill");
+    apx_params p{};
+    p.damping = 0.9f;
+    p.max_iter = 12;
+    p.conv_iter = 0;
+    std::vector<apx_result> res(count);
+    const int J = (int)((max_n + 4 * BT - 1) / (4 * BT));
+    int occ = occupancy_of(J);
+    occ = occ < kMaxWpc ? occ : kMaxWpc;
+    if (occ < 1) return set_err(ctx, APX_EDEVICE, "no occupancy for the batched kernel");
+    const int rows_c[3] = {2, 8, 32};
+    double best = 1e300;
+    int bw = 0, bm = 0;
+    auto timed = [&](int w, int m, double *ms) -> apx_status {
+        ctx->force_bwpc = w;
+        ctx->force_bmin = m;
+        ctx->ws_base = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        const apx_status st = batched_solve(ctx, count, spec.data(), APX_COLD, &p, res.data());
+        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ctx->force_bwpc = ctx->force_bmin = 0;
+        return st;
+    };
+    double ms = 0.0;
+    apx_status st = timed(occ, kMinMemberRows, &ms);   // warm-up (module load, workspace)
+    if (st != APX_OK) return st;
+    for (int w = 1; w <= occ; ++w)
+        for (int m : rows_c) {
+            double t = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                st = timed(w, m, &ms);
+                if (st != APX_OK) return st;
+                t = ms < t ? ms : t;
+            }
+            if (t < best) {
+                best = t;
+                bw = w;
+                bm = m;
+            }
+        }
+    const BatchTune nt{bit_length(count), bit_length(max_n), bw, bm, best};
+    bool put = false;
+    for (BatchTune &t : ctx->btune)
+        if (t.count_bits == nt.count_bits && t.n_bits == nt.n_bits) {
+            t = nt;
+            put = true;
+        }
+    if (!put) ctx->btune.push_back(nt);
+    if (wpc_out) *wpc_out = bw;
+    if (min_rows_out) *min_rows_out = bm;
+    if (ms_out) *ms_out = best;
+    return APX_OK;
+}

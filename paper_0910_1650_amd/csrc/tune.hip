@@ -38,6 +38,11 @@ namespace {
         hipError_t _e = (expr);                               \
         if (_e != hipSuccess) return hip_err(ctx, _e, what);  \
     } while (0)
+#define APX_TRY(expr)                        \
+    do {                                     \
+        const apx_status _s = (expr);        \
+        if (_s != APX_OK) return _s;         \
+    } while (0)
 
 constexpr int kThreads[3] = {256, 512, 1024};
 
@@ -171,13 +176,46 @@ TuneEntry *find_entry(apx_ctx *ctx, int64_t n) {
     return nullptr;
 }
 
-void put_entry(apx_ctx *ctx, const TuneEntry &e) {
+// Replaces the bucket's entry; unless keep_form is false, a new entry
+// without a form keeps the old entry's form and form timings (the two are
+// tuned separately).
+void put_entry(apx_ctx *ctx, const TuneEntry &e, bool keep_form = true) {
     for (TuneEntry &x : ctx->tune)
         if (x.bucket == e.bucket) {
+            const TuneEntry old = x;
             x = e;
+            if (keep_form && e.form == 0) {
+                x.form = old.form;
+                for (int q = 0; q < 3; ++q) x.form_ms[q] = old.form_ms[q];
+            }
             return;
         }
     ctx->tune.push_back(e);
+}
+
+// Points of a 16-D mixture of 20 unit Gaussians whose centres are spread
+// with standard deviation 4 (Box-Muller on a counter hash): the scratch
+// problem of the form timing.
+__device__ __forceinline__ float tune_u01(uint32_t a, uint32_t b) {
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return ((float)(h >> 8) + 0.5f) * (1.0f / 16777216.0f);
+}
+__global__ void k_tune_points(float *X, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = (uint32_t)(tune_u01((uint32_t)i, 1u) * 20.0f);
+    for (int j = 0; j < 16; ++j) {
+        const float u1 = tune_u01(c, 100u + j), u2 = tune_u01(c, 200u + j);
+        const float v1 = tune_u01((uint32_t)i, 300u + j), v2 = tune_u01((uint32_t)i, 400u + j);
+        const float cz = sqrtf(-2.0f * logf(u1)) * cosf(6.2831853f * u2);
+        const float z = sqrtf(-2.0f * logf(v1)) * cosf(6.2831853f * v2);
+        X[i * 16 + j] = 4.0f * cz + z;
+    }
 }
 
 struct DevGuard {
@@ -196,9 +234,10 @@ struct DevGuard {
 
 namespace apx {
 
-apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune) {
+apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, bool may_tune, int *form) {
     *pl = plan_pass(n, ctx->num_cus);
     if (check_every) *check_every = 0;
+    if (form) *form = 0;
     TuneEntry *e = find_entry(ctx, n);
     // the tuner allocates a scratch problem: never with a caller-set workspace
     if (!e && may_tune && ctx->autotune && !ctx->ws_external) {
@@ -212,7 +251,9 @@ apx_status ctx_plan(apx_ctx *ctx, int64_t n, PassPlan *pl, int *check_every, boo
         const PassPlan t = plan_pass_variant(n, ctx->num_cus, e->threads, e->lds != 0);
         if (t.threads != 0) *pl = t;
         if (check_every) *check_every = e->check_every;
+        if (form) *form = e->form;
     }
+    if (form && ctx->force_form) *form = ctx->force_form;
     return APX_OK;
 }
 
@@ -272,9 +313,115 @@ apx_status apx_tune_get(apx_ctx *ctx, int64_t n, int32_t *threads, int32_t *lds,
     return APX_OK;
 }
 
+apx_status apx_autotune_form(apx_ctx *ctx, int64_t n, int32_t *form, double *ms) {
+    if (!ctx) return APX_EINVAL;
+    if (n < 2 || n > 65536) return set_err(ctx, APX_EINVAL, "autotune_form needs 2 <= n <= 65536");
+    DevGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int64_t ld = (n + 63) & ~int64_t(63);
+    Scratch sc;
+    HIP_TRY(hipMalloc(&sc.vec, sizeof(float) * 16 * n), "form scratch");
+    HIP_TRY(hipMalloc(&sc.S, sizeof(float) * n * ld), "form scratch");
+    HIP_TRY(hipMalloc(&sc.R, sizeof(float) * n * ld), "form scratch");
+    HIP_TRY(hipMalloc(&sc.A, sizeof(float) * n * ld), "form scratch");
+    HIP_TRY(hipMalloc(&sc.partial, sizeof(int32_t) * n), "form scratch");
+    k_tune_points<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sc.vec, n);
+    HIP_TRY(hipGetLastError(), "form points");
+    apx_status st = ap_similarity(ctx, sc.vec, n, 16, 16, sc.S, ld, APX_PREF_MEDIAN, nullptr, 0.0f, 12345u,
+                                  1e-12, nullptr);
+    if (st != APX_OK) return st;
+    // per-iteration time: the difference of two fixed-length solves (the
+    // prologue, the final rebuild of A and R and the finalisation cancel)
+    auto run = [&](int f, int32_t iters, double *out_ms) -> apx_status {
+        apx_params p{};
+        p.damping = 0.9f;
+        p.max_iter = iters;
+        p.conv_iter = 0;
+        p.check_every = iters;
+        apx_result r{};
+        ctx->force_form = f;
+        HIP_TRY(hipStreamSynchronize(s), "form sync");
+        const auto t0 = std::chrono::steady_clock::now();
+        const apx_status e = ap_solve(ctx, sc.S, n, ld, sc.R, sc.A, APX_COLD, &p,
+                                      reinterpret_cast<int32_t *>(sc.partial), &r);
+        ctx->force_form = 0;
+        if (e != APX_OK) return e;
+        HIP_TRY(hipStreamSynchronize(s), "form sync");
+        *out_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return APX_OK;
+    };
+    double fm[3] = {0.0, 0.0, 0.0};
+    int pick = 0;
+    constexpr int32_t kShort = 8, kLong = 40;
+    for (int f = APX_FORM_EXPLICIT; f <= APX_FORM_IMPLICIT_RA; ++f) {
+        double t_short = 0.0, t_long = 0.0, best = 1e300;
+        // warm-up run, then the best of two pairs
+        APX_TRY(run(f, kShort, &t_short));
+        for (int rep = 0; rep < 2; ++rep) {
+            APX_TRY(run(f, kShort, &t_short));
+            APX_TRY(run(f, kLong, &t_long));
+            const double per = (t_long - t_short) / (double)(kLong - kShort);
+            best = per < best ? per : best;
+        }
+        fm[f - 1] = best > 0.0 ? best : 1e-9;
+        if (pick == 0 || fm[f - 1] < fm[pick - 1]) pick = f;
+    }
+    TuneEntry *e = find_entry(ctx, n);
+    TuneEntry t{};
+    if (e) {
+        t = *e;
+    } else {
+        // no row-pass entry yet: the default plan with the default poll interval
+        const PassPlan pl = plan_pass(n, ctx->num_cus);
+        t.bucket = tune_bucket(n);
+        t.n = n;
+        t.threads = pl.threads;
+        t.lds = pl.lds_bytes > 0 ? 1 : 0;
+        t.check_every = 0;
+        t.ms_per_iter = 0.0;
+    }
+    t.form = pick;
+    for (int q = 0; q < 3; ++q) t.form_ms[q] = fm[q];
+    put_entry(ctx, t);
+    if (form) *form = pick;
+    if (ms)
+        for (int q = 0; q < 3; ++q) ms[q] = fm[q];
+    return APX_OK;
+}
+
+apx_status apx_tune_set_form(apx_ctx *ctx, int64_t n, int32_t form) {
+    if (!ctx) return APX_EINVAL;
+    if (n < 2 || n > 65536) return set_err(ctx, APX_EINVAL, "need 2 <= n <= 65536");
+    if (form < APX_FORM_DEFAULT || form > APX_FORM_IMPLICIT_RA) return set_err(ctx, APX_EINVAL, "bad form %d", form);
+    TuneEntry *e = find_entry(ctx, n);
+    if (e) {
+        e->form = form;
+        return APX_OK;
+    }
+    const PassPlan pl = plan_pass(n, ctx->num_cus);
+    TuneEntry t{};
+    t.bucket = tune_bucket(n);
+    t.n = n;
+    t.threads = pl.threads;
+    t.lds = pl.lds_bytes > 0 ? 1 : 0;
+    t.form = form;
+    put_entry(ctx, t);
+    return APX_OK;
+}
+
+apx_status apx_tune_get_form(apx_ctx *ctx, int64_t n, int32_t *form, double *ms) {
+    if (!ctx || !form) return APX_EINVAL;
+    const TuneEntry *e = find_entry(ctx, n);
+    *form = e ? e->form : 0;
+    if (ms)
+        for (int q = 0; q < 3; ++q) ms[q] = e ? e->form_ms[q] : 0.0;
+    return APX_OK;
+}
+
 apx_status apx_tune_clear(apx_ctx *ctx) {
     if (!ctx) return APX_EINVAL;
     ctx->tune.clear();
+    ctx->btune.clear();
     return APX_OK;
 }
 
@@ -287,9 +434,9 @@ apx_status apx_tune_save(apx_ctx *ctx, const char *path) {
         const TuneEntry &e = ctx->tune[q];
         std::fprintf(f,
                      "  {\"bucket\": %lld, \"n\": %lld, \"threads\": %d, \"lds\": %d, \"check_every\": %d, "
-                     "\"ms_per_iter\": %.6f}%s\n",
-                     (long long)e.bucket, (long long)e.n, e.threads, e.lds, e.check_every, e.ms_per_iter,
-                     q + 1 < ctx->tune.size() ? "," : "");
+                     "\"ms_per_iter\": %.6f, \"form\": %d, \"form_ms\": [%.6f, %.6f, %.6f]}%s\n",
+                     (long long)e.bucket, (long long)e.n, e.threads, e.lds, e.check_every, e.ms_per_iter, e.form,
+                     e.form_ms[0], e.form_ms[1], e.form_ms[2], q + 1 < ctx->tune.size() ? "," : "");
     }
     std::fprintf(f, " ]\n}\n");
     const bool ok = std::fclose(f) == 0;
@@ -310,10 +457,22 @@ apx_status apx_tune_load(apx_ctx *ctx, const char *path) {
         if (!std::strstr(line, "\"bucket\"")) continue;
         long long b = 0, n = 0;
         TuneEntry e{};
-        if (std::sscanf(line,
-                        " {\"bucket\": %lld, \"n\": %lld, \"threads\": %d, \"lds\": %d, \"check_every\": %d, "
-                        "\"ms_per_iter\": %lf}",
-                        &b, &n, &e.threads, &e.lds, &e.check_every, &e.ms_per_iter) != 6) {
+        const int got_fields = std::sscanf(
+            line,
+            " {\"bucket\": %lld, \"n\": %lld, \"threads\": %d, \"lds\": %d, \"check_every\": %d, "
+            "\"ms_per_iter\": %lf, \"form\": %d, \"form_ms\": [%lf, %lf, %lf]}",
+            &b, &n, &e.threads, &e.lds, &e.check_every, &e.ms_per_iter, &e.form, &e.form_ms[0], &e.form_ms[1],
+            &e.form_ms[2]);
+        // files written before forms were tuned end after ms_per_iter
+        if (got_fields != 10 && got_fields != 6) {
+            bad = true;
+            break;
+        }
+        if (got_fields == 6) {
+            e.form = 0;
+            e.form_ms[0] = e.form_ms[1] = e.form_ms[2] = 0.0;
+        }
+        if (e.form < 0 || e.form > APX_FORM_IMPLICIT_RA) {
             bad = true;
             break;
         }
@@ -331,7 +490,7 @@ apx_status apx_tune_load(apx_ctx *ctx, const char *path) {
     if (cus != ctx->num_cus)
         return set_err(ctx, APX_EINVAL, "%s was tuned for %d compute units, this device has %d", path, cus,
                        ctx->num_cus);
-    for (const TuneEntry &e : got) put_entry(ctx, e);
+    for (const TuneEntry &e : got) put_entry(ctx, e, false);
     return APX_OK;
 }
 

@@ -167,3 +167,23 @@ def test_one_large_instance_runs_as_a_team():
         assert r.iterations == ref.iterations
         assert np.array_equal(idx.cpu().numpy(), ref.idx)
         assert torch.equal(idx, idx2) and r.netsim == r2.netsim
+
+
+def test_tuned_batched_plan_matches_oracle():
+    """apx_autotune_batched picks a plan for the batch's shape from the
+    timed candidates; the batch solved with it still matches the oracle."""
+    insts = synth.batch_instances(count=12, seed0=3151)
+    Ss = [inst_S(p, p.seed) for p in insts]
+    sizes = [S.shape[0] for S in Ss]
+    apx.apx_tune_clear()
+    try:
+        pick = apx.apx_autotune_batched(sizes)
+        print("batched plan pick:", pick, flush=True)
+        assert 1 <= pick["wpc"] <= 4 and pick["min_rows"] in (2, 8, 32) and pick["ms"] > 0
+        idxs, res = apx.ap_solve_batched([dev(S) for S in Ss], damping=0.9, max_iter=1000, conv_iter=15)
+    finally:
+        apx.apx_tune_clear()
+    for S, idx, r in zip(Ss, idxs, res):
+        ref = oracle.ap(S, 0.9, 1000, 15)
+        assert r.converged == ref.converged and r.iterations == ref.iterations
+        assert np.array_equal(idx.cpu().numpy(), ref.idx)
