@@ -563,6 +563,12 @@ __device__ __forceinline__ float imp_alpha(float lam, int t) {
     return (float)(1.0 - pow((double)lam, (double)t));
 }
 
+// lambda^t of the block warm start, one function of t for every pass and
+// the materialisation (the same rounding everywhere).
+__device__ __forceinline__ float ia_lambda_pow(float lam, int t) {
+    return t <= 0 ? 1.0f : (float)pow((double)lam, (double)t);
+}
+
 // Column sums: 64 columns per workgroup, 16 slices of the partial rows per
 // column summed in FP64, slices combined in a fixed order.
 __global__ __launch_bounds__(1024) void k_col_reduce(ColArgs a) {
@@ -1375,7 +1381,7 @@ __device__ __forceinline__ void wg_top2(Top2 &t, int (*sh_v)[2], int *sh_i, int 
     t = Top2{okey_f(V), K, okey_f(V2)};
 }
 
-template <int T, int J, bool GP>
+template <int T, int J, bool GP, bool WB>
 __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
 #pragma clang fp contract(off)
     constexpr int NW = T / 64;
@@ -1425,6 +1431,10 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     const int tpass = p.st->iter + 1;
     const float al = p.st->imp_al;               // alpha_t
     const float al1 = p.st->imp_al1;             // alpha_{t+1}
+    // block warm start: lambda^t and lambda^(t-1) (A_t and A_{t-1} of
+    // never-positive elements: acol + lambda^t a_0)
+    const float lt = WB ? ia_lambda_pow(lam, tpass) : 0.0f;
+    const float ltp = WB ? ia_lambda_pow(lam, tpass - 1) : 0.0f;
     const ImpLayout L = imp_layout(n);
     const char *sin = p.state + (int64_t)(tpass & 1) * p.stride;
     char *sout = p.state + (int64_t)((tpass + 1) & 1) * p.stride;
@@ -1578,11 +1588,46 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         for (int j = 0; j < J; ++j) acv[j] = (j < J - 1 || last_in) ? ld4(acol_t + c0 + j * T * 4) : z4;
     }
     float4 s4[J];
+    // block warm start: the thread's chunks that meet the row's block
+    // [b0, b1) are consecutive, at most NB of them (checked by the host):
+    // a_0 of chunk a0f + q in a0q[q] (zero outside the block)
+    constexpr int NB = WB ? (J < 3 ? J : 3) : 1;
+    float4 a0q[NB];
+    int a0f = J;
     auto load_row = [&](int64_t i, float4 *dst) {
         const rsrc_t srs = row_rsrc(p.S + i * ld, ld);
 #pragma unroll
         for (int j = 0; j < J; ++j)
             if (j < J - 1 || last_in) dst[j] = bld4(srs, tid * 16, j * T * 16);
+        if constexpr (WB) {
+            const int b0 = p.blk[2 * i], b1 = p.blk[2 * i + 1];
+            // first chunk with c + 3 >= b0 (chunk j starts at c0 + 4 T j)
+            const int lo = b0 - 3 - c0;
+            a0f = lo <= 0 ? 0 : (lo + 4 * T - 1) / (4 * T);
+            const rsrc_t ars = row_rsrc(p.A + i * ld, ld);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int j = a0f + q;
+                const int c = c0 + j * T * 4;
+                a0q[q] = (j < J && c < b1 && (j < J - 1 || last_in)) ? bld4(ars, tid * 16, j * T * 16) : z4;
+            }
+        }
+    };
+    // acol + lambda^t a_0 for chunk j (WB): the block chunk, if it is one
+    auto warm_av = [&](int j, float4 &av) {
+        if constexpr (WB) {
+            const int q = j - a0f;
+            if (__any(q >= 0 && q < NB)) {
+                float4 a0 = z4;
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if (q == u) a0 = a0q[u];
+                av.x = av.x + lt * a0.x;
+                av.y = av.y + lt * a0.y;
+                av.z = av.z + lt * a0.z;
+                av.w = av.w + lt * a0.w;
+            }
+        }
     };
     int cur_c[EPT], nxt_c[EPT];
     float cur_v[EPT], nxt_v[EPT];
@@ -1607,6 +1652,12 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         const ColOwner dg = owner_of<T>(ii, tid);
         const int dle = dg.mine ? 4 * dg.j + dg.e : -1;   // local index of the diagonal
         const int xcnt = rcnt[i - r0];
+        const int wb0 = WB ? p.blk[2 * i] : 0, wb1 = WB ? p.blk[2 * i + 1] : 0;
+        // a_0(i,k) of a column of the row's block (WB; a global load, rare paths)
+        auto a0_at = [&](int k) -> float {
+            if constexpr (WB) return (k >= wb0 && k < wb1 && k != ii) ? p.A[i * ld + k] : 0.0f;
+            return 0.0f;
+        };
         // The exemplar decision: column ii wins iff no column k < ii has
         // a+r >= D and no column k > ii has a+r > D, D = a(i,i) + r(i,i)
         // (lowest index on ties).  v > D is tested as v >= next float above D.
@@ -1633,6 +1684,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             if ((unsigned)rk < (unsigned)n) {
                 rs = p.S[i * ld + rk];
                 rav = acol_t[rk];
+                if constexpr (WB) rav = rav + lt * a0_at(rk);
             } else {
                 rk = -1;
             }
@@ -1678,6 +1730,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                     avq[(j + APF) % (APF + 1)] = ld4(acol_t + c0 + (j + APF) * T * 4);
                 av = avq[j % (APF + 1)];
             }
+            warm_av(j, av);
             // out-of-range columns of the last chunk count as listed
             const uint32_t mb = mb8[j * T + tid] | (full ? 0u : oob_bits);
             // columns of this chunk below the diagonal beat it with a tie
@@ -1730,6 +1783,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 } else {
                     av = ld4(acol_t + c0 + (dle >> 2) * T * 4);
                 }
+                if constexpr (WB) {
+                    // the diagonal's chunk is in the block
+                    const int q = (dle >> 2) - a0f;
+                    float4 a0 = z4;
+#pragma unroll
+                    for (int u = 0; u < NB; ++u)
+                        if (q == u) a0 = a0q[u];
+                    av.x = av.x + lt * a0.x;
+                    av.y = av.y + lt * a0.y;
+                    av.z = av.z + lt * a0.z;
+                    av.w = av.w + lt * a0.w;
+                }
                 const uint32_t mb = mb8[(dle >> 2) * T + tid];
                 const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
                 for (int e = 0; e < (dle & 3); ++e) {
@@ -1740,7 +1805,9 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
         // first positive responsibility: A from acol_{t-1}, a new list entry
         auto fresh = [&](int k, float s, float r) {
-            const float an = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
+            float ap = acol_p[k];
+            if constexpr (WB) ap = ap + ltp * a0_at(k);
+            const float an = lam * ap + oml * fminf(0.0f, p.tcol[k] - r);
             merge(an + r, an + s, k);
             const int pos = xcnt + atomicAdd(&xa_new[xs], 1);
             if (pos < xcap) {
@@ -2000,14 +2067,18 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                         for (int qq = 0; qq < cnt; ++qq)
                             if (st_col[sl][qq] == k) r = st_gam[sl][qq];
                     }
+                    const float a0 = a0_at(k);   // read before this element is overwritten
                     float a = acol_t[k];
+                    if constexpr (WB) a = a + lt * a0;
                     if (k == ii) {
                         a = adg;
                     } else if ((mb >> e) & 1u) {
                         for (int qq = 0; qq < xcnt; ++qq)
                             if (xcol_out[i * IMP_KA + qq] == k) a = xval_out[i * IMP_KA + qq];
                     } else if (r > 0.0f) {
-                        a = lam * acol_p[k] + oml * fminf(0.0f, p.tcol[k] - r);
+                        float ap = acol_p[k];
+                        if constexpr (WB) ap = ap + ltp * a0;
+                        a = lam * ap + oml * fminf(0.0f, p.tcol[k] - r);
                     }
                     Arow[k] = a;
                 }
@@ -2034,7 +2105,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
 
 // A = acol off the diagonal, adiag on it, then the listed exceptions.
 __global__ void k_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
-                                 const char *xs) {
+                                 const char *xs, const int32_t *blk, float lam, int32_t t) {
     const XLayout X = x_layout(n);
     const int32_t *cnt = reinterpret_cast<const int32_t *>(xs + X.cnt);
     const int32_t *col = reinterpret_cast<const int32_t *>(xs + X.col);
@@ -2044,18 +2115,30 @@ __global__ void k_ia_materialize(float *A, int64_t ld, int32_t n, const float *a
         if (c < 0) continue;
         float *row = A + i * ld;
         const float ad = adiag[i];
-        // 16-byte stores (rows are 16-byte aligned, the column vector is
-        // padded to a multiple of four); the tail past n is left alone
-        for (int64_t k = 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
-            if (k + 3 < n) {
-                float4 v = *reinterpret_cast<const float4 *>(acol + k);
-                v.x = k == i ? ad : v.x;
-                v.y = k + 1 == i ? ad : v.y;
-                v.z = k + 2 == i ? ad : v.z;
-                v.w = k + 3 == i ? ad : v.w;
-                *reinterpret_cast<float4 *>(row + k) = v;
-            } else {
-                for (int64_t q = k; q < n; ++q) row[q] = (q == i) ? ad : acol[q];
+        if (blk != nullptr) {
+            // block warm start: acol + lambda^t a_0 inside the row's block
+            // (a_0 read from A itself, each element by the thread writing it)
+            const float lt = ia_lambda_pow(lam, t);
+            const int64_t b0 = blk[2 * i], b1 = blk[2 * i + 1];
+            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+                float v = acol[k];
+                if (k >= b0 && k < b1 && k != i) v = v + lt * row[k];
+                row[k] = k == i ? ad : v;
+            }
+        } else {
+            // 16-byte stores (rows are 16-byte aligned, the column vector is
+            // padded to a multiple of four); the tail past n is left alone
+            for (int64_t k = 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
+                if (k + 3 < n) {
+                    float4 v = *reinterpret_cast<const float4 *>(acol + k);
+                    v.x = k == i ? ad : v.x;
+                    v.y = k + 1 == i ? ad : v.y;
+                    v.z = k + 2 == i ? ad : v.z;
+                    v.w = k + 3 == i ? ad : v.w;
+                    *reinterpret_cast<float4 *>(row + k) = v;
+                } else {
+                    for (int64_t q = k; q < n; ++q) row[q] = (q == i) ? ad : acol[q];
+                }
             }
         }
         __syncthreads();
@@ -2144,16 +2227,16 @@ hipError_t launch_imp_t(int kind, const ImpArgs &a, const PassPlan &pl, hipStrea
     return launch_imp_tj<T, J, false>(kind, a, pl, s);
 }
 
-template <int T, int J, bool GP>
+template <int T, int J, bool GP, bool WB>
 hipError_t launch_ia_k(const ImpArgs &a, int grid, size_t lds, hipStream_t s) {
     static bool attr_set = false;   // per process; the attribute is per function
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_row_ia<T, J, GP>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_row_ia<T, J, GP, WB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsIa);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    k_row_ia<T, J, GP><<<grid, T, lds, s>>>(a);
+    k_row_ia<T, J, GP, WB><<<grid, T, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -2165,15 +2248,29 @@ size_t ia_lds(int64_t n, int grid, bool gp) {
     return (size_t)(gp ? 0 : 16 * q) + (size_t)(NXS * mw * 4) + (size_t)(4 * rows);
 }
 
+// The block warm start has 1024-thread variants only (n > 4096).
 template <int T, int J>
 hipError_t launch_ia_t(const ImpArgs &a, const PassPlan &pl, hipStream_t s) {
     const bool gp = pl.lds_bytes < ia_lds(a.n, pl.grid, false);
+    const bool wb = a.blk != nullptr;
+    if constexpr (T == 1024) {
+        if (wb) {
+            if constexpr (J >= 7) {
+                if (gp) return launch_ia_k<T, J, true, true>(a, pl.grid, pl.lds_bytes, s);
+            } else {
+                if (gp) return hipErrorInvalidValue;
+            }
+            return launch_ia_k<T, J, false, true>(a, pl.grid, pl.lds_bytes, s);
+        }
+    } else {
+        if (wb) return hipErrorInvalidValue;
+    }
     if constexpr (J >= 7) {
-        if (gp) return launch_ia_k<T, J, true>(a, pl.grid, pl.lds_bytes, s);
+        if (gp) return launch_ia_k<T, J, true, false>(a, pl.grid, pl.lds_bytes, s);
     } else {
         if (gp) return hipErrorInvalidValue;
     }
-    return launch_ia_k<T, J, false>(a, pl.grid, pl.lds_bytes, s);
+    return launch_ia_k<T, J, false, false>(a, pl.grid, pl.lds_bytes, s);
 }
 
 }  // namespace
@@ -2407,9 +2504,20 @@ hipError_t launch_row_ia(const PassPlan &pl, const ImpArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
-                                 const char *x_parity, hipStream_t s) {
+                                 const char *x_parity, hipStream_t s, const int32_t *blk, float lam, int32_t t) {
     const int g = n < 8192 ? n : 8192;
-    k_ia_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(A, ld, n, acol, adiag, x_parity);
+    k_ia_materialize<<<g > 0 ? g : 1, 256, 0, s>>>(A, ld, n, acol, adiag, x_parity, blk, lam, t);
+    return hipGetLastError();
+}
+
+__global__ void k_extract_diag(const float *A, int64_t ld, int32_t n, float *adiag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) adiag[k] = A[(int64_t)k * ld + k];
+}
+
+hipError_t launch_extract_diag(const float *A, int64_t ld, int32_t n, float *adiag, hipStream_t s) {
+    const int g = (n + 255) / 256;
+    k_extract_diag<<<g > 0 ? g : 1, 256, 0, s>>>(A, ld, n, adiag);
     return hipGetLastError();
 }
 

@@ -298,7 +298,8 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
     std::memcpy(&lam_bits, &lam, sizeof lam_bits);
     const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)(uintptr_t)buf[0], (uint64_t)(uintptr_t)buf[1],
                               (uint64_t)(uintptr_t)A, (uint64_t)n, (uint64_t)ld, lam_bits, (uint64_t)chunk,
-                              (uint64_t)(t0 & 1), (uint64_t)(uintptr_t)w.st, (uint64_t)(uintptr_t)w.partial,
+                              (uint64_t)(t0 & 1) | (uint64_t)(uintptr_t)ctx->ia_blk, (uint64_t)(uintptr_t)w.st,
+                              (uint64_t)(uintptr_t)w.partial,
                               (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.imp,
                               (uint64_t)pl.grid | ((uint64_t)mode << 32) | ((uint64_t)ctx->implicit_k << 40) |
                                   ((uint64_t)ctx->implicit_a << 48),
@@ -313,7 +314,9 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
         for (int u = 0; u < chunk && e == hipSuccess; ++u) {
             const int32_t t = t0 + u;
             if (mode == SOLVE_IMPLICIT_A) {
-                e = launch_row_ia(pl, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a),
+                ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a);
+                ia.blk = ctx->ia_blk;
+                e = launch_row_ia(pl, ia,
                                   ctx->cap);
             } else if (mode == SOLVE_IMPLICIT_R) {
                 e = launch_row_imp(pl, IMP_FULL, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k),
@@ -662,7 +665,11 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     PassPlan ipl{}, apl{};
     // the message-change rule needs both messages in memory: explicit form
     const bool r_ok = !msg_rule && ctx->implicit_k > 0 && warm != APX_WARM_AR && imp_plan(n, ctx->num_cus, &ipl);
-    bool imp_a = r_ok && (warm == APX_COLD || cols) && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
+    // PAP's block-diagonal A' (pap_solve sets the blocks): implicit A with
+    // the lambda^t a_0 term, 1024-thread passes only (n > 4096)
+    const bool wblk = warm == APX_WARM_A && ctx->warm_blk != nullptr && n > 4096;
+    const bool ia_start = warm == APX_COLD || cols || wblk;
+    bool imp_a = r_ok && ia_start && ctx->implicit_a > 0 && n >= ctx->implicit_a_min_n &&
                  ia_plan(n, ctx->num_cus, &apl);
     bool implicit = r_ok && (imp_a || n >= ctx->implicit_min_n);
     // a tuned (or, while the tuner times forms, forced) message form replaces
@@ -673,9 +680,16 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
         imp_a = false;
         implicit = r_ok;
     } else if (tuned_form == APX_FORM_IMPLICIT_RA) {
-        imp_a = r_ok && (warm == APX_COLD || cols) && ctx->implicit_a > 0 && ia_plan(n, ctx->num_cus, &apl);
+        imp_a = r_ok && ia_start && ctx->implicit_a > 0 && ia_plan(n, ctx->num_cus, &apl);
         implicit = r_ok;
     }
+    // the implicit-A passes of this solve read A' through its blocks
+    struct BlkGuard {
+        apx_ctx *c;
+        ~BlkGuard() { c->ia_blk = nullptr; }
+    } blk_guard{ctx};
+    ctx->ia_blk = (imp_a && wblk) ? ctx->warm_blk : nullptr;
+    const int32_t *const ia_blk = ctx->ia_blk;
     int32_t imp_until = implicit ? INT32_MAX : 0;   // last iteration run with implicit R
     int32_t ia_until = imp_a ? INT32_MAX : 0;       // last iteration run with implicit A
     int32_t fallback = 0;                           // imp_abort bits of the fallbacks
@@ -695,6 +709,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             HIP_TRY(launch_fill_f32_rows(w.acol[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
             HIP_TRY(launch_fill_f32_rows(w.adiag[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
             if (cols) HIP_TRY(launch_extract_cols(A, ld, (int32_t)n, w.acol[0], w.adiag[0], s), "implicit A");
+            // block warm start: acol_0 = 0 (A' enters as lambda^t a_0), adiag_0 = diag(A')
+            if (ia_blk) HIP_TRY(launch_extract_diag(A, ld, (int32_t)n, w.adiag[0], s), "implicit A");
             HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.xst + x_layout(n).cnt), 4 * n, 0, s),
                     "implicit A");
         } else if (warm == APX_COLD) {
@@ -764,10 +780,11 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                                         w.eflag, w.st);
                 const int slot = t - t_first;
                 if (ctx->prof) HIP_TRY(hipEventRecord(ctx->prof_ev[2 * slot], s), "event");
-                if (imp_a)
-                    HIP_TRY(launch_row_ia(apl, imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k,
-                                                        ctx->implicit_a), s),
-                            "row pass");
+                if (imp_a) {
+                    ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a);
+                    ia.blk = ia_blk;
+                    HIP_TRY(launch_row_ia(apl, ia, s), "row pass");
+                }
                 else if (implicit)
                     HIP_TRY(launch_row_imp(ipl, IMP_FULL,
                                            imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k), s),
@@ -804,7 +821,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
             if (imp_a && implicit && hst->imp_owner && !(hst->imp_abort & 5)) fallback |= APX_FALLBACK_R_OWNER;
             if (imp_a) {
                 HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[ta & 1], w.adiag[ta & 1],
-                                              w.xst + (ta & 1) * w.xstride, s), "materialize A");
+                                              w.xst + (ta & 1) * w.xstride, s, ia_blk, lam, ta), "materialize A");
                 imp_a = false;
                 ia_until = ta;
             }
@@ -831,7 +848,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     ctx->last_fallback = fallback | (hst->imp_owner ? APX_NOTE_R_OWNER : 0);
     if (imp_a) {
         HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[T & 1], w.adiag[T & 1],
-                                      w.xst + (T & 1) * w.xstride, s), "materialize A");
+                                      w.xst + (T & 1) * w.xstride, s, ia_blk, lam, T), "materialize A");
     }
     if (implicit) {
         // alpha_T is the previous alpha after the reduce of pass T

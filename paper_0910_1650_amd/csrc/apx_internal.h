@@ -157,6 +157,11 @@ struct ImpArgs {
     char *xstate;               // exception lists, two parities of `xstride` bytes
     int64_t xstride;
     int32_t xcap;               // list capacity in use (<= IMP_KA)
+    // Block-diagonal warm start (PAP's Step 4, implicit A): A holds A_0 = A'
+    // (zero outside the diagonal blocks, read only), row i's block is the
+    // column range [blk[2i], blk[2i+1]); an element whose responsibility was
+    // never positive has a_t = acol_t(k) + lambda^t a_0(i,k).  Null: A_0 = 0.
+    const int32_t *blk;
 };
 // Implicit availabilities.  With A_0 = 0, Eq. (3) with damping gives every
 // off-diagonal element (i,k) whose responsibility r_s(i,k) was never positive
@@ -211,7 +216,10 @@ hipError_t launch_row_ia(const PassPlan &pl, const ImpArgs &a, hipStream_t s);
 // A = acol off the diagonal, adiag on it, then the row's exceptions; rows
 // whose list is -1 (overflowed: written by the pass) are left alone.
 hipError_t launch_ia_materialize(float *A, int64_t ld, int32_t n, const float *acol, const float *adiag,
-                                 const char *x_parity, hipStream_t s);
+                                 const char *x_parity, hipStream_t s, const int32_t *blk = nullptr,
+                                 float lam = 0.0f, int32_t t = 0);
+// adiag[k] = A(k,k)
+hipError_t launch_extract_diag(const float *A, int64_t ld, int32_t n, float *adiag, hipStream_t s);
 // Clears the frozen and overflow flags after an overflow hand-over.
 hipError_t launch_state_resume(ApState *st, hipStream_t s);
 
@@ -288,6 +296,12 @@ struct apx_ctx {
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
     int force_form = 0;               // form timing in progress: the form every solve uses
+    // PAP's Step 4 (pap_solve -> ap_solve with APX_WARM_A): per row, the
+    // column range of its diagonal block of A' (device, 2n int32), set for
+    // the duration of that call; ia_blk: the same while the implicit-A
+    // passes of a solve use it
+    const int32_t *warm_blk = nullptr;
+    const int32_t *ia_blk = nullptr;
     std::vector<apx::BatchTune> btune;  // tuned batched plans (apx_autotune_batched)
     int force_bwpc = 0, force_bmin = 0;   // batched plan timing in progress
     std::vector<apx::TuneEntry> tune;

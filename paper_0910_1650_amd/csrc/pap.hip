@@ -67,7 +67,7 @@ namespace {
 // Workspace of pap_solve for parts of sizes nj: [tables | S_jj R_jj A_jj idx_jj]
 // followed by the batch solver's slice, or the full solve's from 0.
 struct PapLayout {
-    size_t o_perm, o_off, o_ptr, o_ld, o_rp, head, bbytes, fbytes;
+    size_t o_perm, o_off, o_ptr, o_ld, o_rp, head, bbytes, fbytes, blk_bytes;
     std::vector<size_t> o_s, o_r, o_a, o_i;
     std::vector<int64_t> ldj;
     bool batch_sub;
@@ -112,7 +112,9 @@ PapLayout pap_layout(int64_t n, int64_t ld, int32_t k, const std::vector<int64_t
                 P.bbytes = b > P.bbytes ? b : P.bbytes;
             }
     }
-    P.fbytes = solve_ws_bytes(n, ld, num_cus);
+    // Step 4: the per-row block table, then the full solve's workspace
+    P.blk_bytes = (sizeof(int32_t) * 2 * (size_t)n + 255) & ~(size_t)255;
+    P.fbytes = P.blk_bytes + solve_ws_bytes(n, ld, num_cus);
     return P;
 }
 
@@ -289,8 +291,32 @@ extern "C" apx_status pap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t
     HIP_TRY(hipGetLastError(), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "sync");
 
-    // Step 4: AP on the whole S from A' (R_0 = 0).
+    // Step 4: AP on the whole S from A' (R_0 = 0).  With contiguous parts
+    // the solve is told each row's block of A', so its availabilities can
+    // stay implicit (A' enters as lambda^t a'(i,k) inside the blocks); the
+    // 1024-thread passes keep a row's block chunks in at most three float4
+    // registers per thread, which bounds a part to 2 * 4096 - 3 points.
     apx_params fp = *orig_params;
     fp.flags &= ~(uint32_t)APX_CHECK_FINITE;
-    return ap_solve(ctx, S, n, ld, R, A, APX_WARM_A, &fp, idx, res);
+    bool contiguous = true;
+    for (int64_t i = 0; i < n && contiguous; ++i) contiguous = pm[i] == i;
+    int64_t maxpart = 0;
+    for (int j = 0; j < k; ++j) maxpart = nj[j] > maxpart ? nj[j] : maxpart;
+    const bool blocks = contiguous && k >= 2 && n > 4096 && maxpart <= 2 * 4096 - 3;
+    if (blocks) {
+        std::vector<int32_t> hb(2 * (size_t)n);
+        for (int j = 0; j < k; ++j)
+            for (int64_t i = off[j]; i < off[j + 1]; ++i) {
+                hb[2 * i] = (int32_t)off[j];
+                hb[2 * i + 1] = (int32_t)off[j + 1];
+            }
+        HIP_TRY(hipMemcpyAsync(b, hb.data(), sizeof(int32_t) * 2 * (size_t)n, hipMemcpyHostToDevice, s), "blocks");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        ctx->warm_blk = reinterpret_cast<const int32_t *>(b);
+        ctx->ws_base = P.blk_bytes;
+    }
+    st = ap_solve(ctx, S, n, ld, R, A, APX_WARM_A, &fp, idx, res);
+    ctx->warm_blk = nullptr;
+    ctx->ws_base = 0;
+    return st;
 }
