@@ -162,8 +162,10 @@ def workload_extras(apx) -> dict:
       subspaces of R^100, 8 random parts of 3000-7000 points; the parts'
       sub-problems alone (one persistent batched launch) with their HBM rate
       (20 B per element and iteration of the explicit form those passes run,
-      summed over the parts' own iteration counts), the whole pap_solve, and
-      cold-start AP on the same S.
+      summed over the parts' own iteration counts), the whole pap_solve
+      (parts of consecutive indices: Step 4 keeps A implicit; and the same
+      sizes over a random permutation of the indices: Step 4 with implicit R
+      only), and cold-start AP on the same S.
     * batch_512: 512 independent 2-D mixtures, n in [100, 2000], 2-20
       components, damping 0.5, at most 200 iterations: one ap_solve_batched
       call; instance-iterations per second and the same HBM rate.
@@ -180,33 +182,43 @@ def workload_extras(apx) -> dict:
     pts = synth.subspaces(n=n, d=100, n_sub=20, dim=5, noise=0.05, seed=seed)
     X = torch.from_numpy(pts.X).cuda()
     S, _ = apx.ap_similarity(X, pref="median", noise_seed=seed, noise_rel=1e-12)
+    # the points are drawn i.i.d., so parts of consecutive indices with random
+    # sizes are a uniformly random partition; the same sizes with a random
+    # permutation of the indices run the general path (no block structure
+    # for Step 4)
     perm, offsets = synth.random_partition(n, 8, 3000, 7000, seed=seed)
     sizes = np.diff(offsets)
     blocks = []
-    pt = torch.from_numpy(perm).cuda()
     for j in range(8):
-        m = pt[offsets[j]:offsets[j + 1]]
+        a, b = int(offsets[j]), int(offsets[j + 1])
         Sj = apx.empty_matrix(int(sizes[j]))
-        Sj.copy_(S[m][:, m])
+        Sj.copy_(S[a:b, a:b])
         blocks.append(Sj)
     (idxs, subres), ms_sub = _timed(lambda: apx.ap_solve_batched(blocks, damping=0.9, max_iter=2000,
                                                                     conv_iter=15))
     sub_bytes = sum(20 * int(sizes[j]) ** 2 * subres[j].iterations for j in range(8))
     del blocks, idxs
     R, A = apx.empty_matrix(n), apx.empty_matrix(n)
-    (idx, res, subs), ms_pap = _timed(lambda: apx.pap_solve(S, R, A, 8, perm, offsets, damping=0.9,
+    (idx, res, subs), ms_pap = _timed(lambda: apx.pap_solve(S, R, A, 8, None, offsets, damping=0.9,
                                                             max_iter=2000, conv_iter=15))
+    step4_info = apx.apx_last_solve_info()
+    (idx_p, res_p, subs_p), ms_pap_perm = _timed(lambda: apx.pap_solve(S, R, A, 8, perm, offsets, damping=0.9,
+                                                                       max_iter=2000, conv_iter=15))
+    del idx_p
     (idx_c, res_c), ms_cold = _timed(lambda: apx.ap_solve(S, R, A, 0.9, 2000, 15))
     sub_gbs = sub_bytes / (ms_sub * 1e-3) / 1e9
     out["pap_c3"] = {
         "workload": "40000 points, union of 20 random 5-D subspaces of R^100 (noise 0.05), "
-                    "8 random parts of 3000-7000 points, damping 0.9",
+                    "8 random parts of 3000-7000 points (consecutive indices of i.i.d. points), damping 0.9",
         "part_sizes": [int(x) for x in sizes],
         "parts_ms": round(ms_sub, 2), "parts_iterations": [r.iterations for r in subres],
         "parts_GBps": round(sub_gbs, 1), "parts_frac": round(sub_gbs / HBM_PEAK_GBS, 4),
         "parts_bytes_basis": "20 B per element and iteration (explicit form), each part's own iteration count",
         "pap_ms": round(ms_pap, 2), "pap_step4_iterations": res.iterations,
+        "pap_step4_form": {"implicit_R_iterations": step4_info[0], "explicit_iterations": step4_info[1],
+                           "implicit_A_iterations": step4_info[2]},
         "pap_netsim": res.netsim, "pap_n_exemplars": res.n_exemplars,
+        "pap_permuted_parts_ms": round(ms_pap_perm, 2), "pap_permuted_step4_iterations": res_p.iterations,
         "cold_ms": round(ms_cold, 2), "cold_iterations": res_c.iterations,
         "cold_netsim": res_c.netsim, "cold_n_exemplars": res_c.n_exemplars,
         "same_exemplars": bool(torch.equal(idx, idx_c)),
