@@ -100,8 +100,8 @@ PAP_K = 8
 
 def time_to_exemplars(apx, S, n, pts_seed):
     """Wall time from S resident in HBM to the stop rule for cold start, PAP
-    (k = 8 random uneven parts) and the learned warm start (features, network,
-    A_0/R_0, cold fallback).  A run counts only if its exemplar set equals the
+    (k = 8 random uneven parts of consecutive indices) and the learned warm
+    start (features, network, column-structured A_0, cold fallback).  A run counts only if its exemplar set equals the
     FP64 oracle's (stored by tests/golden/make_oracle_exemplars.py) and its
     net similarity is within n * 1e-6 * (max S - min S) of the oracle's."""
     import numpy as np

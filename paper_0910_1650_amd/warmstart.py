@@ -169,15 +169,16 @@ def solve_warm(S, theta, damping=0.9, max_iter=2000, conv_iter=15):
 
 def solve_pap(S, k: int, seed: int, damping=0.9, max_iter=2000, conv_iter=15):
     """Algorithm 2 with a random uneven partition into k parts (sizes drawn
-    in [0.075 n, 0.175 n] before normalisation)."""
+    in [0.075 n, 0.175 n] before normalisation) of consecutive indices: the
+    points are drawn i.i.d., so that is a uniformly random partition, and
+    Step 4 can keep its availabilities implicit."""
     import synth
     n = S.shape[0]
-    perm, offsets = synth.random_partition(n, k, lo=max(1, (3 * n) // 40), hi=max(2, (7 * n) // 40),
-                                           seed=seed)
+    _, offsets = synth.random_partition(n, k, lo=max(1, (3 * n) // 40), hi=max(2, (7 * n) // 40), seed=seed)
     R, A = empty_matrix(n), empty_matrix(n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    idx, res, subs = pap_solve(S, R, A, k, perm, offsets, damping, max_iter, conv_iter)
+    idx, res, subs = pap_solve(S, R, A, k, None, offsets, damping, max_iter, conv_iter)
     return idx, res, (time.perf_counter() - t0) * 1e3, subs
 
 
