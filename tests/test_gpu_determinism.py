@@ -52,3 +52,26 @@ def test_solve_repeats_bit_identical():
     for R, A, idx, it in res[1:]:
         assert it == res[0][3]
         assert torch.equal(idx, res[0][2]) and torch.equal(R, res[0][0]) and torch.equal(A, res[0][1])
+
+
+def test_largest_lds_row_pass_solve_repeats_bit_identical():
+    """The largest N whose implicit-A pass keeps its column partials in LDS
+    (31844: the next row prefetched across the per-row barrier with eight
+    float4 chunks per thread) and the global-partials form just above it
+    (31848): three solves of 40 iterations each agree bit for bit."""
+    for n in (31844, 31848):
+        print(f"solve determinism n={n}", flush=True)
+        pts = synth.gaussian_mixture(n=n, d=32, k=40, seed=7)
+        X = torch.from_numpy(pts.X).cuda()
+        S, _ = apx.ap_similarity(X, pref="median", noise_seed=7, noise_rel=1e-12)
+        res = []
+        for _ in range(3):
+            R, A = apx.empty_matrix(n), apx.empty_matrix(n)
+            idx, r = apx.ap_solve(S, R, A, 0.9, 40, 0)
+            res.append((R, A, idx, apx.apx_last_solve_info()))
+        assert res[0][3] == (40, 0, 40)
+        for R, A, idx, info in res[1:]:
+            assert info == res[0][3]
+            assert torch.equal(idx, res[0][2]) and torch.equal(R, res[0][0]) and torch.equal(A, res[0][1])
+        del S, X, res
+        torch.cuda.empty_cache()

@@ -8,9 +8,10 @@ Held-out instances here use seeds 60000+.
 * Against an untrained network of the same shape: the held-out loss on the
   targets of converged runs must drop to at most 80% of the untrained one
   (measured: about 18% on the 2-D family, 74% on the 64-D family, whose
-  loss is dominated by the few large exemplar targets).
-  The oracle's FP64 network evaluates both loss values, so this part does
-  not depend on the GPU forward pass.
+  loss is dominated by the few large exemplar targets).  The loss is
+  evaluated on what the GPU computes (features by apx_features, outputs by
+  the bf16 MFMA forward kernel) against the oracle's targets, and the same
+  check on the oracle's FP64 network must agree.
 * Against cold-start AP (the method without it, and the reference point): the warm-
   started run from ap_warmstart, with cold start as its fallback, is timed
   in iterations against the oracle's cold run.  The test prints the
@@ -57,16 +58,26 @@ def theta():
 def test_training_gain_in_heldout_loss(theta):
     th = theta.cpu().numpy().astype(np.float64)
     th0 = ws.init_params(0).astype(np.float64)
+    th0_dev = torch.from_numpy(th0.astype(np.float32)).cuda()
     for j in range(2):
         family, S = held_out(j, 1500)
         ref = oracle.ap(S, 0.9, 1000, 15)
         F, sig = warm.features(S)
         T = warm.targets(ref.R, sig).astype(np.float64)
         w = np.full(S.shape[0], 1.0 / S.shape[0])
-        trained = warm.loss(th, F.astype(np.float64), T, w)
-        untrained = warm.loss(th0, F.astype(np.float64), T, w)
-        say(f"{family} n=1500 held-out loss: trained {trained:.4f}, untrained {untrained:.4f}")
+        # on the GPU: features of the same S, then the forward kernel
+        Fd, _ = apx.apx_features(apx.to_matrix(torch.from_numpy(S.astype(np.float32))))
+        y1 = apx.apx_mlp_forward(theta, Fd).cpu().numpy().astype(np.float64)
+        y0 = apx.apx_mlp_forward(th0_dev, Fd).cpu().numpy().astype(np.float64)
+        trained = float(np.sum(w[:, None] * warm.huber(y1 - T)))
+        untrained = float(np.sum(w[:, None] * warm.huber(y0 - T)))
+        o_trained = warm.loss(th, F.astype(np.float64), T, w)
+        o_untrained = warm.loss(th0, F.astype(np.float64), T, w)
+        say(f"{family} n=1500 held-out loss on the GPU: trained {trained:.4f}, untrained {untrained:.4f} "
+            f"(oracle network: {o_trained:.4f}, {o_untrained:.4f})")
         assert trained <= 0.8 * untrained
+        assert o_trained <= 0.8 * o_untrained
+        assert abs(trained - o_trained) <= 1e-2 * o_trained
 
 
 def test_warm_start_against_cold_start(theta):
