@@ -93,8 +93,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1927830887, "write": 46021439, "path": "implicit_RA",
-                    "sha256": "8d55700ca899c82f8e06750b70b743b9591a519781d15953b93ea3128d8d79d8"}
+ROW_PASS_TRAFFIC = {"read": 1934845474, "write": 46024233, "path": "implicit_RA",
+                    "sha256": "6479904bde82f2b2d9687d7ee88041909562e1864342ae937c83c3f5dec4bc7a"}
 PAP_K = 8
 
 

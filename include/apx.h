@@ -181,6 +181,24 @@ apx_status apx_last_solve_info(apx_ctx *ctx, int32_t *implicit_iters, int32_t *e
 enum { APX_FALLBACK_R_LIST = 1, APX_FALLBACK_A_LIST = 2, APX_FALLBACK_R_OWNER = 4, APX_NOTE_R_OWNER = 8 };
 apx_status apx_last_fallback(apx_ctx *ctx, int32_t *reasons);
 
+/* apx_set_lean_scan -- the implicit-A pass leaves the ordinary columns out
+ * of the exemplar decision of Algorithm 1 (argmax of a + r, Eqs. (2)-(4))
+ * where they cannot change it (enable = 1, the default): a row's listed and
+ * new columns already beat the diagonal, or D = a(i,i) + r(i,i) > 0 while
+ * every column value is <= 0; any other row is decided again over its
+ * ordinary columns after the reduction.  Positivity of the off-list
+ * responsibility al*s - beta is a compare of s against a per-row threshold
+ * certified to give the same answer in FP32.  enable = 0 (a cross-check)
+ * tests positivity as fl(al*s) > beta and decides every row over its
+ * ordinary columns after the reduction.  Results are bit-identical either
+ * way. */
+apx_status apx_set_lean_scan(apx_ctx *ctx, int enable);
+
+/* apx_last_lean_rescans -- rows of the last ap_solve on this context (summed
+ * over its implicit-A passes) whose ordinary columns had to be tested after
+ * the reduction.  Diagnostic only. */
+apx_status apx_last_lean_rescans(apx_ctx *ctx, int32_t *rows);
+
 /* apx_set_graphs -- replay the iteration loop of ap_solve as a captured HIP
  * graph (enable = 1, the default; the environment variable APX_GRAPHS=0
  * turns it off at context creation) or launch every kernel from the host

@@ -77,6 +77,8 @@ SIGNATURES = {
     "apx_set_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "apx_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "apx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_set_lean_scan": (ctypes.c_int, [_P, ctypes.c_int]),
+    "apx_last_lean_rescans": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     "apx_set_implicit": (ctypes.c_int, [_P, _I32, _I64]),
     "apx_set_implicit_a": (ctypes.c_int, [_P, _I32, _I64]),
     "apx_last_solve_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -352,6 +354,20 @@ def apx_last_fallback(device=None) -> int:
     ctx = context(device)
     a = _I32()
     _check(ctx, lib().apx_last_fallback(ctx, ctypes.byref(a)), "apx_last_fallback")
+    return a.value
+
+
+def apx_set_lean_scan(enable: bool, device=None) -> None:
+    """Lean implicit-A scan (default) or r formed for every element; results are identical."""
+    ctx = context(device)
+    _check(ctx, lib().apx_set_lean_scan(ctx, int(bool(enable))), "apx_set_lean_scan")
+
+
+def apx_last_lean_rescans(device=None) -> int:
+    """Rows of the last ap_solve whose ordinary columns decided the exemplar flag after the reduction."""
+    ctx = context(device)
+    a = _I32()
+    _check(ctx, lib().apx_last_lean_rescans(ctx, ctypes.byref(a)), "apx_last_lean_rescans")
     return a.value
 
 

@@ -1289,6 +1289,31 @@ __device__ __forceinline__ uint32_t xbit(int k) { return 1u << ((((k >> 2) & 3) 
 // its inputs (a max against +inf is folded into a canonicalising max)
 __device__ __forceinline__ float max3f(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 3.40282347e+38f); }
 
+// Neighbouring floats of x (x not NaN; -inf steps up to -FLT_MAX).
+__device__ __forceinline__ float f_up(float x) {
+    if (x == 0.0f) return __int_as_float(1);
+    const int b = __float_as_int(x);
+    return __int_as_float(x > 0.0f ? b + 1 : b - 1);
+}
+__device__ __forceinline__ float f_down(float x) {
+    if (x == 0.0f) return -__int_as_float(1);
+    const int b = __float_as_int(x);
+    return __int_as_float(x > 0.0f ? b - 1 : b + 1);
+}
+// The largest float sth with fl(al sth) <= beta.  The off-list value
+// fl(fl(al s) - beta) is positive exactly when fl(al s) > beta (with gradual
+// underflow a difference of two floats is zero only when they are equal),
+// and fl(al s) is monotone in s, so r > 0 iff s > sth.  beta / al is within
+// an ulp or two of the boundary; the walk ends on it and the result is
+// certified, else NaN (al <= 0, overflow), and the row forms r itself.
+__device__ float pos_threshold(float al, float beta) {
+#pragma clang fp contract(off)
+    float x = beta / al;
+    for (int k = 0; k < 4 && al * x > beta; ++k) x = f_down(x);
+    for (int k = 0; k < 4 && !(al * f_up(x) > beta); ++k) x = f_up(x);
+    return (al * x <= beta && al * f_up(x) > beta) ? x : __int_as_float(0x7FC00000);
+}
+
 // DPP lane moves; lanes a row mask leaves out keep the identity of the
 // reduction (-inf for max, INT32_MAX for min), so an integer min fuses the
 // move into one v_min_i32_dpp
@@ -1388,6 +1413,12 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     constexpr int NOWN = 2;                      // listed columns per owner in k_row_imp
     constexpr int EPT = (IMP_KA + T - 1) / T;    // exception-list entries per thread
     static_assert(IMP_K <= 64, "R-list holders are lanes of wavefront 0");
+    // Lean scan (no block term): the ordinary columns' part of the exemplar
+    // decision is left out of the scan.  It can change the decision only when
+    // no listed, new or special column beats the diagonal and D = a(i,i) +
+    // r(i,i) <= 0 (an ordinary a + r is a sum of two values <= 0 when every
+    // column value is), and such rows are scanned again after the reduction.
+    constexpr bool LEAN = !WB;
 
     if (p.st->frozen) return;
     __shared__ int sh_v[2][4 * NW][2];
@@ -1396,6 +1427,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     __shared__ int st_hash[3][64];               // R-listed column -> list position
     __shared__ float st_gam[3][IMP_K];
     __shared__ float st_beta[3];
+    __shared__ float st_sth[3];                  // r = al s - beta > 0 iff s > st_sth (NaN: not certified)
     __shared__ int st_cnt[3];
     __shared__ float st_ad[3];
     __shared__ float st_sd[3];                   // s(i,i)
@@ -1529,6 +1561,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             st_gam[sl][lane - IMP_K] = __uint_as_float(v);
         } else if (lane == 2 * IMP_K) {
             st_beta[sl] = __uint_as_float(v);
+            st_sth[sl] = (LEAN && p.lean) ? pos_threshold(al, __uint_as_float(v)) : __int_as_float(0x7FC00000);
         } else if (lane == 2 * IMP_K + 1) {
             st_cnt[sl] = (int)v;
         } else if (lane == 2 * IMP_K + 2) {
@@ -1639,13 +1672,39 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         mark_x(r0, cur_c);
         load_row(r0, s4);
     }
-    __syncthreads();
+    // a column value above zero (a warm start) voids the D > 0 argument
+    float amx = kNegInf;
+    if constexpr (LEAN) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int c = c0 + j * T * 4;
+            if (c < n) {
+                float4 av;
+                if constexpr (ACV) av = acv[j];
+                else av = ld4(acol_t + c);
+                amx = max3f(amx, av.x);
+                if (c + 1 < n) amx = max3f(amx, av.y);
+                if (c + 2 < n) amx = max3f(amx, av.z);
+                if (c + 3 < n) amx = max3f(amx, av.w);
+            }
+        }
+    }
+    const bool acol_pos = __syncthreads_or(amx > 0.0f) != 0;
 
     for (int64_t i = r0; i < r1; ++i) {
         const int ii = (int)i;
         const int sl = (int)(i % 3);
         const int xs = (int)(i % NXS);
+        // Positivity of the off-list r = al s - beta in the lean scan:
+        // fl(mc s) > sc with (mc, sc) = (1, the row's threshold) when it is
+        // certified and (al, beta) otherwise, exact either way; a row without
+        // a certified threshold is decided over its ordinary columns after
+        // the reduction.
         const float beta = st_beta[sl];
+        const float sth = st_sth[sl];
+        const bool cert = LEAN && sth == sth;
+        const float mc = cert ? 1.0f : al;
+        const float sc = cert ? sth : beta;
         const int cnt = st_cnt[sl];
         const float adg = st_ad[sl];
         const float sdg = st_sd[sl];
@@ -1736,17 +1795,24 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             // columns of this chunk below the diagonal beat it with a tie
             // (the diagonal's own chunk is finished after the scan)
             const float dth = c + 3 < ii ? D : Dn;
+            bool fj = false;   // the chunk holds a first positive
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float s = f4get(sv, e);
-                const float r = al * s - beta;
                 // listed in either list (or out of range): one mask test
                 const bool lst = (mb & (0x11u << e)) != 0u;
-                const bool pos = r > 0.0f;
-                // ordinary with r <= 0: A is the column value
-                const bool ord = !(lst || pos);
-                const float a = ord ? f4get(av, e) : kNegInf;
-                fl = fl || (a + r >= dth);
+                float a;
+                if constexpr (LEAN) {
+                    // ordinary with r <= 0: A is the column value
+                    const bool pos = mc * s > sc;
+                    fj = fj || (pos && !lst);
+                    a = !(lst || pos) ? f4get(av, e) : kNegInf;
+                } else {
+                    const float r = al * s - beta;
+                    const bool ord = !(lst || r > 0.0f);
+                    a = ord ? f4get(av, e) : kNegInf;
+                    fl = fl || (a + r >= dth);
+                }
                 const float w = a + s;
                 const bool g1 = w > v1;
                 l1 = g1 ? 4 * j + e : l1;
@@ -1757,10 +1823,12 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 // thread holds a first positive, and bounds phase 2's values
                 smax = max3f(smax, lst ? kNegInf : s);
             }
+            if constexpr (LEAN) fch = fj ? (fch | (1u << j)) : fch;
         }
         // a first positive somewhere in the thread's ordinary columns: every
         // chunk is searched (rare once the lists settle)
-        fch = (al * smax - beta > 0.0f) ? ((1u << J) - 1u) & (last_in ? ~0u : ~(1u << (J - 1))) : 0u;
+        if constexpr (!LEAN)
+            fch = (al * smax - beta > 0.0f) ? ((1u << J) - 1u) & (last_in ? ~0u : ~(1u << (J - 1))) : 0u;
         Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
         auto merge = [&](float v, float w, int k) {
             fl = fl || (k < ii ? v >= D : v > D);
@@ -1768,7 +1836,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         };
         // the diagonal's chunk: its columns below the diagonal were tested
         // against Dn; a tie with D there also beats the diagonal
-        if (__any(dle >= 0)) {
+        if (!LEAN && __any(dle >= 0)) {
             if (dle >= 0) {
                 float4 sv = s4[0];
                 float4 av;
@@ -1887,6 +1955,36 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         wg_top2<NW>(t2, sh_v[i & 1], sh_i[i & 1], lane, wave);
         // the previous row's additions to global partials are visible
         if constexpr (GP) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "global");
+        // A lean row whose listed and special columns do not beat the
+        // diagonal, with D <= 0 (or a positive column value), or without a
+        // certified threshold: the ordinary columns decide, tested as the
+        // full scan tests them (S and acol reloaded; the row's mask slot is
+        // intact until the next row)
+        if (LEAN && __builtin_amdgcn_readfirstlane((int)(!cert || (dec_fail[xs] == 0 && (!(D > 0.0f) || acol_pos))))) {
+            bool f2 = false;
+            const float *srow = p.S + i * ld;
+#pragma unroll 1
+            for (int j = 0; j < J; ++j) {
+                const int c = c0 + j * T * 4;
+                if (c >= n) continue;
+                const float4 sv = ld4(srow + c);
+                const float4 av = ld4(acol_t + c);
+                const uint32_t mb = mb8[j * T + tid];
+                const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = c + e;
+                    const float r = al * f4get(sv, e) - beta;
+                    if (k < n && !((ex >> e) & 1u) && !(r > 0.0f)) {
+                        const float q = f4get(av, e) + r;
+                        f2 = f2 || (k < ii ? q >= D : q > D);
+                    }
+                }
+            }
+            if (__any(f2) && lane == 0) atomicOr(&dec_fail[xs], 1);
+            if (tid == 0) atomicAdd(&p.st->lean_rescans, 1);
+            __syncthreads();
+        }
         if (tid == 0) {
             const uint8_t ef = (uint8_t)(dec_fail[xs] == 0);
             if (ef_prev != ef) my_changed = 1;

@@ -303,7 +303,7 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
                               (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.imp,
                               (uint64_t)pl.grid | ((uint64_t)mode << 32) | ((uint64_t)ctx->implicit_k << 40) |
                                   ((uint64_t)ctx->implicit_a << 48),
-                              (uint64_t)pl.threads, (uint64_t)pl.lds_bytes};
+                              (uint64_t)pl.threads | ((uint64_t)ctx->lean << 32), (uint64_t)pl.lds_bytes};
     if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
         if (ctx->gexec) {
             (void)hipGraphExecDestroy(ctx->gexec);
@@ -316,6 +316,7 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
             if (mode == SOLVE_IMPLICIT_A) {
                 ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a);
                 ia.blk = ctx->ia_blk;
+                ia.lean = ctx->lean ? 1 : 0;
                 e = launch_row_ia(pl, ia,
                                   ctx->cap);
             } else if (mode == SOLVE_IMPLICIT_R) {
@@ -575,6 +576,18 @@ apx_status apx_last_fallback(apx_ctx *ctx, int32_t *reasons) {
     return APX_OK;
 }
 
+apx_status apx_set_lean_scan(apx_ctx *ctx, int enable) {
+    if (!ctx) return APX_EINVAL;
+    ctx->lean = enable != 0;
+    return APX_OK;
+}
+
+apx_status apx_last_lean_rescans(apx_ctx *ctx, int32_t *rows) {
+    if (!ctx || !rows) return APX_EINVAL;
+    *rows = ctx->last_lean_rescans;
+    return APX_OK;
+}
+
 apx_status apx_set_graphs(apx_ctx *ctx, int enable) {
     if (!ctx) return APX_EINVAL;
     ctx->graphs = enable != 0;
@@ -783,6 +796,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                 if (imp_a) {
                     ImpArgs ia = imp_args(S, A, n, ld, lam, w, buf, false, ctx->implicit_k, ctx->implicit_a);
                     ia.blk = ia_blk;
+                    ia.lean = ctx->lean ? 1 : 0;
                     HIP_TRY(launch_row_ia(apl, ia, s), "row pass");
                 }
                 else if (implicit)
@@ -846,6 +860,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
     ctx->last_exp_iters = T - ctx->last_imp_iters;
     ctx->last_ia_iters = ia_until < T ? ia_until : T;
     ctx->last_fallback = fallback | (hst->imp_owner ? APX_NOTE_R_OWNER : 0);
+    ctx->last_lean_rescans = hst->lean_rescans;
     if (imp_a) {
         HIP_TRY(launch_ia_materialize(A, ld, (int32_t)n, w.acol[T & 1], w.adiag[T & 1],
                                       w.xst + (T & 1) * w.xstride, s, ia_blk, lam, T), "materialize A");

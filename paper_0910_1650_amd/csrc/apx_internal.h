@@ -39,7 +39,7 @@ struct ApState {
     float msg_tol;
     int32_t imp_owner;  // 1: an implicit-A pass let a thread own more listed R columns than k_row_imp keeps
     int32_t imp_alpha_one;  // 1: alpha_t = 1 for every t (R_0 is the undamped Eq. (2) step, not 0)
-    int32_t pad[1];
+    int32_t lean_rescans;   // rows of lean implicit-A scans that the ordinary columns had to decide
 };
 
 // Row-pass modes.  A full pass of iteration t reads R_t, A_{t-1}, S and the
@@ -162,6 +162,7 @@ struct ImpArgs {
     // column range [blk[2i], blk[2i+1]); an element whose responsibility was
     // never positive has a_t = acol_t(k) + lambda^t a_0(i,k).  Null: A_0 = 0.
     const int32_t *blk;
+    int32_t lean;               // 1: rows with a certified threshold take the lean scan
 };
 // Implicit availabilities.  With A_0 = 0, Eq. (3) with damping gives every
 // off-diagonal element (i,k) whose responsibility r_s(i,k) was never positive
@@ -293,6 +294,8 @@ struct apx_ctx {
     int64_t implicit_a_min_n = 4096;  // smaller cold starts run explicit (faster there)
     int32_t last_ia_iters = 0;        // iterations of the last ap_solve run with implicit A
     int32_t last_fallback = 0;        // why the last ap_solve left an implicit form (imp_abort bits)
+    bool lean = true;                 // lean scan in the implicit-A pass (off: every row forms r)
+    int32_t last_lean_rescans = 0;    // rows of the last ap_solve whose ordinary columns decided
     // autotuner (tune.hip)
     bool autotune = false;            // tune unseen size buckets on first use
     int force_form = 0;               // form timing in progress: the form every solve uses
