@@ -385,6 +385,33 @@ apx_status ap_iterate_noalloc(apx_ctx *ctx, const float *S, int64_t n, int64_t l
 apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
                     int32_t warm, const apx_params *params, int32_t *idx, apx_result *res);
 
+/*
+ * ap_solve_mf -- Algorithm 1 from the points, without any n x n buffer
+ * (matrix-free; beyond the paper, for problems whose S does not fit in
+ * memory).  Every iteration rebuilds S one panel of rows at a time from X
+ * (device, n x d FP32, row stride ldx) on the matrix cores, each entry with
+ * the value ap_similarity would store for the same pref_mode / pref_vec /
+ * pref_scalar / noise_seed / noise_rel (Section 2: s(i,k) = -||x_i -
+ * x_k||^2, preferences on the diagonal, tie noise), and runs the implicit
+ * message passes on those rows; the median preference takes three sweeps of
+ * panels before the run.  Memory: two panels of panel_rows x round64(n)
+ * floats (panel_rows = 0: at most 1 GiB per panel, at least 8 rows per
+ * workgroup) plus O(n) state and the column partials of the panels.  A
+ * cold start only; the exemplar set, labels (idx, device, n), iteration
+ * count and sums are those of ap_similarity + ap_solve up to the rounding of
+ * the column sums' grouping (each panel sums its own rows).  pref_out (host,
+ * nullable) gets the scalar preference.  APX_ENOTIMPL when n is outside the
+ * implicit passes (2 .. 65536), when a row's message list overflows (the
+ * explicit form would need R and A), and for APX_RAW_LABELS or
+ * APX_MSG_THRESHOLD; APX_EINVAL for non-finite X or
+ * pref_vec, a bad preference mode, or panel_rows below one row per
+ * workgroup.  Synchronises the stream.
+ */
+apx_status ap_solve_mf(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx, int32_t pref_mode,
+                       const float *pref_vec, float pref_scalar, uint64_t noise_seed, double noise_rel,
+                       int64_t panel_rows, const apx_params *params, int32_t *idx, apx_result *res,
+                       double *pref_out);
+
 /* One instance of a batched solve: its own S (preferences on the diagonal),
  * R, A (device, FP32, ld >= n, ld % 4 == 0) and labels idx (device, n). */
 typedef struct {

@@ -103,6 +103,9 @@ SIGNATURES = {
     "ap_iterate_noalloc": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, ctypes.c_float, _I32, _P]),
     "ap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, ctypes.POINTER(apx_params), _P,
                                 ctypes.POINTER(apx_result)]),
+    "ap_solve_mf": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _I32, _P, ctypes.c_float, ctypes.c_uint64,
+                                   ctypes.c_double, _I64, ctypes.POINTER(apx_params), _P,
+                                   ctypes.POINTER(apx_result), ctypes.POINTER(ctypes.c_double)]),
     "ap_solve_batched": (ctypes.c_int, [_P, _I32, ctypes.POINTER(apx_instance), _I32,
                                         ctypes.POINTER(apx_params), ctypes.POINTER(apx_result)]),
     "pap_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _P, _I32, _P, _P, ctypes.POINTER(apx_params),
@@ -292,6 +295,32 @@ def ap_solve(S: torch.Tensor, R: torch.Tensor, A: torch.Tensor, damping: float =
     _check(ctx, lib().ap_solve(ctx, Sp, n, ld, Rp, Ap, warm, ctypes.byref(prm), _P(idx.data_ptr()),
                                ctypes.byref(res)), "ap_solve")
     return idx, _res(res)
+
+
+def ap_solve_mf(X: torch.Tensor, pref: str | float | torch.Tensor = "median", noise_seed: int = 0,
+                noise_rel: float = 1e-12, damping: float = 0.5, max_iter: int = 200, conv_iter: int = 15,
+                panel_rows: int = 0, check_every: int = 0, flags: int = 0):
+    """Matrix-free Algorithm 1 from the points X (n,d) float32: S is rebuilt panel by
+    panel each iteration (no n x n buffer); returns (idx int32 tensor, Result, preference)."""
+    if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
+        raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
+    n, d = X.shape
+    if isinstance(pref, str):
+        mode, vec, scal = APX_PREF_MEDIAN, None, 0.0
+    elif isinstance(pref, torch.Tensor):
+        mode, vec, scal = APX_PREF_VECTOR, pref.contiguous(), 0.0
+    else:
+        mode, vec, scal = APX_PREF_SCALAR, None, float(pref)
+    idx = torch.empty(n, dtype=torch.int32, device=X.device)
+    prm = apx_params(damping, max_iter, conv_iter, check_every, flags, 0.0)
+    res = apx_result()
+    out = ctypes.c_double(float("nan"))
+    ctx = context(X.device)
+    _check(ctx, lib().ap_solve_mf(ctx, _P(X.data_ptr()), n, d, X.stride(0), mode,
+                                  _P(vec.data_ptr()) if vec is not None else None, scal, noise_seed, noise_rel,
+                                  panel_rows, ctypes.byref(prm), _P(idx.data_ptr()), ctypes.byref(res),
+                                  ctypes.byref(out)), "ap_solve_mf")
+    return idx, _res(res), out.value
 
 
 def apx_workspace_size(op: int, n: int = 0, ld: int = 0, d: int = 0, count: int = 0, sizes=None,

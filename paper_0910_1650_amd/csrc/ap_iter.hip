@@ -769,8 +769,8 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t *eflag, int32_t 
 // One wavefront per row: label = best exemplar by s(i,k), lowest k on ties.
 __global__ __launch_bounds__(256) void k_labels(FinalArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.n) return;
+    const int64_t i = a.row0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= (a.row1 > 0 ? a.row1 : a.n)) return;
     const int m = *a.nex;
     const float *Srow = a.S + i * a.ld;
     double dp = 0.0, ep = 0.0;
@@ -1232,7 +1232,7 @@ __global__ __launch_bounds__(T) void k_row_imp(ImpArgs p) {
     }
 
     {
-        float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+        float *P = p.partial + (p.part0 + (int64_t)blockIdx.x) * p.ldp;
 #pragma unroll
         for (int j = 0; j < J; ++j)
             if (j < J - 1 || last_in) st4(P + c0 + j * T * 4, lpart[j * T + tid]);
@@ -1492,7 +1492,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     const float *acol_p = p.acol[(tpass + 1) & 1];
     const float *adiag_t = p.adiag[tpass & 1];
     const int xcap = p.xcap;
-    float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+    float *P = p.partial + (p.part0 + (int64_t)blockIdx.x) * p.ldp;
 
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -2497,15 +2497,26 @@ hipError_t launch_copy_rows(float *dst, const float *src, int64_t rows, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalArgs &a, hipStream_t s) {
+hipError_t launch_compact(const FinalArgs &a, hipStream_t s) {
     k_compact<<<1, 1024, 0, s>>>(a.eflag, a.n, a.ex, a.nex);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_labels<<<(a.n + 3) / 4, 256, 0, s>>>(a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+hipError_t launch_labels(const FinalArgs &a, hipStream_t s) {
+    const int64_t rows = (a.row1 > 0 ? a.row1 : a.n) - a.row0;
+    if (rows <= 0) return hipSuccess;
+    k_labels<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+hipError_t launch_sum2(const FinalArgs &a, hipStream_t s) {
     k_sum2<<<1, 1024, 0, s>>>(a.contrib, a.n, a.sums);
     return hipGetLastError();
+}
+hipError_t launch_finalize(const FinalArgs &a, hipStream_t s) {
+    hipError_t e = launch_compact(a, s);
+    if (e != hipSuccess) return e;
+    e = launch_labels(a, s);
+    if (e != hipSuccess) return e;
+    return launch_sum2(a, s);
 }
 
 

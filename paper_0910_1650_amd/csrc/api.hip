@@ -907,3 +907,232 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
 }
 
 }  // extern "C"
+
+// ---- matrix-free AP ----------------------------------------------------------
+// Workspace of ap_solve_mf: the similarity scratch, the run state and message
+// state (no n x n buffer), the partials of every panel launch of a pass, and
+// two panels (S rows; and rows the implicit passes write only when a list
+// overflows, which ends the run).
+namespace {
+struct MfLayout {
+    size_t o_sim, o_t, o_c, o_d, o_p, o_dec, o_e, o_st, o_ex, o_nex, o_con, o_sum, o_imp, o_acol, o_x, o_pan, o_dum,
+        bytes;
+};
+MfLayout mf_layout(int64_t n, int64_t ld, int64_t prows, int64_t nparts) {
+    MfLayout o{};
+    WsLayout L;
+    const int64_t ldp = round4(n);
+    o.o_sim = L.take(mf_sim_bytes(n));
+    o.o_t = L.take(sizeof(float) * ldp);
+    o.o_c = L.take(sizeof(float) * ldp);
+    o.o_d = L.take(sizeof(float) * ldp);
+    o.o_p = L.take(sizeof(float) * ldp * (size_t)nparts);
+    o.o_dec = L.take(sizeof(int32_t) * n);
+    o.o_e = L.take((size_t)n);
+    o.o_st = L.take(sizeof(ApState));
+    o.o_ex = L.take(sizeof(int32_t) * n);
+    o.o_nex = L.take(sizeof(int32_t));
+    o.o_con = L.take(sizeof(double) * 2 * (size_t)n);
+    o.o_sum = L.take(sizeof(double) * 2);
+    o.o_imp = L.take(2 * (size_t)imp_layout(n).stride);
+    o.o_acol = L.take(4 * sizeof(float) * (size_t)ldp);
+    o.o_x = L.take(2 * (size_t)x_layout(n).stride);
+    o.o_pan = L.take(sizeof(float) * (size_t)prows * (size_t)ld);
+    o.o_dum = L.take(sizeof(float) * (size_t)prows * (size_t)ld);
+    o.bytes = L.off;
+    return o;
+}
+int64_t mf_default_rows(int64_t n, int64_t ld, int grid) {
+    // panels of at most 1 GiB, at least 8 rows per workgroup of a pass
+    int64_t p = ((int64_t)1 << 30) / (4 * ld);
+    if (p < 8 * (int64_t)grid) p = 8 * (int64_t)grid;
+    return p < n ? p : n;
+}
+}  // namespace
+
+extern "C" apx_status ap_solve_mf(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
+                                  int32_t pref_mode, const float *pref_vec, float pref_scalar, uint64_t noise_seed,
+                                  double noise_rel, int64_t panel_rows, const apx_params *params, int32_t *idx,
+                                  apx_result *res, double *pref_out) {
+    if (!ctx) return APX_EINVAL;
+    if (!X || !idx || !params || !res) return set_err(ctx, APX_EINVAL, "X, params, idx and res must be non-null");
+    if (d < 1 || ldx < d) return set_err(ctx, APX_EINVAL, "need d >= 1 and ldx >= d");
+    if (pref_mode < APX_PREF_MEDIAN || pref_mode > APX_PREF_VECTOR) return set_err(ctx, APX_EINVAL, "bad pref_mode");
+    if (pref_mode == APX_PREF_VECTOR && !pref_vec) return set_err(ctx, APX_EINVAL, "pref_vec is null");
+    if (pref_mode == APX_PREF_SCALAR && !std::isfinite(pref_scalar))
+        return set_err(ctx, APX_EINVAL, "pref_scalar is not finite");
+    if (!(noise_rel >= 0.0) || !std::isfinite(noise_rel)) return set_err(ctx, APX_EINVAL, "bad noise_rel");
+    APX_TRY(check_params(ctx, params));
+    if (params->flags & (APX_RAW_LABELS | APX_MSG_THRESHOLD))
+        return set_err(ctx, APX_ENOTIMPL, "raw labels and the message-change rule need R and A in memory");
+    PassPlan ipl{}, apl{};
+    if (n < 2 || n > 65536 || !imp_plan(n, ctx->num_cus, &ipl) || !ia_plan(n, ctx->num_cus, &apl) ||
+        ctx->implicit_k <= 0 || ctx->implicit_a <= 0)
+        return set_err(ctx, APX_ENOTIMPL, "n = %lld outside the implicit passes (or they are disabled)", (long long)n);
+    const int64_t ld = (n + 63) & ~int64_t(63);
+    if (panel_rows < 0) return set_err(ctx, APX_EINVAL, "panel_rows < 0");
+    const int gmax = ipl.grid > apl.grid ? ipl.grid : apl.grid;
+    int64_t P = panel_rows > 0 ? panel_rows : mf_default_rows(n, ld, gmax);
+    if (P > n) P = n;
+    if (P < gmax) return set_err(ctx, APX_EINVAL, "panel_rows must be >= %d (one row per workgroup)", gmax);
+    const int64_t Q = (n + P - 1) / P;
+    const float lam = params->damping;
+    DevGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    std::memset(res, 0, sizeof *res);
+
+    const MfLayout o = mf_layout(n, ld, P, Q * gmax);
+    APX_TRY(ws_reserve(ctx, ctx->ws_base + o.bytes));
+    char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
+    // non-finite points or preferences are rejected before anything runs
+    int32_t *hflag = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 2048);
+    HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(ctx->dflag), sizeof(int32_t), 0, s), "finite check");
+    HIP_TRY(launch_check_finite(X, n, d, ldx, ctx->dflag, s), "finite check");
+    if (pref_mode == APX_PREF_VECTOR) HIP_TRY(launch_check_finite(pref_vec, 1, n, n, ctx->dflag, s), "finite check");
+    HIP_TRY(hipMemcpyAsync(hflag, ctx->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "finite check");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (*hflag) return set_err(ctx, APX_EINVAL, "X or pref_vec holds a NaN or infinite value");
+
+    MfSim m{X, n, d, ldx, pref_mode, pref_vec, pref_scalar, noise_seed, noise_rel, b + o.o_sim};
+    float *panel = reinterpret_cast<float *>(b + o.o_pan);
+    float *dummy = reinterpret_cast<float *>(b + o.o_dum);
+    HIP_TRY(mf_sim_setup(m, panel, ld, P, s), "similarity setup");
+    {
+        double *h = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 1024);
+        uint32_t *hk = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->pinned) + 1088);
+        HIP_TRY(hipMemcpyAsync(h, mf_sim_pref(m), sizeof(double), hipMemcpyDeviceToHost, s), "pref copy");
+        HIP_TRY(hipMemcpyAsync(hk, mf_sim_bounds(m), 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "bounds copy");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (hk[1] >= 0xff800000u || hk[0] <= 0x007fffffu)
+            return set_err(ctx, APX_EINVAL, "similarities overflow FP32");
+        if (pref_out) *pref_out = pref_mode == APX_PREF_VECTOR ? NAN : *h;
+    }
+
+    IterWs w{};
+    w.tcol = reinterpret_cast<float *>(b + o.o_t);
+    w.ccol = reinterpret_cast<float *>(b + o.o_c);
+    w.rdiag = reinterpret_cast<float *>(b + o.o_d);
+    w.partial = reinterpret_cast<float *>(b + o.o_p);
+    w.ldp = round4(n);
+    w.dec = reinterpret_cast<int32_t *>(b + o.o_dec);
+    w.eflag = reinterpret_cast<uint8_t *>(b + o.o_e);
+    w.st = reinterpret_cast<ApState *>(b + o.o_st);
+    w.ex = reinterpret_cast<int32_t *>(b + o.o_ex);
+    w.nex = reinterpret_cast<int32_t *>(b + o.o_nex);
+    w.contrib = reinterpret_cast<double *>(b + o.o_con);
+    w.sums = reinterpret_cast<double *>(b + o.o_sum);
+    w.imp = b + o.o_imp;
+    w.imp_stride = imp_layout(n).stride;
+    for (int q = 0; q < 2; ++q) {
+        w.acol[q] = reinterpret_cast<float *>(b + o.o_acol) + q * w.ldp;
+        w.adiag[q] = reinterpret_cast<float *>(b + o.o_acol) + (2 + q) * w.ldp;
+    }
+    w.xst = b + o.o_x;
+    w.xstride = x_layout(n).stride;
+
+    HIP_TRY(launch_state_init(w.st, params->max_iter, params->conv_iter, lam, s, 0, 0.0f, 0), "state init");
+    HIP_TRY(launch_fill_u8(w.eflag, n, 0, s), "flags");
+    const ImpLayout il = imp_layout(n);
+    HIP_TRY(launch_fill_f32_rows(reinterpret_cast<float *>(w.imp + il.beta), 1, n, n, 0.0f, s), "implicit state");
+    HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.imp + il.cnt), 4 * n, 0, s), "implicit state");
+    HIP_TRY(launch_fill_f32_rows(w.acol[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
+    HIP_TRY(launch_fill_f32_rows(w.adiag[0], 1, w.ldp, w.ldp, 0.0f, s), "implicit A");
+    HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(w.xst + x_layout(n).cnt), 4 * n, 0, s), "implicit A");
+
+    // Rows [p0, p1) of S live in the panel: every kernel of the pass reads
+    // row i at S + i * ld, so it gets the panel shifted back by p0 rows (only
+    // its own rows are dereferenced).  Each panel launch writes its own rows
+    // of partials; the column reduce sums all of them.
+    auto shifted = [&](float *base, int64_t p0) { return base - p0 * ld; };
+    // R_1 from R_0 = A_0 = 0 (Eq. (2), damped), panel by panel
+    for (int64_t q = 0; q < Q; ++q) {
+        const int64_t p0 = q * P, p1 = p0 + P < n ? p0 + P : n;
+        HIP_TRY(mf_sim_panel(m, panel, ld, p0, p1, nullptr, s), "similarity panel");
+        float *buf[2] = {shifted(dummy, p0), shifted(dummy, p0)};
+        ImpArgs ia = imp_args(shifted(panel, p0), shifted(dummy, p0), n, ld, lam, w, buf, true, ctx->implicit_k);
+        ia.row_begin = p0;
+        ia.row_end = p1;
+        ia.part0 = q * ipl.grid;
+        HIP_TRY(launch_row_imp(ipl, IMP_PRO_COLD, ia, s), "prologue");
+    }
+    w.nparts = (int)(Q * ipl.grid);
+    HIP_TRY(launch_col_reduce(col_args(w, n, nullptr, 0, 0, lam), s), "column reduce");
+
+    int chunk = params->check_every > 0 ? params->check_every : 16;
+    ApState *hst = static_cast<ApState *>(ctx->pinned);
+    w.nparts = (int)(Q * apl.grid);
+    int32_t t = 1;
+    bool stop = false;
+    while (!stop) {
+        const int32_t t_end = t + chunk <= params->max_iter + 1 ? t + chunk : params->max_iter + 1;
+        for (; t < t_end; ++t) {
+            for (int64_t q = 0; q < Q; ++q) {
+                const int64_t p0 = q * P, p1 = p0 + P < n ? p0 + P : n;
+                HIP_TRY(mf_sim_panel(m, panel, ld, p0, p1, w.st, s), "similarity panel");
+                float *buf[2] = {shifted(dummy, p0), shifted(dummy, p0)};
+                ImpArgs ia = imp_args(shifted(panel, p0), shifted(dummy, p0), n, ld, lam, w, buf, false,
+                                      ctx->implicit_k, ctx->implicit_a);
+                ia.lean = ctx->lean ? 1 : 0;
+                ia.row_begin = p0;
+                ia.row_end = p1;
+                ia.part0 = q * apl.grid;
+                HIP_TRY(launch_row_ia(apl, ia, s), "row pass");
+            }
+            HIP_TRY(launch_col_reduce(col_args(w, n, w.st, 1, t, lam), s), "column reduce");
+        }
+        HIP_TRY(hipMemcpyAsync(hst, w.st, sizeof(ApState), hipMemcpyDeviceToHost, s), "state copy");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (hst->frozen == 2)
+            return set_err(ctx, APX_ENOTIMPL,
+                           "a row list overflowed at iteration %d: the matrix-free form needs the implicit "
+                           "messages throughout",
+                           hst->iter);
+        stop = hst->frozen || t > params->max_iter;
+    }
+    const int32_t T = hst->iter;
+    res->iterations = T;
+    res->converged = hst->converged;
+    ctx->last_imp_iters = T;
+    ctx->last_exp_iters = 0;
+    ctx->last_ia_iters = T;
+    ctx->last_fallback = hst->imp_owner ? APX_NOTE_R_OWNER : 0;
+    ctx->last_lean_rescans = hst->lean_rescans;
+
+    // labels: exemplars from the last pass's flags, every row's best
+    // exemplar from its panel
+    FinalArgs fa{};
+    fa.ld = ld;
+    fa.n = (int32_t)n;
+    fa.eflag = w.eflag;
+    fa.ex = w.ex;
+    fa.nex = w.nex;
+    fa.idx = idx;
+    fa.contrib = w.contrib;
+    fa.sums = w.sums;
+    HIP_TRY(launch_compact(fa, s), "finalize");
+    for (int64_t q = 0; q < Q; ++q) {
+        const int64_t p0 = q * P, p1 = p0 + P < n ? p0 + P : n;
+        HIP_TRY(mf_sim_panel(m, panel, ld, p0, p1, nullptr, s), "similarity panel");
+        fa.S = shifted(panel, p0);
+        fa.row0 = p0;
+        fa.row1 = p1;
+        HIP_TRY(launch_labels(fa, s), "labels");
+    }
+    HIP_TRY(launch_sum2(fa, s), "finalize");
+    double *hd = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned) + 256);
+    int32_t *hn = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + 512);
+    HIP_TRY(hipMemcpyAsync(hd, w.sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "sums");
+    HIP_TRY(hipMemcpyAsync(hn, w.nex, sizeof(int32_t), hipMemcpyDeviceToHost, s), "nex");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    res->n_exemplars = *hn;
+    if (*hn == 0) {
+        res->dpsim = res->expref = res->netsim = NAN;
+    } else {
+        res->dpsim = hd[0];
+        res->expref = hd[1];
+        res->netsim = hd[0] + hd[1];
+    }
+    res->status = APX_OK;
+    return APX_OK;
+}
+

@@ -163,6 +163,7 @@ struct ImpArgs {
     // never positive has a_t = acol_t(k) + lambda^t a_0(i,k).  Null: A_0 = 0.
     const int32_t *blk;
     int32_t lean;               // 1: rows with a certified threshold take the lean scan
+    int64_t part0;              // first partial row of this launch (row panels of one pass)
 };
 // Implicit availabilities.  With A_0 = 0, Eq. (3) with damping gives every
 // off-diagonal element (i,k) whose responsibility r_s(i,k) was never positive
@@ -236,8 +237,13 @@ struct FinalArgs {
     double *contrib;    // 2n scratch
     double *sums;       // [dpsim, expref]
     const int32_t *raw; // nullable: raw decisions to use as the labels
+    int64_t row0, row1; // labels of rows [row0, row1) only (row1 = 0: all rows)
 };
 hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+// The finalize steps one by one (labels of one row panel at a time).
+hipError_t launch_compact(const FinalArgs &a, hipStream_t s);
+hipError_t launch_labels(const FinalArgs &a, hipStream_t s);
+hipError_t launch_sum2(const FinalArgs &a, hipStream_t s);
 
 // Autotuned choices for one problem-size bucket (see tune.hip).
 struct TuneEntry {
@@ -341,6 +347,24 @@ struct BatchSpec {
 size_t batched_ws_bytes(int32_t count, const BatchSpec *spec, int num_cus);
 // Workspace bytes of the other calls (apx_workspace_size).
 size_t similarity_ws_bytes(int64_t n);
+// Matrix-free S (similarity.hip): rows of S rebuilt from X one panel at a
+// time, each entry with the value ap_similarity stores.
+struct MfSim {
+    const float *X;
+    int64_t n, d, ldx;
+    int32_t pref_mode;
+    const float *pref_vec;
+    float pref_scalar;
+    uint64_t seed;
+    double noise_rel;
+    char *ws;   // mf_sim_bytes(n) of device scratch
+};
+size_t mf_sim_bytes(int64_t n);
+hipError_t mf_sim_setup(const MfSim &m, float *panel, int64_t ld, int64_t prows, hipStream_t s);
+hipError_t mf_sim_panel(const MfSim &m, float *panel, int64_t ld, int64_t p0, int64_t p1, const ApState *st,
+                        hipStream_t s);
+const double *mf_sim_pref(const MfSim &m);       // device: the scalar preference
+const uint32_t *mf_sim_bounds(const MfSim &m);   // device: bounds of the off-diagonal keys
 size_t pap_ws_bytes(int64_t n, int64_t ld, int32_t k, const int64_t *sizes, int num_cus);
 size_t lap_ws_bytes(int64_t n, int64_t d, int64_t L, int num_cus);
 size_t lap_full_ws_bytes(int64_t n, int64_t d, int64_t L, int64_t m0, int num_cus);

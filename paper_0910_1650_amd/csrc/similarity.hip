@@ -58,28 +58,17 @@ struct SimArgs {
 // (g, q = 0..3), written directly (one float per row, 128-byte row
 // segments per half wavefront) and mirrored (the four rows q are
 // consecutive columns of S's row c: one float4).
-__global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
-    // Decode the upper-triangle tile (bi <= bj) from the linear block index.
-    const int64_t T = a.tiles_per_side;
-    int64_t t = blockIdx.x, bi = 0;
-    while (t >= T - bi) {
-        t -= T - bi;
-        ++bi;
-    }
-    const int64_t bj = bi + t;
-    const int64_t row0 = bi * BM, col0 = bj * BM;
+constexpr int LDA = BM + 1;   // padded LDS rows: conflict-free transposed stores
 
-    constexpr int LDA = BM + 1;                     // padded: conflict-free transposed stores
-    __shared__ float As[KB * LDA], Bs[KB * LDA];    // 33 KB of staging
-    __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
+// Gram block <x_i, x_k> of rows row0.. and columns col0.. (BM each) into the
+// accumulators: wavefront (wm, wn) holds the 2 x 2 32x32 blocks at rows
+// wm*64 + 32x, columns wn*64 + 32y.  Every entry sums its products in the
+// same order (K chunks of KB, two per MFMA), whichever tile it lies in and
+// whichever of x_i, x_k is the A operand, so an entry has one value.
+__device__ __forceinline__ void gram_tile(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t row0,
+                                          int64_t col0, v16f (&acc)[2][2], float *As, float *Bs) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    for (int e = tid; e < BM; e += NT) {
-        nr[e] = row0 + e < a.n ? a.nrm[row0 + e] : 0.0f;
-        nc[e] = col0 + e < a.n ? a.nrm[col0 + e] : 0.0f;
-    }
-
-    v16f acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -97,12 +86,12 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             const int m = e / KB, kk = e % KB;
             const int64_t kg = k0 + kk;
             const int64_t ra = row0 + m, rb = col0 + m;
-            va[u] = (ra < a.n && kg < a.d) ? a.X[ra * a.ldx + kg] : 0.0f;
-            vb[u] = (rb < a.n && kg < a.d) ? a.X[rb * a.ldx + kg] : 0.0f;
+            va[u] = (ra < n && kg < d) ? X[ra * ldx + kg] : 0.0f;
+            vb[u] = (rb < n && kg < d) ? X[rb * ldx + kg] : 0.0f;
         }
     };
     fetch(0);
-    for (int64_t k0 = 0; k0 < a.d; k0 += KB) {
+    for (int64_t k0 = 0; k0 < d; k0 += KB) {
         // staged k-major; the previous chunk's MFMAs are done (barrier below)
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
@@ -112,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
             Bs[kk * LDA + m] = vb[u];
         }
         __syncthreads();
-        if (k0 + KB < a.d) fetch(k0 + KB);
+        if (k0 + KB < d) fetch(k0 + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 2) {
             const int kr = kk + (lane >> 5);
@@ -129,6 +118,29 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
+    // Decode the upper-triangle tile (bi <= bj) from the linear block index.
+    const int64_t T = a.tiles_per_side;
+    int64_t t = blockIdx.x, bi = 0;
+    while (t >= T - bi) {
+        t -= T - bi;
+        ++bi;
+    }
+    const int64_t bj = bi + t;
+    const int64_t row0 = bi * BM, col0 = bj * BM;
+
+    __shared__ float As[KB * LDA], Bs[KB * LDA];    // 33 KB of staging
+    __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    for (int e = tid; e < BM; e += NT) {
+        nr[e] = row0 + e < a.n ? a.nrm[row0 + e] : 0.0f;
+        nc[e] = col0 + e < a.n ? a.nrm[col0 + e] : 0.0f;
+    }
+    v16f acc[2][2];
+    gram_tile(a.X, a.n, a.d, a.ldx, row0, col0, acc, As, Bs);
 
     uint32_t kmin = 0xffffffffu, kmax = 0u;
     const bool diag_tile = (bi == bj);
@@ -241,9 +253,10 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
 
 // Histogram of the keys of upper-triangle entries whose high bits match the
 // current prefix of each rank.  shift/bits select the digit of this pass.
+// Rows [r0, r1) of S (row i at S + i * ld).
 __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int64_t ld,
                                                   const SelState *st, int pass,
-                                                  unsigned long long *hist) {
+                                                  unsigned long long *hist, int64_t r0, int64_t r1) {
     // dynamic LDS: one histogram of nb bins on the first pass (both ranks
     // start from the same empty prefix), two on the others
     extern __shared__ uint32_t hsh[];
@@ -266,7 +279,8 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
         if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
         if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
     };
-    for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
+    const int64_t re = r1 < n - 1 ? r1 : n - 1;
+    for (int64_t i = r0 + blockIdx.x; i < re; i += gridDim.x) {
         const float *row = S + i * ld;
         // columns i+1 .. n-1: the unaligned head one by one, then 16-byte
         // loads (rows start 16-byte aligned: ld is a multiple of 4)
@@ -370,6 +384,18 @@ __device__ __forceinline__ double noise_u(uint64_t seed, int64_t n, int64_t i, i
     return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
+// fl32((double)v + scale * u) for u in [0, 1).  When scale <= |v| 2^-27 the
+// sum stays below v + 2^(e-26) (2^e <= |v|), far from the midpoint to v's
+// upper neighbour (at least 2^(e-25) away, also when |v| is a power of two
+// and v < 0), so it rounds back to v and the counter generator is skipped:
+// the same value, without its 64-bit arithmetic (the tie noise is far below
+// one FP32 ulp of most entries).
+__device__ __forceinline__ float add_noise(float v, double scale, uint64_t seed, int64_t n, int64_t i, int64_t k) {
+    const double dv = (double)v;
+    if (scale <= fabs(dv) * 0x1p-27) return v;
+    return (float)(dv + scale * noise_u(seed, n, i, k));
+}
+
 // Range of S with the preferences on the diagonal (FP64).
 __global__ void k_pref_range(PrefArgs a, double *range_out) {
     __shared__ float lo[256], hi[256];
@@ -404,8 +430,8 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
         float *row = a.S + i * a.ld;
         if (a.noise_rel > 0.0) {
             auto one = [&](int64_t k, float v) -> float {
-                const double base = (k == i) ? pref_of(a, i, pm) : (double)v;
-                return (float)(base + scale * noise_u(a.seed, a.n, i, k));
+                if (k != i) return add_noise(v, scale, a.seed, a.n, i, k);
+                return (float)(pref_of(a, i, pm) + scale * noise_u(a.seed, a.n, i, k));
             };
             // 16-byte loads and stores (rows are 16-byte aligned); the
             // padding past n is left alone
@@ -455,7 +481,7 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
                 if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
                 if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
             }
-            return k == i ? v : (float)((double)v + scale * noise_u(a.seed, a.n, i, k));
+            return k == i ? v : add_noise(v, scale, a.seed, a.n, i, k);
         };
         for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.n; k += 4 * (int64_t)blockDim.x) {
             if (k + 3 < a.n) {
@@ -485,6 +511,98 @@ __global__ void k_pref_diag(PrefArgs a, const double *range) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
         const double base = pref_of(a, i, pm);
         a.S[i * a.ld + i] = a.noise_rel > 0.0 ? (float)(base + scale * noise_u(a.seed, a.n, i, i)) : (float)base;
+    }
+}
+
+// ---- matrix-free S: row panels ---------------------------------------------
+// Rows [p0, p1) of S into a panel (row i at Sp + (i - p0) * ld), every tile
+// of the panel computed (nothing mirrored).  An entry gets the value that
+// ap_similarity stores: the same Gram sum (gram_tile), then, with final set,
+// the preference on the diagonal and the tie noise as the median or the
+// preference pass adds it (the off-diagonal noise scale is the range of the
+// off-diagonal entries in median mode, of S with the preferences otherwise).
+// final = 0: the values before both, and the bounds of the off-diagonal keys.
+struct PanelArgs {
+    const float *X;
+    int64_t n, d, ldx;
+    const float *nrm;
+    float *Sp;
+    int64_t ld, p0, p1;
+    int final;
+    PrefArgs pa;              // preference mode and values, select state, bounds, noise
+    const double *range;      // final: range of S with the preferences
+    uint32_t *minmax;         // final = 0: bounds of the off-diagonal keys (atomic)
+    const ApState *st;        // nullable: a frozen run skips the panel
+};
+
+__global__ __launch_bounds__(NT) void k_sim_panel(PanelArgs a) {
+    if (a.st != nullptr && a.st->frozen) return;
+    const int64_t tn = (a.n + BM - 1) / BM;
+    const int64_t bi = blockIdx.x / tn, bj = blockIdx.x % tn;
+    const int64_t row0 = a.p0 + bi * BM, col0 = bj * BM;
+    __shared__ float As[KB * LDA], Bs[KB * LDA];
+    __shared__ float nr[BM], nc[BM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    for (int e = tid; e < BM; e += NT) {
+        nr[e] = row0 + e < a.n ? a.nrm[row0 + e] : 0.0f;
+        nc[e] = col0 + e < a.n ? a.nrm[col0 + e] : 0.0f;
+    }
+    v16f acc[2][2];
+    gram_tile(a.X, a.n, a.d, a.ldx, row0, col0, acc, As, Bs);
+
+    double pm = 0.0, sc_off = 0.0, sc_diag = 0.0;
+    if (a.final) {
+        pm = median_of(a.pa);
+        sc_diag = a.pa.noise_rel * (*a.range);
+        sc_off = a.pa.mode == APX_PREF_MEDIAN
+            ? a.pa.noise_rel * ((double)keyf(a.pa.minmax[1]) - (double)keyf(a.pa.minmax[0]))
+            : sc_diag;
+    }
+    const bool noise = a.pa.noise_rel > 0.0;
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int c = wn * 64 + y * 32 + (lane & 31);
+            const int64_t k = col0 + c;
+            const float ncc = nc[c];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int mb = wm * 64 + x * 32 + 8 * g + 4 * (lane >> 5);
+                const int64_t ib = row0 + mb;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t i = ib + q;
+                    if (k >= a.n || i >= a.p1) continue;
+                    const float v = 2.0f * acc[x][y][4 * g + q] - (nr[mb + q] + ncc);
+                    float out = v;
+                    if (!a.final) {
+                        if (k != i) {
+                            const uint32_t key = fkey(v);
+                            kmin = min(kmin, key);
+                            kmax = max(kmax, key);
+                        }
+                    } else if (k == i) {
+                        const double base = pref_of(a.pa, i, pm);
+                        out = noise ? (float)(base + sc_diag * noise_u(a.pa.seed, a.n, i, i)) : (float)base;
+                    } else if (noise) {
+                        out = add_noise(v, sc_off, a.pa.seed, a.n, i, k);
+                    }
+                    a.Sp[(i - a.p0) * a.ld + k] = out;
+                }
+            }
+        }
+    if (!a.final) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+        }
+        if (lane == 0) {
+            if (kmin < __atomic_load_n(&a.minmax[0], __ATOMIC_RELAXED)) atomicMin(&a.minmax[0], kmin);
+            if (kmax > __atomic_load_n(&a.minmax[1], __ATOMIC_RELAXED)) atomicMax(&a.minmax[1], kmax);
+        }
     }
 }
 
@@ -582,7 +700,7 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
                 const int gn = (int)(n < 8192 ? n : 8192);
                 k_sel_hist_noise<<<gn, 256, lds, s>>>(pa, hist);
             } else {
-                k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist);
+                k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist, 0, n);
             }
             HIP_TRY(hipGetLastError(), "select histogram");
             k_sel_pick<<<1, 256, 0, s>>>(sel, pass, hist);
@@ -612,3 +730,99 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     if (pref_out) *pref_out = pref_mode == APX_PREF_VECTOR ? NAN : *h;
     return APX_OK;
 }
+
+// ---- matrix-free similarity: the row panels of ap_solve_mf -----------------
+namespace apx {
+
+size_t mf_sim_bytes(int64_t n) { return sim_layout(n).bytes; }
+
+namespace {
+struct MfPtrs {
+    float *nrm;
+    uint32_t *mm;
+    SelState *sel;
+    unsigned long long *hist;
+    double *dvals;   // [0] range, [1] preference
+};
+MfPtrs mf_ptrs(const MfSim &m) {
+    const SimLayout L = sim_layout(m.n);
+    MfPtrs q;
+    q.nrm = reinterpret_cast<float *>(m.ws + L.o_n);
+    q.mm = reinterpret_cast<uint32_t *>(m.ws + L.o_mm);
+    q.sel = reinterpret_cast<SelState *>(m.ws + L.o_sel);
+    q.hist = reinterpret_cast<unsigned long long *>(m.ws + L.o_h);
+    q.dvals = reinterpret_cast<double *>(m.ws + L.o_r);
+    return q;
+}
+PanelArgs panel_args(const MfSim &m, const MfPtrs &q, float *panel, int64_t ld, int64_t p0, int64_t p1, int final,
+                     const ApState *st) {
+    PanelArgs a{};
+    a.X = m.X;
+    a.n = m.n;
+    a.d = m.d;
+    a.ldx = m.ldx;
+    a.nrm = q.nrm;
+    a.Sp = panel;
+    a.ld = ld;
+    a.p0 = p0;
+    a.p1 = p1;
+    a.final = final;
+    a.pa = PrefArgs{nullptr, m.n, ld, m.pref_mode, m.pref_vec, m.pref_scalar, q.sel, q.mm, m.seed, m.noise_rel,
+                    &q.dvals[1]};
+    a.range = &q.dvals[0];
+    a.minmax = q.mm;
+    a.st = st;
+    return a;
+}
+hipError_t launch_panel(const PanelArgs &a, hipStream_t s) {
+    const int64_t tiles = ((a.p1 - a.p0 + BM - 1) / BM) * ((a.n + BM - 1) / BM);
+    k_sim_panel<<<(unsigned)tiles, NT, 0, s>>>(a);
+    return hipGetLastError();
+}
+}  // namespace
+
+const double *mf_sim_pref(const MfSim &m) { return &mf_ptrs(m).dvals[1]; }
+const uint32_t *mf_sim_bounds(const MfSim &m) { return mf_ptrs(m).mm; }
+
+// Norms, the bounds of the off-diagonal entries, the median (three digit
+// sweeps of the upper triangle, one panel at a time) and the range of S with
+// the preferences: what ap_similarity derives from the stored S.
+hipError_t mf_sim_setup(const MfSim &m, float *panel, int64_t ld, int64_t prows, hipStream_t s) {
+    const MfPtrs q = mf_ptrs(m);
+    const int64_t n = m.n;
+    const unsigned long long M = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+    const unsigned long long lo = (M % 2) ? (M - 1) / 2 : M / 2 - 1;
+    const unsigned long long hi = (M % 2) ? (M - 1) / 2 : M / 2;
+    k_sel_init<<<1, 256, 0, s>>>(q.sel, q.mm, lo, hi, q.hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sqnorm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m.X, n, m.d, m.ldx, q.nrm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int sweeps = m.pref_mode == APX_PREF_MEDIAN ? 3 : 1;
+    for (int pass = 0; pass < sweeps; ++pass) {
+        for (int64_t p0 = 0; p0 < n; p0 += prows) {
+            const int64_t p1 = p0 + prows < n ? p0 + prows : n;
+            if ((e = launch_panel(panel_args(m, q, panel, ld, p0, p1, 0, nullptr), s)) != hipSuccess) return e;
+            if (m.pref_mode == APX_PREF_MEDIAN) {
+                const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
+                const int g = (int)(p1 - p0 < 2048 ? p1 - p0 : 2048);
+                k_sel_hist<<<g, 256, lds, s>>>(panel - p0 * ld, n, ld, q.sel, pass, q.hist, p0, p1);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        }
+        if (m.pref_mode == APX_PREF_MEDIAN) {
+            k_sel_pick<<<1, 256, 0, s>>>(q.sel, pass, q.hist);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    const PanelArgs a = panel_args(m, q, panel, ld, 0, 0, 1, nullptr);
+    k_pref_range<<<1, 256, 0, s>>>(a.pa, &q.dvals[0]);
+    return hipGetLastError();
+}
+
+hipError_t mf_sim_panel(const MfSim &m, float *panel, int64_t ld, int64_t p0, int64_t p1, const ApState *st,
+                        hipStream_t s) {
+    return launch_panel(panel_args(m, mf_ptrs(m), panel, ld, p0, p1, 1, st), s);
+}
+
+}  // namespace apx
