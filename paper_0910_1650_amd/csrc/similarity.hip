@@ -287,7 +287,22 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
         const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
         const int64_t kh = k4 < n ? k4 : n;
         if (i + 1 + threadIdx.x < kh) count(row[i + 1 + threadIdx.x]);
-        for (int64_t k = k4 + 4 * (int64_t)threadIdx.x; k < n; k += 4 * (int64_t)blockDim.x) {
+        // four 16-byte loads in flight per thread, then their counts
+        const int64_t st = 4 * (int64_t)blockDim.x;
+        int64_t k = k4 + 4 * (int64_t)threadIdx.x;
+        for (; k + 3 * st + 3 < n; k += 4 * st) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k + u * st);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                count(v[u].x);
+                count(v[u].y);
+                count(v[u].z);
+                count(v[u].w);
+            }
+        }
+        for (; k < n; k += st) {
             if (k + 3 < n) {
                 const float4 v = *reinterpret_cast<const float4 *>(row + k);
                 count(v.x);
@@ -483,7 +498,24 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
             }
             return k == i ? v : add_noise(v, scale, a.seed, a.n, i, k);
         };
-        for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.n; k += 4 * (int64_t)blockDim.x) {
+        // two 16-byte loads in flight per thread, then their counts and stores
+        const int64_t st = 4 * (int64_t)blockDim.x;
+        int64_t k0 = 4 * (int64_t)threadIdx.x;
+        for (; k0 + st + 3 < a.n; k0 += 2 * st) {
+            float4 v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k0 + u * st);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t k = k0 + u * st;
+                v[u].x = one(k, v[u].x);
+                v[u].y = one(k + 1, v[u].y);
+                v[u].z = one(k + 2, v[u].z);
+                v[u].w = one(k + 3, v[u].w);
+                *reinterpret_cast<float4 *>(row + k) = v[u];
+            }
+        }
+        for (int64_t k = k0; k < a.n; k += st) {
             if (k + 3 < a.n) {
                 float4 v = *reinterpret_cast<const float4 *>(row + k);
                 v.x = one(k, v.x);
