@@ -253,6 +253,41 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
 
 // Histogram of the keys of upper-triangle entries whose high bits match the
 // current prefix of each rank.  shift/bits select the digit of this pass.
+// f(k, v) for the entries v = row[k], k = i+1 .. n-1, of row i: the unaligned
+// head one by one, then 16-byte loads (rows start 16-byte aligned: ld is a
+// multiple of 4), four in flight per thread.
+template <class F>
+__device__ __forceinline__ void upper_row(const float *row, int64_t i, int64_t n, F &&f) {
+    const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
+    const int64_t kh = k4 < n ? k4 : n;
+    if (i + 1 + threadIdx.x < kh) f(i + 1 + threadIdx.x, row[i + 1 + threadIdx.x]);
+    const int64_t st = 4 * (int64_t)blockDim.x;
+    int64_t k = k4 + 4 * (int64_t)threadIdx.x;
+    for (; k + 3 * st + 3 < n; k += 4 * st) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k + u * st);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            f(k + u * st, v[u].x);
+            f(k + u * st + 1, v[u].y);
+            f(k + u * st + 2, v[u].z);
+            f(k + u * st + 3, v[u].w);
+        }
+    }
+    for (; k < n; k += st) {
+        if (k + 3 < n) {
+            const float4 v = *reinterpret_cast<const float4 *>(row + k);
+            f(k, v.x);
+            f(k + 1, v.y);
+            f(k + 2, v.z);
+            f(k + 3, v.w);
+        } else {
+            for (int64_t q = k; q < n; ++q) f(q, row[q]);
+        }
+    }
+}
+
 // Rows [r0, r1) of S (row i at S + i * ld).
 __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int64_t ld,
                                                   const SelState *st, int pass,
@@ -273,47 +308,14 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
     const bool same = p0 == p1;
     uint32_t *const h0 = hsh;
     uint32_t *const h1 = hsh + (nh - 1) * nb;
-    auto count = [&](float v) {
+    auto count = [&](int64_t, float v) {
         const uint32_t key = fkey(v);
         const uint32_t dig = (key >> shift) & (nb - 1u);
         if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
         if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
     };
     const int64_t re = r1 < n - 1 ? r1 : n - 1;
-    for (int64_t i = r0 + blockIdx.x; i < re; i += gridDim.x) {
-        const float *row = S + i * ld;
-        // columns i+1 .. n-1: the unaligned head one by one, then 16-byte
-        // loads (rows start 16-byte aligned: ld is a multiple of 4)
-        const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
-        const int64_t kh = k4 < n ? k4 : n;
-        if (i + 1 + threadIdx.x < kh) count(row[i + 1 + threadIdx.x]);
-        // four 16-byte loads in flight per thread, then their counts
-        const int64_t st = 4 * (int64_t)blockDim.x;
-        int64_t k = k4 + 4 * (int64_t)threadIdx.x;
-        for (; k + 3 * st + 3 < n; k += 4 * st) {
-            float4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k + u * st);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                count(v[u].x);
-                count(v[u].y);
-                count(v[u].z);
-                count(v[u].w);
-            }
-        }
-        for (; k < n; k += st) {
-            if (k + 3 < n) {
-                const float4 v = *reinterpret_cast<const float4 *>(row + k);
-                count(v.x);
-                count(v.y);
-                count(v.z);
-                count(v.w);
-            } else {
-                for (int64_t q = k; q < n; ++q) count(row[q]);
-            }
-        }
-    }
+    for (int64_t i = r0 + blockIdx.x; i < re; i += gridDim.x) upper_row(S + i * ld, i, n, count);
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
         const uint32_t c0 = h0[b], c1 = same ? c0 : h1[b];
@@ -437,42 +439,36 @@ __global__ void k_pref_range(PrefArgs a, double *range_out) {
     }
 }
 
-// Diagonal := preference; then, if enabled, every entry += scale * u(i,k).
+// Diagonal := preference (+ its noise); with noise, every off-diagonal entry
+// v becomes fl32(v + scale * u(i,k)).  S is symmetric before the noise, so
+// the upper triangle alone is read: an entry the noise changes (add_noise)
+// is written at (i,k) and, with its own draw, at (k,i); the others keep v.
 __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *range) {
     const double pm = median_of(a);
     const double scale = a.noise_rel * (*range);
+    const bool noise = a.noise_rel > 0.0;
     for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
         float *row = a.S + i * a.ld;
-        if (a.noise_rel > 0.0) {
-            auto one = [&](int64_t k, float v) -> float {
-                if (k != i) return add_noise(v, scale, a.seed, a.n, i, k);
-                return (float)(pref_of(a, i, pm) + scale * noise_u(a.seed, a.n, i, k));
-            };
-            // 16-byte loads and stores (rows are 16-byte aligned); the
-            // padding past n is left alone
-            for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.n; k += 4 * (int64_t)blockDim.x) {
-                if (k + 3 < a.n) {
-                    float4 v = *reinterpret_cast<const float4 *>(row + k);
-                    v.x = one(k, v.x);
-                    v.y = one(k + 1, v.y);
-                    v.z = one(k + 2, v.z);
-                    v.w = one(k + 3, v.w);
-                    *reinterpret_cast<float4 *>(row + k) = v;
-                } else {
-                    for (int64_t q = k; q < a.n; ++q) row[q] = one(q, row[q]);
-                }
-            }
-        } else if (threadIdx.x == 0) {
-            row[i] = (float)pref_of(a, i, pm);
+        if (threadIdx.x == 0) {
+            const double base = pref_of(a, i, pm);
+            row[i] = noise ? (float)(base + scale * noise_u(a.seed, a.n, i, i)) : (float)base;
         }
+        if (!noise) continue;
+        upper_row(row, i, a.n, [&](int64_t k, float v) {
+            if (scale <= fabs((double)v) * 0x1p-27) return;
+            row[k] = add_noise(v, scale, a.seed, a.n, i, k);
+            a.S[k * a.ld + i] = add_noise(v, scale, a.seed, a.n, k, i);
+        });
     }
 }
 
-// Median mode, last select pass fused with the tie noise: every row is read
-// once; upper-triangle entries are counted for the last digit (their values
-// before noise), every off-diagonal entry gets its noise, and the diagonal
-// is left for k_pref_diag once the median is known.  The noise scale needs
-// only the off-diagonal range (the median lies inside it).
+// Median mode, last select pass fused with the tie noise: the upper triangle
+// is read once and counted for the last digit (values before noise); an
+// entry the noise changes is written at (i,k) and, with its own draw, at
+// (k,i) (S is symmetric before the noise; no pass reads the lower triangle
+// or an entry after its row's block has read it).  The diagonal is left for
+// k_pref_diag once the median is known.  The noise scale needs only the
+// off-diagonal range (the median lies inside it).
 __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned long long *hist) {
     extern __shared__ uint32_t hsh[];
     constexpr int pass = 2;
@@ -487,46 +483,17 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
     uint32_t *const h0 = hsh;
     uint32_t *const h1 = hsh + nb;
     const double scale = a.noise_rel * ((double)keyf(a.minmax[1]) - (double)keyf(a.minmax[0]));
-    for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < a.n - 1; i += gridDim.x) {
         float *row = a.S + i * a.ld;
-        auto one = [&](int64_t k, float v) -> float {
-            if (k > i) {
-                const uint32_t key = fkey(v);
-                const uint32_t dig = (key >> shift) & (nb - 1u);
-                if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
-                if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
-            }
-            return k == i ? v : add_noise(v, scale, a.seed, a.n, i, k);
-        };
-        // two 16-byte loads in flight per thread, then their counts and stores
-        const int64_t st = 4 * (int64_t)blockDim.x;
-        int64_t k0 = 4 * (int64_t)threadIdx.x;
-        for (; k0 + st + 3 < a.n; k0 += 2 * st) {
-            float4 v[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k0 + u * st);
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int64_t k = k0 + u * st;
-                v[u].x = one(k, v[u].x);
-                v[u].y = one(k + 1, v[u].y);
-                v[u].z = one(k + 2, v[u].z);
-                v[u].w = one(k + 3, v[u].w);
-                *reinterpret_cast<float4 *>(row + k) = v[u];
-            }
-        }
-        for (int64_t k = k0; k < a.n; k += st) {
-            if (k + 3 < a.n) {
-                float4 v = *reinterpret_cast<const float4 *>(row + k);
-                v.x = one(k, v.x);
-                v.y = one(k + 1, v.y);
-                v.z = one(k + 2, v.z);
-                v.w = one(k + 3, v.w);
-                *reinterpret_cast<float4 *>(row + k) = v;
-            } else {
-                for (int64_t q = k; q < a.n; ++q) row[q] = one(q, row[q]);
-            }
-        }
+        upper_row(row, i, a.n, [&](int64_t k, float v) {
+            const uint32_t key = fkey(v);
+            const uint32_t dig = (key >> shift) & (nb - 1u);
+            if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
+            if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
+            if (scale <= fabs((double)v) * 0x1p-27) return;
+            row[k] = add_noise(v, scale, a.seed, a.n, i, k);
+            a.S[k * a.ld + i] = add_noise(v, scale, a.seed, a.n, k, i);
+        });
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -729,8 +696,7 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
         for (int pass = 0; pass < 3; ++pass) {
             const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
             if (pass == 2 && noise_rel > 0.0) {
-                const int gn = (int)(n < 8192 ? n : 8192);
-                k_sel_hist_noise<<<gn, 256, lds, s>>>(pa, hist);
+                k_sel_hist_noise<<<g, 256, lds, s>>>(pa, hist);
             } else {
                 k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist, 0, n);
             }
