@@ -93,8 +93,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1934845474, "write": 46024233, "path": "implicit_RA",
-                    "sha256": "6479904bde82f2b2d9687d7ee88041909562e1864342ae937c83c3f5dec4bc7a"}
+ROW_PASS_TRAFFIC = {"read": 1934007216, "write": 46024754, "path": "implicit_RA",
+                    "sha256": "cfcd417f680f9abc8fd831daf8098096d37f208aaa88356969186ae371d55f55"}
 PAP_K = 8
 
 
