@@ -7,7 +7,8 @@ the implicit message passes on those rows.  Checks:
 
 * one panel (the stored path's grouping of the column sums): the same
   labels, stop iteration and net similarity as ap_similarity + ap_solve;
-* several panels with a ragged last one: the same exemplar set, labels and
+* several panels with a ragged last one (n = 3000 and 6000 with partials
+  in LDS, n = 33000 with global partials): the same exemplar set, labels and
   stop iteration (the column sums group their rows per panel: rounding
   only), net similarity equal (it sums the same S entries in one order);
 * the C2 configuration (N = 20000, 64-D mixture, damping 0.9): the oracle's
@@ -53,7 +54,8 @@ def _stored(X, seed, lam, max_iter, conv_iter, pref="median"):
     return idx.cpu().numpy(), res, p
 
 
-@pytest.mark.parametrize("n,pref,rows_few", [(6000, "median", 1000), (6000, -300.0, 1000), (3000, "median", 700)])
+@pytest.mark.parametrize("n,pref,rows_few", [(6000, "median", 1000), (6000, -300.0, 1000), (3000, "median", 700),
+                                              (33000, "median", 4000)])
 def test_matrix_free_matches_stored_path(n, pref, rows_few):
     seed = 6201
     print(f"matrix-free n={n} pref={pref}", flush=True)
