@@ -102,8 +102,10 @@ enum {
     APX_OP_FEATURES = 6,      /* apx_features: n points                                */
     APX_OP_MLP_BACKWARD = 7,  /* apx_mlp_backward: count points                        */
     APX_OP_WARMSTART = 8,     /* ap_warmstart: n x n, ld                               */
-    APX_OP_LAP_FULL = 9       /* lap_full_solve: n points in d dimensions, count
+    APX_OP_LAP_FULL = 9,      /* lap_full_solve: n points in d dimensions, count
                                  landmarks, m0 = ld                                    */
+    APX_OP_SOLVE_MF = 10      /* ap_solve_mf: n points, count = panel_rows (0: the
+                                 default panel)                                        */
 };
 
 /*

@@ -25,7 +25,7 @@ APX_COLD, APX_WARM_A, APX_WARM_AR, APX_WARM_COLUMNS = range(4)
 APX_MLP_FEATURES, APX_MLP_PARAMS = 16, 18946
 APX_RAW_LABELS, APX_CHECK_FINITE, APX_MSG_THRESHOLD = 1, 2, 4
 (APX_OP_SIMILARITY, APX_OP_ITERATE, APX_OP_SOLVE, APX_OP_SOLVE_BATCHED, APX_OP_PAP, APX_OP_LAP,
- APX_OP_FEATURES, APX_OP_MLP_BACKWARD, APX_OP_WARMSTART, APX_OP_LAP_FULL) = range(10)
+ APX_OP_FEATURES, APX_OP_MLP_BACKWARD, APX_OP_WARMSTART, APX_OP_LAP_FULL, APX_OP_SOLVE_MF) = range(11)
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTIMPL"}
 
 

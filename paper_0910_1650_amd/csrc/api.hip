@@ -493,6 +493,16 @@ apx_status apx_set_workspace(apx_ctx *ctx, void *dev_ptr, size_t bytes) {
     return APX_OK;
 }
 
+namespace {
+struct MfShape {
+    int64_t ld, P, Q;
+    int gmax;
+    PassPlan ipl, apl;
+};
+bool mf_shape(int64_t n, int64_t panel_rows, int num_cus, MfShape *sh);
+size_t mf_bytes(int64_t n, const MfShape &sh);
+}  // namespace
+
 size_t apx_workspace_size(const apx_ctx *ctx, int32_t op, int64_t n, int64_t ld, int64_t d, int32_t count,
                           const int64_t *sizes) {
     if (!ctx) return 0;
@@ -526,6 +536,10 @@ size_t apx_workspace_size(const apx_ctx *ctx, int32_t op, int64_t n, int64_t ld,
     case APX_OP_LAP_FULL:
         return (n >= 2 && d >= 1 && count >= 2 && count <= n && ld >= 2) ? lap_full_ws_bytes(n, d, count, ld, cus)
                                                                           : 0;
+    case APX_OP_SOLVE_MF: {
+        MfShape sh;
+        return (count >= 0 && mf_shape(n, count, cus, &sh)) ? mf_bytes(n, sh) : 0;
+    }
     default:
         return 0;
     }
@@ -948,6 +962,20 @@ int64_t mf_default_rows(int64_t n, int64_t ld, int grid) {
     if (p < 8 * (int64_t)grid) p = 8 * (int64_t)grid;
     return p < n ? p : n;
 }
+// Plans and panels of a matrix-free solve; false when n is outside the
+// implicit passes or the panel holds less than one row per workgroup.
+bool mf_shape(int64_t n, int64_t panel_rows, int num_cus, MfShape *sh) {
+    if (n < 2 || n > 65536 || !imp_plan(n, num_cus, &sh->ipl) || !ia_plan(n, num_cus, &sh->apl)) return false;
+    sh->ld = (n + 63) & ~int64_t(63);
+    sh->gmax = sh->ipl.grid > sh->apl.grid ? sh->ipl.grid : sh->apl.grid;
+    int64_t P = panel_rows > 0 ? panel_rows : mf_default_rows(n, sh->ld, sh->gmax);
+    if (P > n) P = n;
+    if (P < sh->gmax) return false;
+    sh->P = P;
+    sh->Q = (n + P - 1) / P;
+    return true;
+}
+size_t mf_bytes(int64_t n, const MfShape &sh) { return mf_layout(n, sh.ld, sh.P, sh.Q * sh.gmax).bytes; }
 }  // namespace
 
 extern "C" apx_status ap_solve_mf(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int64_t ldx,
@@ -965,17 +993,15 @@ extern "C" apx_status ap_solve_mf(apx_ctx *ctx, const float *X, int64_t n, int64
     APX_TRY(check_params(ctx, params));
     if (params->flags & (APX_RAW_LABELS | APX_MSG_THRESHOLD))
         return set_err(ctx, APX_ENOTIMPL, "raw labels and the message-change rule need R and A in memory");
-    PassPlan ipl{}, apl{};
-    if (n < 2 || n > 65536 || !imp_plan(n, ctx->num_cus, &ipl) || !ia_plan(n, ctx->num_cus, &apl) ||
-        ctx->implicit_k <= 0 || ctx->implicit_a <= 0)
-        return set_err(ctx, APX_ENOTIMPL, "n = %lld outside the implicit passes (or they are disabled)", (long long)n);
-    const int64_t ld = (n + 63) & ~int64_t(63);
     if (panel_rows < 0) return set_err(ctx, APX_EINVAL, "panel_rows < 0");
-    const int gmax = ipl.grid > apl.grid ? ipl.grid : apl.grid;
-    int64_t P = panel_rows > 0 ? panel_rows : mf_default_rows(n, ld, gmax);
-    if (P > n) P = n;
-    if (P < gmax) return set_err(ctx, APX_EINVAL, "panel_rows must be >= %d (one row per workgroup)", gmax);
-    const int64_t Q = (n + P - 1) / P;
+    MfShape sh;
+    if (!mf_shape(n, 0, ctx->num_cus, &sh) || ctx->implicit_k <= 0 || ctx->implicit_a <= 0)
+        return set_err(ctx, APX_ENOTIMPL, "n = %lld outside the implicit passes (or they are disabled)", (long long)n);
+    if (!mf_shape(n, panel_rows, ctx->num_cus, &sh))
+        return set_err(ctx, APX_EINVAL, "panel_rows must be >= %d (one row per workgroup)", sh.gmax);
+    const PassPlan ipl = sh.ipl, apl = sh.apl;
+    const int64_t ld = sh.ld, P = sh.P, Q = sh.Q;
+    const int gmax = sh.gmax;
     const float lam = params->damping;
     DevGuard g(ctx->device);
     hipStream_t s = ctx->stream;

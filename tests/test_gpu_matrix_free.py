@@ -108,3 +108,25 @@ def test_matrix_free_errors():
     Xs = torch.zeros((70000, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(RuntimeError, match="implicit passes"):
         apx.ap_solve_mf(Xs)
+
+
+def test_matrix_free_caller_workspace():
+    """apx_workspace_size(APX_OP_SOLVE_MF) covers the call: with a caller
+    workspace of exactly that size it allocates nothing and gives the same
+    result; one page less is APX_ENOMEM."""
+    n, seed, rows = 6000, 6203, 1000
+    X = torch.from_numpy(synth.gaussian_mixture(n=n, d=16, k=20, seed=seed).X).cuda()
+    idx0, res0, _ = apx.ap_solve_mf(X, noise_seed=seed, damping=0.9, max_iter=1000, panel_rows=rows)
+    need = apx.apx_workspace_size(apx.APX_OP_SOLVE_MF, n, count=rows)
+    assert need > 0 and apx.apx_workspace_size(apx.APX_OP_SOLVE_MF, n, count=16) == 0
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    try:
+        apx.apx_set_workspace(buf)
+        idx1, res1, _ = apx.ap_solve_mf(X, noise_seed=seed, damping=0.9, max_iter=1000, panel_rows=rows)
+        assert torch.equal(idx0, idx1) and res1.iterations == res0.iterations and res1.netsim == res0.netsim
+        apx.apx_set_workspace(buf[: need - 4096])
+        with pytest.raises(apx.ApxError) as ei:
+            apx.ap_solve_mf(X, noise_seed=seed, damping=0.9, max_iter=1000, panel_rows=rows)
+        assert ei.value.status == apx.APX_ENOMEM
+    finally:
+        apx.apx_set_workspace(None)
