@@ -403,8 +403,8 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
  * count and sums are those of ap_similarity + ap_solve up to the rounding of
  * the column sums' grouping (each panel sums its own rows).  pref_out (host,
  * nullable) gets the scalar preference.  APX_ENOTIMPL when n is outside the
- * implicit passes (2 .. 40960: a row of at most ten 4-float chunks per
- * thread), when a row's message list overflows (the explicit form would
+ * implicit passes (2 .. 40448: a row of at most ten 4-float chunks per
+ * thread, the implicit-R prologue's partials in LDS), when a row's message list overflows (the explicit form would
  * need R and A), and for APX_RAW_LABELS or APX_MSG_THRESHOLD; APX_EINVAL for non-finite X or
  * pref_vec, a bad preference mode, or panel_rows below one row per
  * workgroup.  Synchronises the stream.
