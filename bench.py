@@ -93,8 +93,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1934007216, "write": 46024754, "path": "implicit_RA",
-                    "sha256": "cfcd417f680f9abc8fd831daf8098096d37f208aaa88356969186ae371d55f55"}
+ROW_PASS_TRAFFIC = {"read": 1933882667, "write": 46025256, "path": "implicit_RA",
+                    "sha256": "fd71b93f361df3d9f7b3f99663a699a878c196f1f06e85c0805f05045ed0ab1c"}
 PAP_K = 8
 
 
@@ -173,7 +173,9 @@ def workload_extras(apx) -> dict:
       landmarks: the landmark similarity and AP, then the assignment of every
       point; the whole lap_solve and the assignment's FP32 rate.
     * matrix_free_c2: ap_solve_mf on the benchmark's points (S rebuilt per
-      iteration, no n x n buffer), against the oracle's exemplar set."""
+      iteration, no n x n buffer), against the oracle's exemplar set.
+    * long_rows_n100000: ten explicit iterations (ap_iterate) at n = 100000,
+      where every row is streamed twice per pass, with their HBM rate."""
     import numpy as np
     import torch
 
@@ -333,6 +335,28 @@ def workload_extras(apx) -> dict:
     del X
     torch.cuda.empty_cache()
     print("extras: matrix-free done", file=sys.stderr, flush=True)
+
+    # explicit passes on rows too long to hold in registers: two sweeps per row
+    n, seed, iters = 100000, 3201, 10
+    pts = synth.gaussian_mixture(n=n, d=8, k=30, seed=seed)
+    X = torch.from_numpy(pts.X).cuda()
+    S, _ = apx.ap_similarity(X, pref="median", noise_seed=seed, noise_rel=1e-12)
+    del X
+    R, A = apx.empty_matrix(n, fill=0.0), apx.empty_matrix(n, fill=0.0)
+    apx.ap_iterate(S, R, A, LAMBDA, 2)
+    _, ms = _timed(lambda: apx.ap_iterate(S, R, A, LAMBDA, iters))
+    gbs = 20.0 * n * n * iters / (ms * 1e-3) / 1e9
+    out["long_rows_n100000"] = {
+        "workload": f"ap_iterate on {n} points (8-D, 30-component mixture), damping {LAMBDA}: "
+                    f"{iters} iterations of the explicit passes, each row streamed twice",
+        "ms_per_iteration": round(ms / iters, 3),
+        "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "bytes_basis": "20 B per element and iteration (S, R_t, A_{t-1} read, R_{t+1}, A_t written); "
+                       "the pass moves 28 B (S and R_t read twice)",
+    }
+    del S, R, A
+    torch.cuda.empty_cache()
+    print("extras: long rows done", file=sys.stderr, flush=True)
     return out
 
 

@@ -352,8 +352,9 @@ apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int64_t d, int
  * iteration first updates and damps R from (S, A), then A from the new R.
  * decision (device, nullable) receives argmax_k a(i,k)+r(i,k) after the last
  * iteration (lowest k on ties).  Calls compose: n1 then n2 iterations give
- * bit-identical messages to n1 + n2 in one call.  Requires n >= 2,
- * n_iter >= 1.  Asynchronous.
+ * bit-identical messages to n1 + n2 in one call.  Requires 2 <= n <= 131072
+ * (APX_ENOTIMPL above) and n_iter >= 1; rows beyond 49152 elements are
+ * streamed twice per pass instead of held in registers.  Asynchronous.
  */
 apx_status ap_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
                       float damping, int32_t n_iter, int32_t *decision);
@@ -381,8 +382,10 @@ apx_status ap_iterate_noalloc(apx_ctx *ctx, const float *S, int64_t n, int64_t l
  * a(k,j)+r(k,j) = k} label themselves and every other point takes the
  * exemplar of largest s(i,k) (lowest k on ties).  res (host) gets the
  * iteration count, convergence flag, |E| and dpsim/expref/netsim in FP64.
- * n = 1 returns idx = [0] and netsim = s(0,0) without iterating.
- * Non-convergence is not an error (converged = 0).  Synchronises the stream.
+ * n = 1 returns idx = [0] and netsim = s(0,0) without iterating; n above
+ * 131072 gives APX_ENOTIMPL (the caller's S, R, A and one more n x n buffer
+ * of the library must fit in device memory).  Non-convergence is not an
+ * error (converged = 0).  Synchronises the stream.
  */
 apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *R, float *A,
                     int32_t warm, const apx_params *params, int32_t *idx, apx_result *res);

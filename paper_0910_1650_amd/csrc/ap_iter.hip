@@ -557,6 +557,149 @@ __global__ __launch_bounds__(T) void k_row_pass_reg(PassArgs p) {
     }
 }
 
+// Row pass for rows of any length: two sweeps over the row instead of
+// holding it in registers.  Sweep 1 reads S, R_t, A_{t-1} chunk by chunk and
+// forms A_t (written), the decision and the top-2 of A_t + S; after the
+// workgroup reduction, sweep 2 reads S and R_t again and forms R_{t+1}
+// (written) and the column partials, which accumulate in the workgroup's
+// partial row in memory in row order (each thread owns its columns).  The
+// per-chunk arithmetic is the register variant's, in the same order, so the
+// results are bit-identical to it; 28 B per element and iteration instead
+// of 20 (S and R_t are read twice), plus the partial row's update.  The
+// first sweep's S and R_t loads are cached (the second sweep reads them
+// again); everything else is streamed with the nontemporal hint.
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_row_pass_2s(PassArgs p) {
+#pragma clang fp contract(off)
+    constexpr int T = 1024;
+    constexpr bool DELTA = (MODE == PASS_FULL_DELTA);
+    constexpr bool DO_A = (MODE == PASS_FULL || MODE == PASS_A_ONLY || DELTA);
+    constexpr bool DO_R = (MODE != PASS_A_ONLY);
+    constexpr bool LD_S = DO_R;
+    constexpr bool LD_RA = (MODE != PASS_R_COLD);
+    constexpr int NW = T / 64;
+
+    if (p.st != nullptr && p.st->frozen) return;
+    __shared__ float sh_f[2][NW][3];
+    __shared__ int sh_i[2][NW][2];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n = p.n;
+    const int64_t ld = p.ld;
+    const float lam = p.lam;
+    const float oml = 1.0f - lam;
+    const int64_t nrows = p.row_end - p.row_begin;
+    const int64_t r0 = p.row_begin + (int64_t)blockIdx.x * nrows / gridDim.x;
+    const int64_t r1 = p.row_begin + (int64_t)(blockIdx.x + 1) * nrows / gridDim.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int c0 = tid * 4;
+    // chunks of this thread that hold columns (j < Jn: c0 + 4 T j < n)
+    const int Jn = c0 < n ? (n - c0 + 4 * T - 1) / (4 * T) : 0;
+
+    float *P = p.partial + (int64_t)blockIdx.x * p.ldp;
+    if constexpr (DO_R) {
+        for (int j = 0; j < Jn; ++j) st4(P + c0 + j * T * 4, z4);
+    }
+    int my_nex = 0, my_changed = 0;
+    float mda = 0.0f, mdr = 0.0f;
+
+    for (int64_t i = r0; i < r1; ++i) {
+        const int ii = (int)i;
+        const ColOwner dg = owner_of<T>(ii, tid);
+        float *Arow = p.A + i * ld;
+        const float *Rrow = p.Rin + i * ld;
+        const float *Srow = p.S + i * ld;
+        float ci = 0.0f;
+        if constexpr (DO_A) ci = p.ccol[ii];
+        float v1 = kNegInf, v2 = kNegInf, dv = kNegInf;
+        int l1 = -1, dl = -1;
+#pragma unroll 4
+        for (int j = 0; j < Jn; ++j) {
+            const int c = c0 + j * T * 4;
+            const bool full = c + 3 < n;
+            float4 a = z4, r = z4, sv = z4;
+            if constexpr (LD_RA) {
+                a = bld4(Arow, 0, c * 4);
+                r = ld4(Rrow + c);
+            }
+            if constexpr (LD_S) sv = ld4(Srow + c);
+            if constexpr (DO_A) {
+                const float4 aold = a;
+                chunk_avail(a, r, ld4(p.tcol + c), ci, j, dg, c, n, full, lam, oml, dv, dl);
+                if (full) bst4(Arow, 0, c * 4, a);
+                else
+                    for (int e = 0; e < 4; ++e)
+                        if (c + e < n) Arow[c + e] = f4get(a, e);
+                if constexpr (DELTA) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (full || c + e < n) mda = fmaxf(mda, fabsf(f4get(a, e) - f4get(aold, e)));
+                }
+            }
+            if constexpr (DO_R) (void)chunk_top2(a, r, sv, j, c, n, full, lam, oml, v1, l1, v2);
+        }
+        Top2 t2{v1, l1 < 0 ? INT32_MAX : local_to_col<T>(l1, tid), v2};
+        ArgMax dm{dv, dl < 0 ? INT32_MAX : local_to_col<T>(dl, tid)};
+        const int slot = (int)(i & 1);
+        wg_reduce<NW, DO_A, DO_R>(t2, dm, sh_f[slot], sh_i[slot], lane, wave);
+        if constexpr (DO_A) {
+            if (tid == 0) note_decision(p, ii, dm.k, my_nex, my_changed);
+        }
+        if constexpr (DO_R) {
+            const float m_other = oml * t2.v1;
+            const float m_self = oml * t2.v2;
+            const ColOwner ko = owner_of<T>(t2.k1, tid);
+            float *Rout = p.Rout + i * ld;
+#pragma unroll 4
+            for (int j = 0; j < Jn; ++j) {
+                const int c = c0 + j * T * 4;
+                const bool full = c + 3 < n;
+                float4 r = z4;
+                if constexpr (LD_RA) r = bld4(Rrow, 0, c * 4);
+                const float4 sv = bld4(Srow, 0, c * 4);
+                // u = lambda r + (1 - lambda) s, as the first sweep's top-2 step forms it
+                float4 u = z4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (full || c + e < n) f4set(u, e, lam * f4get(r, e) + oml * f4get(sv, e));
+                float4 rn;
+                const float4 pos = chunk_resp(u, j, ko, dg, m_self, m_other, c, n, full, rn, p.rdiag + ii);
+                if (full) bst4(Rout, 0, c * 4, rn);
+                else
+                    for (int e = 0; e < 4; ++e)
+                        if (c + e < n) Rout[c + e] = f4get(rn, e);
+                float4 acc = ld4(P + c);
+                add4(acc, pos);
+                st4(P + c, acc);
+                if constexpr (DELTA) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (full || c + e < n) mdr = fmaxf(mdr, fabsf(f4get(rn, e) - f4get(r, e)));
+                }
+            }
+        }
+    }
+    if constexpr (DO_A) {
+        if (tid == 0 && p.st != nullptr) {
+            if (my_nex) atomicAdd(&p.st->nex, my_nex);
+            if (my_changed) atomicOr(&p.st->changed, 1);
+        }
+    }
+    if constexpr (DELTA) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mda = fmaxf(mda, __shfl_xor(mda, off, 64));
+            mdr = fmaxf(mdr, __shfl_xor(mdr, off, 64));
+        }
+        if (lane == 0 && p.st != nullptr) {
+            atomicMax(&p.st->d_a, __float_as_uint(mda));
+            atomicMax(&p.st->d_r_next, __float_as_uint(mdr));
+        }
+    }
+}
+
 // alpha_t = 1 - lambda^t of the implicit responsibilities, from one function
 // of t so every pass and the materialisation use the same rounding.
 __device__ __forceinline__ float imp_alpha(float lam, int t) {
@@ -850,6 +993,17 @@ hipError_t launch_lds(const PassArgs &a, int grid, size_t lds, hipStream_t s) {
         attr_set = true;
     }
     k_row_pass<T, J, MODE><<<grid, T, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_2s(int mode, const PassArgs &a, int grid, hipStream_t s) {
+    switch (mode) {
+    case PASS_FULL_DELTA: k_row_pass_2s<PASS_FULL_DELTA><<<grid, 1024, 0, s>>>(a); break;
+    case PASS_FULL: k_row_pass_2s<PASS_FULL><<<grid, 1024, 0, s>>>(a); break;
+    case PASS_R_ONLY: k_row_pass_2s<PASS_R_ONLY><<<grid, 1024, 0, s>>>(a); break;
+    case PASS_R_COLD: k_row_pass_2s<PASS_R_COLD><<<grid, 1024, 0, s>>>(a); break;
+    default: k_row_pass_2s<PASS_A_ONLY><<<grid, 1024, 0, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 
@@ -2394,15 +2548,35 @@ PassPlan plan_pass_variant(int64_t n, int num_cus, int threads, bool lds) {
     return pl;
 }
 
+// Above 12 chunks per thread (n > 49152) the register-resident pass holds
+// u and the partials of up to 16 chunks with low occupancy and falls below
+// the two-sweep pass, which reads S and R_t twice: at 13-16 chunks the
+// register pass moves 3.4-3.8 TB/s of its 20 B per element, the two-sweep
+// pass 4.0 TB/s; at 12 chunks and below the register pass is faster.
+constexpr int kRegPassMaxChunks = 12;
+
 PassPlan plan_pass(int64_t n, int num_cus) {
     PassPlan pl = plan_pass_variant(n, num_cus, n <= 4096 ? 256 : 1024, true);
-    // APX_ROW_PASS=reg selects the register variant (cross-checks).
+    // APX_ROW_PASS=reg selects the register variant, APX_ROW_PASS=2s the
+    // two-sweep pass (cross-checks; 1024-thread plans only).
     const char *v = getenv("APX_ROW_PASS");
     if (v && v[0] == 'r') pl.lds_bytes = 0;
+    const bool force_2s = v && v[0] == '2' && n > 4096;
+    if (n > 4096 && (pl.threads == 0 || pl.chunks > kRegPassMaxChunks || force_2s)) {
+        // rows longer than the register-resident variants hold well (or
+        // forced): the same row -> workgroup map, two sweeps per row
+        const int64_t q = (n + 3) / 4;
+        pl.grid = (int)(n < num_cus ? n : num_cus);
+        pl.threads = 1024;
+        pl.chunks = (int)((q + 1023) / 1024);
+        pl.lds_bytes = 0;
+        pl.two_sweep = 1;
+    }
     return pl;
 }
 
 hipError_t launch_row_pass(const PassPlan &pl, int mode, const PassArgs &a, hipStream_t s) {
+    if (pl.two_sweep) return pl.threads == 1024 ? launch_2s(mode, a, pl.grid, s) : hipErrorInvalidValue;
     if (pl.threads == 256) {
         switch (pl.chunks) {
         case 1: return launch_t<256, 1>(mode, a, pl, s);

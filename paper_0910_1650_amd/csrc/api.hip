@@ -303,7 +303,8 @@ apx_status graph_chunk(apx_ctx *ctx, const PassPlan &pl, int mode, const float *
                               (uint64_t)(uintptr_t)w.tcol, (uint64_t)(uintptr_t)w.imp,
                               (uint64_t)pl.grid | ((uint64_t)mode << 32) | ((uint64_t)ctx->implicit_k << 40) |
                                   ((uint64_t)ctx->implicit_a << 48),
-                              (uint64_t)pl.threads | ((uint64_t)ctx->lean << 32), (uint64_t)pl.lds_bytes};
+                              (uint64_t)pl.threads | ((uint64_t)ctx->lean << 32) | ((uint64_t)pl.two_sweep << 33),
+                              (uint64_t)pl.lds_bytes};
     if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof key) != 0) {
         if (ctx->gexec) {
             (void)hipGraphExecDestroy(ctx->gexec);
@@ -356,7 +357,7 @@ apx_status check_iterate(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, co
                          float damping, int32_t n_iter) {
     if (!ctx) return APX_EINVAL;
     if (n < 2) return set_err(ctx, APX_EINVAL, "ap_iterate needs n >= 2 (n = %lld)", (long long)n);
-    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
+    if (n > kMaxSolveN) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds %lld", (long long)n, (long long)kMaxSolveN);
     APX_TRY(check_matrix(ctx, S, "S", n, ld));
     APX_TRY(check_matrix(ctx, R, "R", n, ld));
     APX_TRY(check_matrix(ctx, A, "A", n, ld));
@@ -641,7 +642,7 @@ apx_status ap_solve(apx_ctx *ctx, const float *S, int64_t n, int64_t ld, float *
                     int32_t warm, const apx_params *params, int32_t *idx, apx_result *res) {
     if (!ctx) return APX_EINVAL;
     if (n < 1) return set_err(ctx, APX_EINVAL, "n must be >= 1");
-    if (n > 65536) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds 65536", (long long)n);
+    if (n > kMaxSolveN) return set_err(ctx, APX_ENOTIMPL, "n = %lld exceeds %lld", (long long)n, (long long)kMaxSolveN);
     APX_TRY(check_matrix(ctx, S, "S", n, ld));
     APX_TRY(check_matrix(ctx, R, "R", n, ld));
     APX_TRY(check_matrix(ctx, A, "A", n, ld));

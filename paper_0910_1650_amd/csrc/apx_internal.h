@@ -91,12 +91,17 @@ struct ColArgs {
     float lam;
 };
 
+// Largest n of ap_iterate and ap_solve: four n x n FP32 matrices (S, A and
+// the two R buffers) fill the 288 GB of one MI355X at about this size.
+constexpr int64_t kMaxSolveN = 131072;
+
 // Launch helpers (ap_iter.hip).
 struct PassPlan {
     int threads;   // workgroup size
     int chunks;    // float4 chunks per thread per row
     int grid;      // workgroups
     size_t lds_bytes;  // dynamic LDS of the LDS-resident variant (0: register variant)
+    int two_sweep;     // 1: rows streamed twice (rows beyond the register-resident variants)
 };
 PassPlan plan_pass(int64_t n, int num_cus);
 // The same row -> workgroup map with a chosen workgroup size and variant;
