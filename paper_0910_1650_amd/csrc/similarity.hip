@@ -18,7 +18,12 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 128;      // tile edge
-constexpr int KB = 32;       // K chunk staged in LDS
+// K chunk staged in LDS.  16 rather than 32 halves the registers that
+// carry the next chunk's loads, so three workgroups fit a CU instead of two
+// (168 registers instead of 192): the writes of S of one workgroup overlap
+// the MFMAs of two others.  The MFMA sequence (two K values per step, in
+// ascending order) is the same for any chunk size, so S is unchanged.
+constexpr int KB = 16;
 constexpr int NT = 256;      // threads per tile (4 wavefronts)
 
 // Ordered 32-bit key of a float: unsigned order equals float order.
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
     const int64_t bj = bi + t;
     const int64_t row0 = bi * BM, col0 = bj * BM;
 
-    __shared__ float As[KB * LDA], Bs[KB * LDA];    // 33 KB of staging
+    __shared__ float As[KB * LDA], Bs[KB * LDA];    // 16.5 KB of staging
     __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
