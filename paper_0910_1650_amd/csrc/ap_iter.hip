@@ -1818,6 +1818,21 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
     };
     int cur_c[EPT], nxt_c[EPT];
     float cur_v[EPT], nxt_v[EPT];
+    // exception-list entries' s(i,k) and t_k, gathered right after the row's
+    // S loads are issued (a row ahead), so that their latency overlaps the
+    // previous row's reduction instead of following the scan
+    float xsv[EPT], xtv[EPT], nxs[EPT], nxt[EPT];
+    auto gather_x = [&](int64_t i, const int *xc, float *sv, float *tv) {
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            sv[u] = 0.0f;
+            tv[u] = 0.0f;
+            if ((unsigned)xc[u] < (unsigned)n) {
+                sv[u] = p.S[i * ld + xc[u]];
+                tv[u] = p.tcol[xc[u]];
+            }
+        }
+    };
     if (r0 < r1) {
         const int rc = sw && lane < IMP_K ? cnt_in[r0] : 0;
         const float rgam = sw && lane < IMP_K ? gam_in[r0 * IMP_K + lane] : 0.0f;
@@ -1825,6 +1840,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         fetch_x(r0, cur_c, cur_v);
         mark_x(r0, cur_c);
         load_row(r0, s4);
+        gather_x(r0, cur_c, xsv, xtv);
     }
     // a column value above zero (a warm start) voids the D > 0 argument
     float amx = kNegInf;
@@ -1900,17 +1916,6 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 if constexpr (WB) rav = rav + lt * a0_at(rk);
             } else {
                 rk = -1;
-            }
-        }
-        // exception-list entries: s(i,k) and t_k
-        float xsv[EPT], xtv[EPT];
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            xsv[u] = 0.0f;
-            xtv[u] = 0.0f;
-            if ((unsigned)cur_c[u] < (unsigned)n) {
-                xsv[u] = p.S[i * ld + cur_c[u]];
-                xtv[u] = p.tcol[cur_c[u]];
             }
         }
 
@@ -2103,6 +2108,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             put_state(i + 1, nstate, ncnt, ngam);
             mark_x(i + 1, nxt_c);
             load_row(i + 1, s4);
+            gather_x(i + 1, nxt_c, nxs, nxt);
         }
         __builtin_amdgcn_sched_barrier(0);
 
@@ -2340,6 +2346,8 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         for (int u = 0; u < EPT; ++u) {
             cur_c[u] = nxt_c[u];
             cur_v[u] = nxt_v[u];
+            xsv[u] = nxs[u];
+            xtv[u] = nxt[u];
         }
     }
 

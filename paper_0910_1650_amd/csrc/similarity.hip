@@ -25,6 +25,7 @@ constexpr int BM = 128;      // tile edge
 // ascending order) is the same for any chunk size, so S is unchanged.
 constexpr int KB = 16;
 constexpr int NT = 256;      // threads per tile (4 wavefronts)
+constexpr int SEL_BINS = 8192;   // bins per rank in the global select histogram (13-bit first digit)
 
 // Ordered 32-bit key of a float: unsigned order equals float order.
 __device__ __forceinline__ uint32_t fkey(float f) {
@@ -53,16 +54,23 @@ struct SimArgs {
     int64_t ld;
     int64_t tiles_per_side;
     uint32_t *minmax;     // [0] = min key, [1] = max key of off-diagonal entries
+    // median preference: the first digit pass of the exact select (13-bit
+    // digits of the upper entries' keys; both ranks share the empty prefix)
+    // counted here, into hist[b] and hist[SEL_BINS + b]; null: no counting
+    unsigned long long *hist;
 };
 
 // One 128 x 128 tile per workgroup.  X rows are staged through LDS one K
 // chunk at a time, the next chunk's global loads in flight during the
 // current chunk's MFMAs; the epilogue writes S straight from the
-// accumulators (no LDS tile, so four workgroups fit a CU): lane l of
+// accumulators (no LDS tile): lane l of
 // block (x, y) holds column c = l mod 32 and rows 8g + 4(l / 32) + q
 // (g, q = 0..3), written directly (one float per row, 128-byte row
 // segments per half wavefront) and mirrored (the four rows q are
-// consecutive columns of S's row c: one float4).
+// consecutive columns of S's row c: one float4).  With the median
+// preference (COUNT) the epilogue also counts the first 13-bit digit of
+// every upper entry's key in an LDS histogram whose nonzero bins the tile
+// adds to the global one: the select's first pass over S is not needed.
 constexpr int LDA = BM + 1;   // padded LDS rows: conflict-free transposed stores
 
 // Gram block <x_i, x_k> of rows row0.. and columns col0.. (BM each) into the
@@ -125,6 +133,7 @@ __device__ __forceinline__ void gram_tile(const float *X, int64_t n, int64_t d, 
     }
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
     // Decode the upper-triangle tile (bi <= bj) from the linear block index.
     const int64_t T = a.tiles_per_side;
@@ -138,8 +147,11 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
 
     __shared__ float As[KB * LDA], Bs[KB * LDA];    // 16.5 KB of staging
     __shared__ float nr[BM], nc[BM];                // squared norms of the tile's rows and columns
+    __shared__ uint32_t hsh[COUNT ? SEL_BINS : 1];  // first-digit counts of the tile's upper entries
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    if constexpr (COUNT)
+        for (int b = tid; b < SEL_BINS; b += NT) hsh[b] = 0u;   // published by gram_tile's barriers (d >= 1)
     for (int e = tid; e < BM; e += NT) {
         nr[e] = row0 + e < a.n ? a.nrm[row0 + e] : 0.0f;
         nc[e] = col0 + e < a.n ? a.nrm[col0 + e] : 0.0f;
@@ -173,6 +185,7 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
                             const uint32_t key = fkey(v[q]);
                             kmin = min(kmin, key);
                             kmax = max(kmax, key);
+                            if constexpr (COUNT) atomicAdd(&hsh[key >> 19], 1u);
                         }
                     }
                     float *dst = a.S + k * a.ld + ib;
@@ -197,6 +210,7 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
                             const uint32_t key = fkey(v[q]);
                             kmin = min(kmin, key);
                             kmax = max(kmax, key);
+                            if constexpr (COUNT) atomicAdd(&hsh[key >> 19], 1u);
                         }
                     }
                 }
@@ -224,6 +238,17 @@ __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
         if (kmin < __atomic_load_n(&a.minmax[0], __ATOMIC_RELAXED)) atomicMin(&a.minmax[0], kmin);
         if (kmax > __atomic_load_n(&a.minmax[1], __ATOMIC_RELAXED)) atomicMax(&a.minmax[1], kmax);
     }
+    // the tile's counts (integers: the sums do not depend on the order);
+    // the barrier above ordered every LDS count before these reads
+    if constexpr (COUNT) {
+        for (int b = tid; b < SEL_BINS; b += NT) {
+            const uint32_t c = hsh[b];
+            if (c) {
+                atomicAdd(&a.hist[b], (unsigned long long)c);
+                atomicAdd(&a.hist[SEL_BINS + b], (unsigned long long)c);
+            }
+        }
+    }
 }
 
 // ---- exact order statistics of the upper triangle -------------------------
@@ -237,7 +262,6 @@ struct SelState {
 // Digits of the 32-bit key: 13 bits (the first pass, when both ranks share
 // the empty prefix and one histogram counts for both: more bins spread the
 // counter contention of keys that share their exponent), then 10 and 9.
-constexpr int SEL_BINS = 8192;   // bins per rank in the global histogram
 __device__ __forceinline__ void sel_digit(int pass, int &shift, int &bits, uint32_t &hmask) {
     shift = pass == 0 ? 19 : (pass == 1 ? 9 : 0);
     bits = pass == 0 ? 13 : (pass == 1 ? 10 : 9);
@@ -259,38 +283,50 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
 // Histogram of the keys of upper-triangle entries whose high bits match the
 // current prefix of each rank.  shift/bits select the digit of this pass.
 // f(k, v) for the entries v = row[k], k = i+1 .. n-1, of row i: the unaligned
-// head one by one, then 16-byte loads (rows start 16-byte aligned: ld is a
-// multiple of 4), four in flight per thread.
-template <class F>
+// head one by one, then 16-byte pieces (rows start 16-byte aligned: ld is a
+// multiple of 4), U per thread in flight in every step, the row's ragged end
+// included (its last piece read element by element, nothing at or beyond n).
+template <int U, class F>
 __device__ __forceinline__ void upper_row(const float *row, int64_t i, int64_t n, F &&f) {
     const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
     const int64_t kh = k4 < n ? k4 : n;
     if (i + 1 + threadIdx.x < kh) f(i + 1 + threadIdx.x, row[i + 1 + threadIdx.x]);
     const int64_t st = 4 * (int64_t)blockDim.x;
-    int64_t k = k4 + 4 * (int64_t)threadIdx.x;
-    for (; k + 3 * st + 3 < n; k += 4 * st) {
-        float4 v[4];
+    for (int64_t kb = k4 + 4 * (int64_t)threadIdx.x; kb < n; kb += U * st) {
+        float4 v[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4 *>(row + k + u * st);
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + u * st;
+            if (k + 3 < n) {
+                v[u] = *reinterpret_cast<const float4 *>(row + k);
+            } else {
+                v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (k < n) v[u].x = row[k];
+                if (k + 1 < n) v[u].y = row[k + 1];
+                if (k + 2 < n) v[u].z = row[k + 2];
+            }
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            f(k + u * st, v[u].x);
-            f(k + u * st + 1, v[u].y);
-            f(k + u * st + 2, v[u].z);
-            f(k + u * st + 3, v[u].w);
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + u * st;
+            if (k < n) f(k, v[u].x);
+            if (k + 1 < n) f(k + 1, v[u].y);
+            if (k + 2 < n) f(k + 2, v[u].z);
+            if (k + 3 < n) f(k + 3, v[u].w);
         }
     }
-    for (; k < n; k += st) {
-        if (k + 3 < n) {
-            const float4 v = *reinterpret_cast<const float4 *>(row + k);
-            f(k, v.x);
-            f(k + 1, v.y);
-            f(k + 2, v.z);
-            f(k + 3, v.w);
-        } else {
-            for (int64_t q = k; q < n; ++q) f(q, row[q]);
-        }
-    }
+}
+
+// Workgroups of a row-walking pass: as many as are resident on the chip
+// at once (workgroup b walks rows b, b + grid, ...: a second, partial round
+// would leave most CUs idle while it finishes), at most one per row.
+int walk_grid(const void *kern, size_t lds, int64_t rows) {
+    int dev = 0, cus = 0, occ = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t g = (int64_t)occ * cus;
+    return (int)(rows < g ? rows : g);
 }
 
 // Rows [r0, r1) of S (row i at S + i * ld).
@@ -320,7 +356,7 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
         if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
     };
     const int64_t re = r1 < n - 1 ? r1 : n - 1;
-    for (int64_t i = r0 + blockIdx.x; i < re; i += gridDim.x) upper_row(S + i * ld, i, n, count);
+    for (int64_t i = r0 + blockIdx.x; i < re; i += gridDim.x) upper_row<8>(S + i * ld, i, n, count);
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
         const uint32_t c0 = h0[b], c1 = same ? c0 : h1[b];
@@ -459,7 +495,7 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
             row[i] = noise ? (float)(base + scale * noise_u(a.seed, a.n, i, i)) : (float)base;
         }
         if (!noise) continue;
-        upper_row(row, i, a.n, [&](int64_t k, float v) {
+        upper_row<2>(row, i, a.n, [&](int64_t k, float v) {
             if (scale <= fabs((double)v) * 0x1p-27) return;
             row[k] = add_noise(v, scale, a.seed, a.n, i, k);
             a.S[k * a.ld + i] = add_noise(v, scale, a.seed, a.n, k, i);
@@ -490,7 +526,7 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
     const double scale = a.noise_rel * ((double)keyf(a.minmax[1]) - (double)keyf(a.minmax[0]));
     for (int64_t i = blockIdx.x; i < a.n - 1; i += gridDim.x) {
         float *row = a.S + i * a.ld;
-        upper_row(row, i, a.n, [&](int64_t k, float v) {
+        upper_row<2>(row, i, a.n, [&](int64_t k, float v) {
             const uint32_t key = fkey(v);
             const uint32_t dig = (key >> shift) & (nb - 1u);
             if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
@@ -689,20 +725,26 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     HIP_TRY(hipGetLastError(), "select init");
     k_sqnorm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(X, n, d, ldx, nrm);
     HIP_TRY(hipGetLastError(), "sqnorm");
-    SimArgs sa{X, n, d, ldx, nrm, S, ld, (n + BM - 1) / BM, mm};
+    // median preference: the GEMM counts the select's first digit
+    SimArgs sa{X, n, d, ldx, nrm, S, ld, (n + BM - 1) / BM, mm, pref_mode == APX_PREF_MEDIAN ? hist : nullptr};
     const int64_t ntiles = sa.tiles_per_side * (sa.tiles_per_side + 1) / 2;
-    k_sim_gemm<<<(unsigned)ntiles, NT, 0, s>>>(sa);
+    if (sa.hist) k_sim_gemm<true><<<(unsigned)ntiles, NT, 0, s>>>(sa);
+    else k_sim_gemm<false><<<(unsigned)ntiles, NT, 0, s>>>(sa);
     HIP_TRY(hipGetLastError(), "similarity gemm");
     PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1]};
     if (pref_mode == APX_PREF_MEDIAN) {
-        // three digit passes over the upper triangle; with noise the last
-        // one also adds the noise to every off-diagonal entry
-        const int g = (int)(n - 1 < 2048 ? n - 1 : 2048);
+        // three digits: the first counted by the GEMM, two passes over the
+        // upper triangle; with noise the last one also adds the noise to
+        // every off-diagonal entry
         for (int pass = 0; pass < 3; ++pass) {
             const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
-            if (pass == 2 && noise_rel > 0.0) {
+            if (pass == 0) {
+                // first digit: counted by the GEMM
+            } else if (pass == 2 && noise_rel > 0.0) {
+                const int g = walk_grid((const void *)k_sel_hist_noise, lds, n - 1);
                 k_sel_hist_noise<<<g, 256, lds, s>>>(pa, hist);
             } else {
+                const int g = walk_grid((const void *)k_sel_hist, lds, n - 1);
                 k_sel_hist<<<g, 256, lds, s>>>(S, n, ld, sel, pass, hist, 0, n);
             }
             HIP_TRY(hipGetLastError(), "select histogram");
@@ -808,7 +850,7 @@ hipError_t mf_sim_setup(const MfSim &m, float *panel, int64_t ld, int64_t prows,
             if ((e = launch_panel(panel_args(m, q, panel, ld, p0, p1, 0, nullptr), s)) != hipSuccess) return e;
             if (m.pref_mode == APX_PREF_MEDIAN) {
                 const size_t lds = sizeof(uint32_t) * (pass == 0 ? 8192 : 2 * (pass == 1 ? 1024 : 512));
-                const int g = (int)(p1 - p0 < 2048 ? p1 - p0 : 2048);
+                const int g = walk_grid((const void *)k_sel_hist, lds, p1 - p0);
                 k_sel_hist<<<g, 256, lds, s>>>(panel - p0 * ld, n, ld, q.sel, pass, q.hist, p0, p1);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             }
