@@ -93,8 +93,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1933882667, "write": 46025256, "path": "implicit_RA",
-                    "sha256": "fd71b93f361df3d9f7b3f99663a699a878c196f1f06e85c0805f05045ed0ab1c"}
+ROW_PASS_TRAFFIC = {"read": 1709288527, "write": 45959401, "path": "implicit_RA",
+                    "sha256": "7a933e4607c333f6be9d275182da9d0992bdf444003076a0953576c0f905c09e"}
 PAP_K = 8
 
 
