@@ -1922,6 +1922,12 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         // ---- scan of the ordinary elements
         float v1 = kNegInf, v2 = kNegInf;
         float smax = kNegInf;   // largest s of the thread's columns that phase 2 leaves to it
+        // the same per chunk (rows of up to six chunks per thread; longer
+        // ones have no registers to spare and reread every chunk)
+        constexpr bool CHM = J <= 6;
+        float cmx[CHM ? J : 1];
+#pragma unroll
+        for (int j = 0; j < (CHM ? J : 1); ++j) cmx[j] = kNegInf;
         int l1 = -1;
         uint32_t fch = 0;       // chunks holding a first positive responsibility
         // longer rows: acol_t chunks stream from L2, one chunk ahead of use
@@ -1955,6 +1961,7 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
             // (the diagonal's own chunk is finished after the scan)
             const float dth = c + 3 < ii ? D : Dn;
             bool fj = false;   // the chunk holds a first positive
+            float cm = kNegInf;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float s = f4get(sv, e);
@@ -1980,9 +1987,23 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                 // largest s of the ordinary columns (positive r included):
                 // r = al s - beta is monotone in s, so it tells whether the
                 // thread holds a first positive, and bounds phase 2's values
-                smax = max3f(smax, lst ? kNegInf : s);
+                cm = max3f(cm, lst ? kNegInf : s);
             }
+            if constexpr (CHM) cmx[j] = cm;
+            smax = max3f(smax, cm);
             if constexpr (LEAN) fch = fj ? (fch | (1u << j)) : fch;
+        }
+        // Chunks that can hold a positive R_{t+1} in phase 2: beta1 =
+        // lam beta + (1-lam) V1 with V1 (the row's largest a + s) >= this
+        // thread's v1, and fl(al1 s - b) rises with s and falls with b, so a
+        // chunk whose largest ordinary s gives fl(al1 s - b_lo) <= 0, b_lo =
+        // lam beta + (1-lam) v1, adds nothing there.
+        uint32_t hch = ~0u;
+        if constexpr (CHM) {
+            const float blo = lam * beta + oml * v1;
+            hch = 0u;
+#pragma unroll
+            for (int j = 0; j < J; ++j) hch |= (al1 * cmx[j] - blo > 0.0f) ? (1u << j) : 0u;
         }
         // a first positive somewhere in the thread's ordinary columns: every
         // chunk is searched (rare once the lists settle)
@@ -2250,14 +2271,15 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
         }
         // ordinary elements: a positive value needs al1 s - beta1 > 0,
         // which is monotone in s, so only threads whose largest ordinary
-        // s passes reread their chunks (from L2)
+        // s passes reread their chunks (from L2), and only the chunks that
+        // the scan's bound leaves open
         const bool hot = al1 * smax - beta1 > 0.0f;
         if (__any(hot)) {
             if (hot) {
                 const float *srow = p.S + i * ld;
 #pragma unroll 1
                 for (int j = 0; j < J; ++j) {
-                    if (!(j < J - 1 || last_in)) continue;
+                    if (!(j < J - 1 || last_in) || !((hch >> j) & 1u)) continue;
                     const int c = c0 + j * T * 4;
                     const float4 sv = ld4(srow + c);
                     const uint32_t mb = mb8[j * T + tid];
