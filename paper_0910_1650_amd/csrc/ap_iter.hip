@@ -2074,12 +2074,32 @@ __global__ __launch_bounds__(T) void k_row_ia(ImpArgs p) {
                     if (jj == j) sv = s4[jj];
                 const uint32_t mb = mb8[j * T + tid];
                 const uint32_t ex = (mb | (mb >> 4)) & 0xFu;
-                for (int e = 0; e < 4; ++e) {
-                    const int k = c0 + j * T * 4 + e;
-                    if (k >= n) break;
-                    const float s = f4get(sv, e);
-                    const float r = al * s - beta;
-                    if (!((ex >> e) & 1u) && r > 0.0f) fresh(k, s, r);
+                const int cj = c0 + j * T * 4;
+                if constexpr (CHM) {
+                    // the chunk's first positives as a bit mask, then one
+                    // append per entry (a wavefront runs the append as often
+                    // as its busiest lane needs it, not once per element
+                    // position)
+                    uint32_t fm = 0u;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float r = al * f4get(sv, e) - beta;
+                        fm |= (cj + e < n && !((ex >> e) & 1u) && r > 0.0f) ? (1u << e) : 0u;
+                    }
+                    while (fm) {
+                        const int e = __builtin_ctz(fm);
+                        fm &= fm - 1;
+                        const float s = f4get(sv, e);
+                        fresh(cj + e, s, al * s - beta);
+                    }
+                } else {
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = cj + e;
+                        if (k >= n) break;
+                        const float s = f4get(sv, e);
+                        const float r = al * s - beta;
+                        if (!((ex >> e) & 1u) && r > 0.0f) fresh(k, s, r);
+                    }
                 }
             }
         }
