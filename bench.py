@@ -93,8 +93,8 @@ CALIB_ELEMS = 400_000_000       # 1.6 GB FP32 copy: the counter calibration kern
 # row-pass source with this SHA-256; otherwise the benchmark reports traffic
 # as null.
 ROW_PASS_SRC = "paper_0910_1650_amd/csrc/ap_iter.hip"
-ROW_PASS_TRAFFIC = {"read": 1709288527, "write": 45959401, "path": "implicit_RA",
-                    "sha256": "7a933e4607c333f6be9d275182da9d0992bdf444003076a0953576c0f905c09e"}
+ROW_PASS_TRAFFIC = {"read": 1688642971, "write": 45899219, "path": "implicit_RA",
+                    "sha256": "26823068bb96016525d0e0a14b2d86c187fcaf236554ec60c5d87ea3c66d543e"}
 PAP_K = 8
 
 
