@@ -47,6 +47,24 @@ def test_median_is_exact(n):
     assert np.all(np.diag(S) == np.float32(p))
 
 
+@pytest.mark.parametrize("n", [2050, 9001])
+def test_median_is_exact_with_noise_on_long_rows(n):
+    # The first digit is counted by the GEMM, the second by a row walk with
+    # eight 16-byte loads per thread in flight (8192 entries a step: n = 9001
+    # takes a full step and a ragged one), the third by the noise pass (two
+    # loads, 2048 entries a step); the median is of the entries before the
+    # noise, whichever entries the noise then moves.
+    print(f"median with noise n={n}", flush=True)
+    pts = synth.gaussian_mixture(n=n, d=16, k=12, seed=n)
+    S0, p0 = run(pts.X, pref="median")
+    off = ~np.eye(n, dtype=bool)
+    want = np.median(S0[off])
+    S1, p1 = run(pts.X, pref="median", seed=n, noise=1e-6)
+    assert p0 == want and p1 == want
+    moved = (S1 != S0) & off
+    assert moved.any()                                   # the noise changed entries
+
+
 def test_median_with_many_ties():
     # integer grid: many exactly equal distances
     g = np.array([[i % 7, i // 7] for i in range(70)], dtype=np.float32)
