@@ -286,6 +286,7 @@ __global__ void k_sel_init(SelState *st, uint32_t *minmax, unsigned long long lo
 // head one by one, then 16-byte pieces (rows start 16-byte aligned: ld is a
 // multiple of 4), U per thread in flight in every step, the row's ragged end
 // included (its last piece read element by element, nothing at or beyond n).
+typedef float sv4 __attribute__((ext_vector_type(4)));
 template <int U, class F>
 __device__ __forceinline__ void upper_row(const float *row, int64_t i, int64_t n, F &&f) {
     const int64_t k4 = (i + 4) & ~int64_t(3);          // first multiple of 4 above i
@@ -298,7 +299,9 @@ __device__ __forceinline__ void upper_row(const float *row, int64_t i, int64_t n
         for (int u = 0; u < U; ++u) {
             const int64_t k = kb + u * st;
             if (k + 3 < n) {
-                v[u] = *reinterpret_cast<const float4 *>(row + k);
+                // read once per pass: nontemporal
+                const sv4 w = __builtin_nontemporal_load(reinterpret_cast<const sv4 *>(row + k));
+                v[u] = make_float4(w.x, w.y, w.z, w.w);
             } else {
                 v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (k < n) v[u].x = row[k];
@@ -454,6 +457,16 @@ __device__ __forceinline__ float add_noise(float v, double scale, uint64_t seed,
     return (float)(dv + scale * noise_u(seed, n, i, k));
 }
 
+// The noise of an upper entry v = s(i,k) that the noise changes, written at
+// (i,k) and, with its own draw, at (k,i).  Out of line: the row walks call
+// it for few entries, and inlined into each of their unrolled element slots
+// its 64-bit arithmetic would take the registers of their loads in flight.
+__device__ __noinline__ void put_noise(float *S, int64_t ld, float v, double scale, uint64_t seed, int64_t n,
+                                       int64_t i, int64_t k) {
+    S[i * ld + k] = add_noise(v, scale, seed, n, i, k);
+    S[k * ld + i] = add_noise(v, scale, seed, n, k, i);
+}
+
 // Range of S with the preferences on the diagonal (FP64).
 __global__ void k_pref_range(PrefArgs a, double *range_out) {
     __shared__ float lo[256], hi[256];
@@ -495,10 +508,9 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
             row[i] = noise ? (float)(base + scale * noise_u(a.seed, a.n, i, i)) : (float)base;
         }
         if (!noise) continue;
-        upper_row<2>(row, i, a.n, [&](int64_t k, float v) {
+        upper_row<8>(row, i, a.n, [&](int64_t k, float v) {
             if (scale <= fabs((double)v) * 0x1p-27) return;
-            row[k] = add_noise(v, scale, a.seed, a.n, i, k);
-            a.S[k * a.ld + i] = add_noise(v, scale, a.seed, a.n, k, i);
+            put_noise(a.S, a.ld, v, scale, a.seed, a.n, i, k);
         });
     }
 }
@@ -526,14 +538,13 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
     const double scale = a.noise_rel * ((double)keyf(a.minmax[1]) - (double)keyf(a.minmax[0]));
     for (int64_t i = blockIdx.x; i < a.n - 1; i += gridDim.x) {
         float *row = a.S + i * a.ld;
-        upper_row<2>(row, i, a.n, [&](int64_t k, float v) {
+        upper_row<8>(row, i, a.n, [&](int64_t k, float v) {
             const uint32_t key = fkey(v);
             const uint32_t dig = (key >> shift) & (nb - 1u);
             if ((key & hmask) == p0) atomicAdd(&h0[dig], 1u);
             if (!same && (key & hmask) == p1) atomicAdd(&h1[dig], 1u);
             if (scale <= fabs((double)v) * 0x1p-27) return;
-            row[k] = add_noise(v, scale, a.seed, a.n, i, k);
-            a.S[k * a.ld + i] = add_noise(v, scale, a.seed, a.n, k, i);
+            put_noise(a.S, a.ld, v, scale, a.seed, a.n, i, k);
         });
     }
     __syncthreads();
