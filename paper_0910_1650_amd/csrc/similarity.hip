@@ -58,6 +58,7 @@ struct SimArgs {
     // digits of the upper entries' keys; both ranks share the empty prefix)
     // counted here, into hist[b] and hist[SEL_BINS + b]; null: no counting
     unsigned long long *hist;
+    const int32_t *bad;   // nonzero: the input failed the finite check, write nothing
 };
 
 // One 128 x 128 tile per workgroup.  X rows are staged through LDS one K
@@ -135,6 +136,7 @@ __device__ __forceinline__ void gram_tile(const float *X, int64_t n, int64_t d, 
 
 template <bool COUNT>
 __global__ __launch_bounds__(NT) void k_sim_gemm(SimArgs a) {
+    if (*a.bad) return;
     // Decode the upper-triangle tile (bi <= bj) from the linear block index.
     const int64_t T = a.tiles_per_side;
     int64_t t = blockIdx.x, bi = 0;
@@ -368,40 +370,63 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float *S, int64_t n, int
     }
 }
 
+// Inclusive prefix sum over the 256 threads: wavefront shuffles, then the
+// wavefront totals through LDS (ws: 4 entries).
+__device__ __forceinline__ unsigned long long block_scan256(unsigned long long x, unsigned long long *ws) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    unsigned long long add = 0ull;
+    for (int k = 0; k < w; ++k) add += ws[k];
+    __syncthreads();
+    return x + add;
+}
+
 // Pick the digit holding each rank; extend the prefixes; clear the histogram.
 // 256 threads: each sums nb/256 consecutive digits, a block scan of the
-// sums finds the segment holding the rank, its owner walks its digits.
+// sums finds the segment holding the rank, its owner walks its digits
+// (held in registers since the sum).
 __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int pass, unsigned long long *hist) {
     int shift, bits;
     uint32_t hmask;
     sel_digit(pass, shift, bits, hmask);
     const uint32_t nb = 1u << bits;
     const uint32_t per = nb / 256;               // digits per thread (32, 4 or 2)
-    __shared__ unsigned long long sc[256];
+    constexpr int MAXPER = SEL_BINS / 256;
+    __shared__ unsigned long long ws[4];
     const int t = threadIdx.x;
     for (int r = 0; r < 2; ++r) {
         const unsigned long long *hr = hist + r * SEL_BINS;
+        // the thread's segment of digits, all loads in flight at once
+        unsigned long long v[MAXPER];
+#pragma unroll
+        for (int q = 0; q < MAXPER; ++q) v[q] = (uint32_t)q < per ? hr[t * per + q] : 0ull;
         unsigned long long own = 0ull;
-        for (uint32_t q = 0; q < per; ++q) own += hr[t * per + q];
-        sc[t] = own;
-        __syncthreads();
-        // inclusive scan (Hillis-Steele)
-        for (int off = 1; off < 256; off <<= 1) {
-            const unsigned long long v = t >= off ? sc[t - off] : 0ull;
-            __syncthreads();
-            sc[t] += v;
-            __syncthreads();
-        }
+#pragma unroll
+        for (int q = 0; q < MAXPER; ++q) own += v[q];
+        // read before the scan's barriers: the owner rewrites it below
         const unsigned long long rank = st->rank[r];
-        const unsigned long long before = sc[t] - own;    // digits below this thread's segment
-        __syncthreads();
-        if (rank >= before && rank < sc[t]) {
+        const unsigned long long incl = block_scan256(own, ws);
+        const unsigned long long before = incl - own;   // digits below this thread's segment
+        if (rank >= before && rank < incl) {
             unsigned long long cum = before;
             uint32_t b = t * per;
-            for (;; ++b) {
-                const unsigned long long c = hr[b];
-                if (rank < cum + c) break;
-                cum += c;
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q < MAXPER; ++q) {
+                if (!found && (uint32_t)q < per) {
+                    if (rank < cum + v[q]) {
+                        found = true;
+                        b = t * per + q;
+                    } else {
+                        cum += v[q];
+                    }
+                }
             }
             st->rank[r] = rank - cum;
             st->prefix[r] |= (b << shift);
@@ -422,6 +447,7 @@ struct PrefArgs {
     uint64_t seed;
     double noise_rel;
     double *pref_dev;         // out: the scalar preference (median/scalar)
+    const int32_t *bad = nullptr;   // nonzero: the input failed the finite check, write nothing
 };
 
 __device__ __forceinline__ double pref_of(const PrefArgs &a, int64_t i, double pm) {
@@ -498,6 +524,7 @@ __global__ void k_pref_range(PrefArgs a, double *range_out) {
 // the upper triangle alone is read: an entry the noise changes (add_noise)
 // is written at (i,k) and, with its own draw, at (k,i); the others keep v.
 __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *range) {
+    if (a.bad != nullptr && *a.bad) return;
     const double pm = median_of(a);
     const double scale = a.noise_rel * (*range);
     const bool noise = a.noise_rel > 0.0;
@@ -523,6 +550,7 @@ __global__ __launch_bounds__(256) void k_pref_noise(PrefArgs a, const double *ra
 // k_pref_diag once the median is known.  The noise scale needs only the
 // off-diagonal range (the median lies inside it).
 __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned long long *hist) {
+    if (a.bad != nullptr && *a.bad) return;
     extern __shared__ uint32_t hsh[];
     constexpr int pass = 2;
     int shift, bits;
@@ -557,6 +585,7 @@ __global__ __launch_bounds__(256) void k_sel_hist_noise(PrefArgs a, unsigned lon
 
 // The diagonal after the fused pass: s(i,i) = p (+ its noise).
 __global__ void k_pref_diag(PrefArgs a, const double *range) {
+    if (a.bad != nullptr && *a.bad) return;
     const double pm = median_of(a);
     const double scale = a.noise_rel * (*range);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -719,9 +748,9 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     HIP_TRY(launch_fill_u8(reinterpret_cast<uint8_t *>(ctx->dflag), sizeof(int32_t), 0, s), "finite check");
     HIP_TRY(launch_check_finite(X, n, d, ldx, ctx->dflag, s), "finite check");
     if (pref_mode == APX_PREF_VECTOR) HIP_TRY(launch_check_finite(pref_vec, 1, n, n, ctx->dflag, s), "finite check");
-    HIP_TRY(hipMemcpyAsync(hflag, ctx->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "finite check");
-    HIP_TRY(hipStreamSynchronize(s), "sync");
-    if (*hflag) return set_err(ctx, APX_EINVAL, "X or pref_vec holds a NaN or infinite value");
+    // (no wait here: every kernel that writes S reads the flag first and
+    // returns when it is set; the host reads it at the end)
+    const int32_t *bad = static_cast<const int32_t *>(ctx->dflag);
     char *b = static_cast<char *>(ctx->ws) + ctx->ws_base;
     float *nrm = reinterpret_cast<float *>(b + o_n);
     uint32_t *mm = reinterpret_cast<uint32_t *>(b + o_mm);
@@ -737,12 +766,12 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     k_sqnorm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(X, n, d, ldx, nrm);
     HIP_TRY(hipGetLastError(), "sqnorm");
     // median preference: the GEMM counts the select's first digit
-    SimArgs sa{X, n, d, ldx, nrm, S, ld, (n + BM - 1) / BM, mm, pref_mode == APX_PREF_MEDIAN ? hist : nullptr};
+    SimArgs sa{X, n, d, ldx, nrm, S, ld, (n + BM - 1) / BM, mm, pref_mode == APX_PREF_MEDIAN ? hist : nullptr, bad};
     const int64_t ntiles = sa.tiles_per_side * (sa.tiles_per_side + 1) / 2;
     if (sa.hist) k_sim_gemm<true><<<(unsigned)ntiles, NT, 0, s>>>(sa);
     else k_sim_gemm<false><<<(unsigned)ntiles, NT, 0, s>>>(sa);
     HIP_TRY(hipGetLastError(), "similarity gemm");
-    PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1]};
+    PrefArgs pa{S, n, ld, pref_mode, pref_vec, pref_scalar, sel, mm, noise_seed, noise_rel, &dvals[1], bad};
     if (pref_mode == APX_PREF_MEDIAN) {
         // three digits: the first counted by the GEMM, two passes over the
         // upper triangle; with noise the last one also adds the noise to
@@ -779,7 +808,9 @@ extern "C" apx_status ap_similarity(apx_ctx *ctx, const float *X, int64_t n, int
     uint32_t *hk = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->pinned) + 1088);
     HIP_TRY(hipMemcpyAsync(h, &dvals[1], sizeof(double), hipMemcpyDeviceToHost, s), "pref copy");
     HIP_TRY(hipMemcpyAsync(hk, mm, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "bounds copy");
+    HIP_TRY(hipMemcpyAsync(hflag, ctx->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "finite check");
     HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (*hflag) return set_err(ctx, APX_EINVAL, "X or pref_vec holds a NaN or infinite value");
     const uint32_t key_pinf = 0xff800000u, key_ninf = 0x007fffffu;   // fkey(+inf), fkey(-inf)
     if (hk[1] >= key_pinf || hk[0] <= key_ninf)
         return set_err(ctx, APX_EINVAL, "similarities overflow FP32 (S holds non-finite values)");
