@@ -166,6 +166,25 @@ def test_long_rows_global_partials():
     assert float((out["0"][1] - Ae).abs().max()) <= TOL * rng
 
 
+def test_six_chunks_per_thread_against_explicit():
+    # n = 22000: six float4 chunks per thread, the longest rows on which the
+    # implicit-A pass bounds each hot thread's rereads per chunk and appends
+    # a chunk's first positives one at a time; 25 fixed iterations through
+    # the passes in which most entries turn positive, against the explicit
+    # messages (checked against the oracle elsewhere)
+    n = 22000
+    say(f"implicit A six chunks n={n}")
+    pts = synth.gaussian_mixture(n=n, d=64, k=50, seed=2701)
+    X = torch.from_numpy(pts.X).cuda()
+    Sd, _ = apx.ap_similarity(X, pref="median", noise_seed=2701, noise_rel=1e-12)
+    R, A, idx, res, info = solve(Sd, 16, 1024, max_iter=25, conv_iter=0)
+    assert info[2] == 25                                   # implicit A throughout
+    Re, Ae, ie, re, _ = solve(Sd, 0, 0, max_iter=25, conv_iter=0)
+    rng = float(Sd.max() - Sd.min())
+    assert float((R - Re).abs().max()) <= TOL * rng
+    assert float((A - Ae).abs().max()) <= TOL * rng
+
+
 def tie_matrix(n, dims, hi, seed, pref_q):
     """Duplicated integer points: S = -||x_i - x_k||^2 is integer and every
     column has a twin, so a+s and a+r are tied in many rows."""
