@@ -272,7 +272,20 @@ __global__ void k_features(const RowStats *st, int32_t n, const float *sigma, fl
 // Network
 // ---------------------------------------------------------------------------
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+
+// gfx950's 32x32x16 bf16 matrix op (FP32 accumulate): lane l holds row (or
+// column) l mod 32 and k = 8 (l / 32) .. + 7 of its operand.  The two halves
+// of an operand come from 8-byte aligned LDS rows (their padding keeps the
+// 8-byte loads free of bank conflicts).
+__device__ __forceinline__ v16f mfma16(v4s a0, v4s a1, v4s b0, v4s b1, v16f c) {
+    const v8s a = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    const v8s b = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
 
 __device__ __forceinline__ v16f zero16() {
     v16f z;
@@ -364,45 +377,45 @@ __global__ __launch_bounds__(FW_T) void k_mlp_fwd(FwdArgs a) {
     __syncthreads();
 
     const int64_t p0 = (int64_t)blockIdx.x * FW_P + wave * 32;
-    const int li = lane & 31, lk = (lane >> 5) * 4;
+    const int li = lane & 31, lk = (lane >> 5) * 8;
     uint16_t *hw = sh.h + (wave * 32) * LW2;
 
-    // Layer 1: A operand = bf16 features of point p0 + li, k = 8 ks + lk .. + 3.
+    // Layer 1 (K = 16, one matrix op per 32 units): A operand = bf16
+    // features of point p0 + li, k = lk .. lk + 7.
     v4s xa[2];
     {
         const int64_t p = p0 + li;
         const int64_t src = p < a.count ? (a.rows ? a.rows[p] : p) : -1;
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
+        for (int h = 0; h < 2; ++h) {
             float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (src >= 0) f = *reinterpret_cast<const float4 *>(a.F + src * NF + 8 * ks + lk);
-            xa[ks] = v4s{(short)bf16_bits(f.x), (short)bf16_bits(f.y), (short)bf16_bits(f.z),
-                         (short)bf16_bits(f.w)};
+            if (src >= 0) f = *reinterpret_cast<const float4 *>(a.F + src * NF + lk + 4 * h);
+            xa[h] = v4s{(short)bf16_bits(f.x), (short)bf16_bits(f.y), (short)bf16_bits(f.z),
+                        (short)bf16_bits(f.w)};
         }
     }
     v16f acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        acc[nt] = zero16();
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const v4s b = *reinterpret_cast<const v4s *>(sh.w1t + (32 * nt + li) * LW1 + 8 * ks + lk);
-            acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(xa[ks], b, acc[nt], 0, 0, 0);
-        }
+        const uint16_t *w = sh.w1t + (32 * nt + li) * LW1 + lk;
+        acc[nt] = mfma16(xa[0], xa[1], *reinterpret_cast<const v4s *>(w), *reinterpret_cast<const v4s *>(w + 4),
+                         zero16());
     }
     layer_epilogue<STASH>(acc, sh.b1, hw, a.Z1, a.H1, p0, a.count, lane);
     __syncthreads();
 
-    // Layer 2: 32 points x 128 units, K = 128 in 16 steps of 8.
+    // Layer 2: 32 points x 128 units, K = 128 in 8 steps of 16.
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = zero16();
 #pragma unroll 4
-    for (int ks = 0; ks < 16; ++ks) {
-        const v4s av = *reinterpret_cast<const v4s *>(hw + li * LW2 + 8 * ks + lk);
+    for (int ks = 0; ks < 8; ++ks) {
+        const uint16_t *hr = hw + li * LW2 + 16 * ks + lk;
+        const v4s a0 = *reinterpret_cast<const v4s *>(hr), a1 = *reinterpret_cast<const v4s *>(hr + 4);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const v4s b = *reinterpret_cast<const v4s *>(sh.w2t + (32 * nt + li) * LW2 + 8 * ks + lk);
-            acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, b, acc[nt], 0, 0, 0);
+            const uint16_t *w = sh.w2t + (32 * nt + li) * LW2 + 16 * ks + lk;
+            acc[nt] = mfma16(a0, a1, *reinterpret_cast<const v4s *>(w), *reinterpret_cast<const v4s *>(w + 4),
+                             acc[nt]);
         }
     }
     __syncthreads();
